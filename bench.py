@@ -1,0 +1,344 @@
+"""Benchmark of the pre-packed TSMM hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-extras]
+
+Workload (the headline): binary64 tall-A x small-B,
+C = alpha*A*B + beta*C with m = 2^23 rows, k = n in {8, 32, 128} and
+beta in {0, 1} -- six sub-cases.  B is packed once per k and reused by every
+call; each call reads a different A buffer (a rotation of two per k, each
+larger than the last-level cache), so no call sees its A in cache.  One
+step = one execute of each of the six sub-cases.  The value is the
+algorithmic HBM bytes of a step (A once, C once, plus C once more when
+beta = 1; packing excluded, as the paper excludes it) over the wall time of
+the step: GB/s, whole job.
+
+Extras (same run, reported beside the headline): the op T split-k shape
+(C(64x64) = A^T B, A and B 2^22 x 64), the binary32 precision comparison
+(m = 2^24, k = n = 256: binary32 products, split-bf16 x3 / x6, binary64 on
+binary64 copies) and the batched persistent launch (512 uneven instances,
+replayed from a HIP graph).
+
+The `roofline` object is for the kernel that takes the most time in a step,
+timed with HIP events on the stream it runs on; `cpu_baseline` times the
+FP64 CPU oracle on a bounded row sample of the same workload on this host's
+cores and reports the sampled error of the GPU results against it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}
+M_ROWS = 1 << 23
+KS = (8, 32, 128)
+BETAS = (0.0, 1.0)
+
+
+def opn_bytes(m, n, k, beta, sa=8, sc=8):
+    return m * (k * sa + n * sc * (2 if beta != 0.0 else 1))
+
+
+def parse():
+    ap = argparse.ArgumentParser(description="pre-packed TSMM benchmark")
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default=None, help="profile helper: run only this headline sub-case, e.g. k128b1")
+    return ap.parse_args()
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream every launch of
+    the binding goes to)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.ev = []
+
+    def start(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def stop(self, key, e0):
+        e1 = self.torch.cuda.Event(enable_timing=True)
+        e1.record()
+        self.ev.append((key, e0, e1))
+
+    def per_key_ms(self):
+        self.torch.cuda.synchronize()
+        out = {}
+        for key, a, b in self.ev:
+            out.setdefault(key, []).append(a.elapsed_time(b))
+        return out
+
+
+def headline(torch, T, I, args):
+    """The binary64 streaming sweep: returns per-sub-case state and timings."""
+    cases = []
+    for k in KS:
+        n = k
+        B = I.device_uniform((k, n), I.BASE_SEED, 100 + k, torch.float64)
+        pk = T.pack(B)
+        As = [I.device_uniform((M_ROWS, k), I.BASE_SEED, 200 + 10 * k + r, torch.float64) for r in range(2)]
+        for beta in BETAS:
+            tag = "k%db%d" % (k, int(beta))
+            if args.only and tag != args.only:
+                continue
+            C = I.device_uniform((M_ROWS, n), I.BASE_SEED, 300 + 10 * k + int(beta), torch.float64)
+            p = T.plan(M_ROWS, n, k, "N", torch.float64)
+            cases.append(dict(tag=tag, k=k, n=n, beta=beta, B=B, pk=pk, As=As, C=C, p=p,
+                              bytes=opn_bytes(M_ROWS, n, k, beta), flops=2.0 * M_ROWS * n * k))
+    return cases
+
+
+def run_headline(torch, T, cases, steps, warmup):
+    timer = Timer(torch)
+    call = [0]
+
+    def step(record):
+        for c in cases:
+            A = c["As"][call[0] % 2]
+            e0 = timer.start() if record else None
+            T.execute(c["p"], A, c["pk"], c["C"], 1.0, c["beta"])
+            if record:
+                timer.stop(c["tag"], e0)
+        call[0] += 1
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, timer.per_key_ms()
+
+
+def bound_of(bytes_, flops, dt):
+    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
+    t_cmp = flops / (PEAK_TFLOPS[dt] * 1e12)
+    return ("hbm", t_hbm) if t_hbm >= t_cmp else ("mfma", t_cmp)
+
+
+def extras_opt(torch, T, I, steps, warmup):
+    K, m, n = 1 << 22, 64, 64
+    A = I.device_normal((K, m), I.BASE_SEED, 21, torch.float64)
+    B = I.device_normal((K, n), I.BASE_SEED, 22, torch.float64)
+    p = T.plan(m, n, K, "T", torch.float64)
+    pk = T.pack(B, "T")
+    C = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        T.execute(p, A, pk, C, 1.0, 0.0)
+    timer = Timer(torch)
+    for _ in range(steps):
+        e0 = timer.start()
+        T.execute(p, A, pk, C, 1.0, 0.0)
+        timer.stop("opt", e0)
+    ms = float(np.median(timer.per_key_ms()["opt"]))
+    byt = K * (m + n) * 8
+    fl = 2.0 * K * m * n
+    return dict(shape="A,B 2^22x64 f64, C=A^T B", plan=p.describe(), us=ms * 1e3, GB_s=byt / ms / 1e6,
+                hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, TFLOP_s=fl / ms / 1e9,
+                roofline_frac=bound_of(byt, fl, "f64")[1] / (ms * 1e-3)), (A, B, C)
+
+
+def extras_precision(torch, T, I, steps, warmup):
+    m, k, n = 1 << 24, 256, 256
+    A32 = I.device_col_scaled_uniform(m, k, I.BASE_SEED, 41, torch.float32)
+    B32 = I.device_uniform((k, n), I.BASE_SEED, 42, torch.float32)
+    out = {}
+    rows = I.sample_rows(m, 4096, 17)
+    idx = torch.from_numpy(rows).cuda()
+    keep = {"A_rows": A32[idx].cpu().numpy(), "B": B32.cpu().numpy()}
+    variants = [("f32_native", torch.float32, "native"), ("bf16x6", torch.float32, "bf16x6"),
+                ("bf16x3", torch.float32, "bf16x3"), ("f64", torch.float64, "native")]
+    for name, dt, mode in variants:
+        if dt == torch.float64:
+            A = A32.to(torch.float64)
+            B = B32.to(torch.float64)
+        else:
+            A, B = A32, B32
+        p = T.plan(m, n, k, "N", dt)
+        if mode != "native":
+            p.set_mode(mode)
+        pk = T.pack(B, "N", mode)
+        C = torch.empty((m, n), dtype=dt, device="cuda")
+        for _ in range(warmup):
+            T.execute(p, A, pk, C, 1.0, 0.0)
+        timer = Timer(torch)
+        for _ in range(max(3, steps // 4)):
+            e0 = timer.start()
+            T.execute(p, A, pk, C, 1.0, 0.0)
+            timer.stop(name, e0)
+        ms = float(np.median(timer.per_key_ms()[name]))
+        s = 8 if dt == torch.float64 else 4
+        byt = m * (k + n) * s
+        fl = 2.0 * m * n * k
+        bnd = bound_of(byt, fl, "f64" if dt == torch.float64 else ("bf16" if mode != "native" else "f32"))
+        out[name] = dict(plan=p.describe(), us=ms * 1e3, GB_s=byt / ms / 1e6, hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS,
+                         TFLOP_s=fl / ms / 1e9)
+        keep[name] = C[idx].cpu().numpy()
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out, keep
+
+
+def extras_batched(torch, T, I, steps, warmup):
+    count = 512
+    ms_, ns_, ks_ = I.batched_shapes(count, I.BASE_SEED)
+    out = {}
+    keep = {}
+    for dname, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        As, packs, Cs = [], [], []
+        byt = 0
+        fl = 0.0
+        for b in range(count):
+            m, n, k = int(ms_[b]), int(ns_[b]), int(ks_[b])
+            As.append(I.device_uniform((m, k), I.BASE_SEED, 1000 + b, dt))
+            packs.append(T.pack(I.device_uniform((k, n), I.BASE_SEED, 3000 + b, dt)))
+            Cs.append(torch.empty((m, n), dtype=torch.float32, device="cuda"))
+            byt += m * (k * As[-1].element_size() + n * 4)
+            fl += 2.0 * m * n * k
+        bp = T.plan_batched(ms_, ns_, ks_, dt)
+        bp.bind(As, packs, Cs)
+        g = bp.graph()
+        for _ in range(warmup):
+            g.launch()
+        timer = Timer(torch)
+        for _ in range(steps):
+            e0 = timer.start()
+            g.launch()
+            timer.stop(dname, e0)
+        ms = float(np.median(timer.per_key_ms()[dname]))
+        out[dname] = dict(instances=count, us=ms * 1e3, GB_s=byt / ms / 1e6, hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS,
+                          TFLOP_s=fl / ms / 1e9, bytes=byt)
+        keep[dname] = (As, packs, Cs, bp, g)
+    return out, keep
+
+
+def cpu_baseline(torch, I, cases, target_s=15.0):
+    """The FP64 oracle on a row sample of the headline workload, on this
+    host's cores; also the sampled error of the GPU results."""
+    import oracle
+    oracle.build()
+    cores = len(os.sched_getaffinity(0))
+    rows = I.sample_rows(M_ROWS, 1 << 17, 3)
+    idx = torch.from_numpy(rows).cuda()
+    tot_bytes, tot_s, worst = 0, 0.0, 0.0
+    per = []
+    for c in cases:
+        A = c["As"][0][idx].cpu().numpy()
+        B = c["B"].cpu().numpy()
+        C0 = c["C0s"] if "C0s" in c else None
+        t0 = time.perf_counter()
+        ref = oracle.gemm_n(A, B, C0, 1.0, c["beta"], threads=cores)
+        dt = time.perf_counter() - t0
+        tot_s += dt
+        tot_bytes += opn_bytes(len(rows), c["n"], c["k"], c["beta"])
+        if "Cs" in c:
+            err = oracle.normwise_rel_err(c["Cs"], ref)
+            worst = max(worst, err)
+            per.append(dict(case=c["tag"], sample_err=err))
+    return dict(value=tot_bytes / tot_s / 1e9, unit="GB/s", cores=cores, kind="oracle",
+                sample="%d sampled rows of each of the %d sub-cases (m=2^23 rows each), oracle time %.2f s"
+                       % (len(rows), len(cases), tot_s),
+                seconds=tot_s, sample_err_max=worst, per_case=per)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2208_08088_amd import inputs as I
+    from paper_2208_08088_amd import tsmm as T
+    T._lib()  # fail loudly if the HIP library is missing
+    torch.cuda.set_device(0)
+
+    cases = headline(torch, T, I, args)
+    print("[bench] headline cases ready: %s" % ", ".join(c["tag"] for c in cases), file=sys.stderr, flush=True)
+    # snapshot sampled C0 rows and check one call of each case (for the CPU leg)
+    rows = I.sample_rows(M_ROWS, 1 << 17, 3)
+    idx = torch.from_numpy(rows).cuda()
+    for c in cases:
+        c["C0s"] = c["C"][idx].cpu().numpy()
+        T.execute(c["p"], c["As"][0], c["pk"], c["C"], 1.0, c["beta"])
+        c["Cs"] = c["C"][idx].cpu().numpy()
+    torch.cuda.synchronize()
+
+    wall, per = run_headline(torch, T, cases, args.steps, args.warmup)
+    step_bytes = sum(c["bytes"] for c in cases)
+    value = step_bytes * args.steps / wall / 1e9
+    breakdown = []
+    dom = None
+    for c in cases:
+        msl = per[c["tag"]]
+        ms = float(np.mean(msl))
+        bnd, t_ideal = bound_of(c["bytes"], c["flops"], "f64")
+        row = dict(case=c["tag"], m=M_ROWS, k=c["k"], n=c["n"], beta=c["beta"], us=ms * 1e3,
+                   GB_s=c["bytes"] / ms / 1e6, hbm_frac=c["bytes"] / ms / 1e6 / HBM_PEAK_GBS,
+                   TFLOP_s=c["flops"] / ms / 1e9, bound=bnd, roofline_frac=t_ideal / (ms * 1e-3),
+                   plan=c["p"].describe())
+        breakdown.append(row)
+        if dom is None or ms > dom[1]:
+            dom = (c, ms, bnd)
+    c, ms, bnd = dom
+    if bnd == "hbm":
+        ach, peak, unit = c["bytes"] / ms / 1e6, HBM_PEAK_GBS, "GB/s"
+    else:
+        ach, peak, unit = c["flops"] / ms / 1e9, PEAK_TFLOPS["f64"], "TFLOP/s"
+    roofline = dict(kernel="k_stream<double,%d,%d> (%s)" % (c["k"], c["n"] // 16, c["tag"]), bound=bnd,
+                    achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=None,
+                    per_launch_bytes=c["bytes"], per_launch_flops=c["flops"], avg_launch_us=ms * 1e3)
+    print("[bench] headline done: %.1f GB/s" % value, file=sys.stderr, flush=True)
+
+    result = dict(metric="TSMM GB/s (frac of HBM peak): FP64 plain vs split-BF16/FP32 at <=1e-6 rel err",
+                  value=value, unit="GB/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                  ms_per_step=wall / args.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+                  dtype="f64", data="synthetic",
+                  config=dict(workload="binary64 tall-A x small-B, m=2^23, k=n in {8,32,128}, beta in {0,1}, "
+                                       "packed B reused, fresh A per call", m=M_ROWS, k_n=list(KS),
+                              betas=list(BETAS), step_bytes=step_bytes),
+                  hbm_frac=value / HBM_PEAK_GBS, roofline=roofline, breakdown=breakdown)
+
+    if not args.no_extras and not args.only:
+        opt, keep_t = extras_opt(torch, T, I, args.steps, args.warmup)
+        print("[bench] op T done", file=sys.stderr, flush=True)
+        prec, keep_p = extras_precision(torch, T, I, args.steps, args.warmup)
+        print("[bench] precision done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        bat, keep_b = extras_batched(torch, T, I, args.steps, args.warmup)
+        print("[bench] batched done", file=sys.stderr, flush=True)
+        del keep_b, keep_t
+        result["extras"] = dict(op_t_splitk=opt, precision_m2p24_k256=prec, batched_512=bat)
+
+    if not args.no_cpu_baseline and not args.only:
+        result["cpu_baseline"] = cpu_baseline(torch, I, cases)
+        if "extras" in result:
+            # sampled errors of the precision variants against the oracle
+            import oracle
+            ref = oracle.gemm_n(keep_p["A_rows"], keep_p["B"], threads=len(os.sched_getaffinity(0)))
+            for name, row in result["extras"]["precision_m2p24_k256"].items():
+                row["sample_err"] = oracle.normwise_rel_err(keep_p[name], ref)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

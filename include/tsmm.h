@@ -1,0 +1,293 @@
+/*
+ * tsmm.h -- pre-packed tall-and-skinny matrix multiply on MI355X (gfx950).
+ *
+ * The operation is the GEMM contract of AutoTSMM (Sec. I, Eq. (1)):
+ *
+ *     C = alpha * op(A) * B + beta * C
+ *
+ * for the tall-and-skinny case, where one dimension of an operand is far
+ * smaller than the other (Sec. I).  The library follows the paper's split
+ * of the problem (Algorithm 1, Sec. III):
+ *
+ *   tsmm_pack     packs the small operand once into a reusable handle
+ *                 (the PACKB step of Algorithm 1; the pre-pack module of
+ *                 Sec. IV-A.3);
+ *   tsmm_plan     builds an execution plan for a shape from the tile table
+ *                 written by the install-time autotuner (the runtime stage
+ *                 of Sec. III: cache-blocked designer, multi-thread
+ *                 optimizer, performance evaluator; Eqs. (2)-(3));
+ *   tsmm_execute  runs the multiply (the COMPUTE step of Algorithm 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are dense, row-major and contiguous (no leading dimensions).
+ *   - op N:  A is m x k, B is k x n, C is m x n:      C = a*A*B   + b*C.
+ *     op T:  A is k x m, B is k x n, C is m x n:      C = a*A^T*B + b*C,
+ *            the reduction shape over a long shared dimension k.
+ *   - Every matrix pointer passed to tsmm_pack / tsmm_execute* is a DEVICE
+ *     pointer owned by the caller; size and shape arrays passed to the plan
+ *     calls are HOST pointers.  C must not alias A or B.
+ *   - alpha and beta are binary64.  The epilogue is evaluated in binary64 as
+ *     RN(RN(alpha*acc) + RN(beta*c)), with no fused multiply-add, and rounded
+ *     once more to C's type.  beta == 0 never reads C (NaN in C is safe);
+ *     alpha == 0 never reads A or the packed operand; k == 0 gives
+ *     C = beta*C; m == 0 or n == 0 launches nothing.
+ *   - Element types: TSMM_F64 inputs give a binary64 C; TSMM_F32 inputs give
+ *     a binary32 C; TSMM_BF16 inputs give a binary32 C.
+ *   - Every call returns a tsmm_status and never aborts.  Arguments are
+ *     validated on the host before any HIP call, so invalid arguments are
+ *     reported the same way on hosts without a GPU.  tsmm_last_error()
+ *     returns a thread-local text with the detail of the last failure.
+ *   - tsmm_pack and tsmm_execute* are asynchronous on the HIP stream given
+ *     (NULL = the null stream); device faults surface at the caller's next
+ *     synchronisation.
+ *   - Handles are opaque host objects; the destroy calls accept NULL.
+ *     Plans and packed handles are immutable once built, except for the
+ *     stream / workspace / tile setters, which a caller must not race with
+ *     an execute on the same plan.
+ */
+#ifndef TSMM_H
+#define TSMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tsmm_status {
+    TSMM_SUCCESS = 0,
+    TSMM_ERROR_INVALID_VALUE = 1,  /* bad pointer, negative size, bad enum */
+    TSMM_ERROR_SHAPE_MISMATCH = 2, /* plan and packed operand disagree      */
+    TSMM_ERROR_NOT_SUPPORTED = 3,  /* shape/type/mode outside the library   */
+    TSMM_ERROR_TABLE = 4,          /* tile table unreadable (strict mode)   */
+    TSMM_ERROR_OUT_OF_MEMORY = 5,  /* device or host allocation failed      */
+    TSMM_ERROR_NO_DEVICE = 6,      /* no usable gfx950 device               */
+    TSMM_ERROR_HIP = 7             /* a HIP runtime call failed             */
+} tsmm_status;
+
+typedef enum tsmm_dtype {
+    TSMM_F64 = 0,  /* binary64 in, binary64 out                       */
+    TSMM_F32 = 1,  /* binary32 in, binary32 out                       */
+    TSMM_BF16 = 2  /* bfloat16 in, binary32 accumulation and output   */
+} tsmm_dtype;
+
+typedef enum tsmm_layout {
+    TSMM_OP_N = 0, /* C = alpha*A*B + beta*C,   A m x k */
+    TSMM_OP_T = 1  /* C = alpha*A^T*B + beta*C, A k x m */
+} tsmm_layout;
+
+/* Arithmetic used for TSMM_F32 inputs (other types accept NATIVE only).
+ *   NATIVE  binary32 matrix-core products, binary32 accumulation.
+ *   BF16X3  two-term bfloat16 split of both operands (x = hi + mid + r),
+ *           products hi*hi + hi*mid + mid*hi, binary32 accumulation.
+ *   BF16X6  three-term split (x = hi + mid + lo, exact for normal binary32),
+ *           the six products with term order i + j <= 2, binary32
+ *           accumulation.  The packed operand carries a power-of-two scale
+ *           per column of B that the binary64 epilogue undoes. */
+typedef enum tsmm_mode {
+    TSMM_MODE_NATIVE = 0,
+    TSMM_MODE_BF16X3 = 1,
+    TSMM_MODE_BF16X6 = 2
+} tsmm_mode;
+
+/* Kernel families a tile can name (tsmm_tile.kernel). */
+typedef enum tsmm_kernel {
+    TSMM_KERNEL_AUTO = 0,     /* let the plan choose                          */
+    TSMM_KERNEL_SIMPLE = 1,   /* any shape: one thread per output, no packing
+                                 assumptions; the conservative fallback        */
+    TSMM_KERNEL_STREAM = 2,   /* op N streaming: packed B fragments, A rows
+                                 streamed through registers, matrix cores     */
+    TSMM_KERNEL_SPLITK = 3,   /* op T: split-k partials + ordered reduce      */
+    TSMM_KERNEL_SPLITBF16 = 4 /* op N, TSMM_F32 in BF16X3 / BF16X6 mode       */
+} tsmm_kernel;
+
+/* One entry of the tile table: the register/LDS blocking and launch shape
+ * of a plan (the analogue of the paper's m_t / m_c / k_c / n_c blocking and
+ * thread split, Sec. IV-A.1 and IV-A.2).  Zero in a field means "default". */
+typedef struct tsmm_tile {
+    int32_t kernel;        /* tsmm_kernel                                   */
+    int32_t rows_per_wave; /* 16-row tiles a wavefront owns at a time: 1,2,4 */
+    int32_t waves_per_wg;  /* wavefronts per workgroup: 1..16               */
+    int32_t wg_per_cu;     /* resident workgroups per compute unit (grid =
+                              CUs * wg_per_cu, capped by the work): 1..32   */
+    int32_t splitk;        /* op T: number of partial sums P (1..65536)     */
+    int32_t nsplit;        /* op N: column groups sharing one row block     */
+} tsmm_tile;
+
+/* Device properties the planner uses; tsmm_plan reads them from the current
+ * HIP device.  tsmm_plan_with_caps takes them from the caller instead, so
+ * that plan arithmetic can be checked without a GPU. */
+typedef struct tsmm_device_caps {
+    int32_t compute_units;    /* 256 on MI355X                      */
+    int32_t lds_bytes_per_cu; /* 163840 on gfx950                   */
+    int32_t gcn_arch;         /* 950 for gfx950                     */
+} tsmm_device_caps;
+
+typedef struct tsmm_packed_s *tsmm_packed_t;
+typedef struct tsmm_plan_s *tsmm_plan_t;
+typedef struct tsmm_graph_s *tsmm_graph_t;
+
+/* ------------------------------------------------------------------ errors */
+
+/* Static text for a status code; never NULL. */
+const char *tsmm_status_string(tsmm_status status);
+
+/* Thread-local detail of the last failing call on this thread ("" if none).
+ * The pointer stays valid until the next tsmm_* call on the same thread. */
+const char *tsmm_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t tsmm_version(void);
+
+/* -------------------------------------------------------------------- pack */
+
+/* Pack the small operand B once, for reuse by any number of executes
+ * (Algorithm 1, PACKB with unit scale; Sec. II-C and IV-A.3: packing is
+ * done apart from, and before, the computation so that its cost is paid
+ * once).
+ *   B       device pointer, row-major k x n of `dtype` (bfloat16 as raw
+ *           16-bit patterns).  Read asynchronously on `stream`; the caller
+ *           keeps it alive until the stream has passed the pack.
+ *   k, n    B's shape, k >= 0, n >= 0.
+ *   layout  TSMM_OP_N: B is the small operand and is rearranged into the
+ *           matrix-core fragment order of the execute kernels (and, for the
+ *           BF16X3 / BF16X6 modes, split into bfloat16 planes with a
+ *           power-of-two scale per column).  TSMM_OP_T: both operands are
+ *           tall and nothing is copied: the handle refers to B itself, which
+ *           the caller keeps alive and unchanged while the handle is used.
+ *   mode    tsmm_mode; only TSMM_F32 accepts a mode other than NATIVE.
+ *   stream  hipStream_t or NULL.
+ *   out     receives the handle (host object owning device memory that the
+ *           library allocates); free it with tsmm_packed_destroy after the
+ *           last execute that uses it has completed.
+ * Errors: INVALID_VALUE (NULL out, NULL B with k*n > 0, negative sizes, bad
+ * enum), NOT_SUPPORTED (mode not valid for dtype), OUT_OF_MEMORY, HIP. */
+tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout,
+                      tsmm_dtype dtype, tsmm_mode mode, void *stream,
+                      tsmm_packed_t *out);
+
+/* Bytes of device memory held by a packed handle. */
+tsmm_status tsmm_packed_bytes(tsmm_packed_t packed, size_t *bytes);
+
+/* Write B back from a packed handle (row-major k x n, the packed type; for
+ * the split modes the binary32 value (sum of the planes) * 2^e_j).  Used to
+ * check that packing loses nothing.  B_out is a device pointer of k*n
+ * elements.  Asynchronous on `stream`. */
+tsmm_status tsmm_unpack(tsmm_packed_t packed, void *B_out, void *stream);
+
+/* Copy the bfloat16 planes and column exponents of a split-mode handle:
+ * planes_out receives terms*k*n uint16 values, plane t of element (i, j) at
+ * t*k*n + i*n + j (the split of B[i][j] * 2^-e_j); exps_out receives n
+ * int32 values e_j.  Device pointers; asynchronous on `stream`.
+ * NOT_SUPPORTED for a handle that is not in a split mode. */
+tsmm_status tsmm_packed_split_planes(tsmm_packed_t packed, void *planes_out,
+                                     void *exps_out, void *stream);
+
+void tsmm_packed_destroy(tsmm_packed_t packed);
+
+/* -------------------------------------------------------------------- plan */
+
+/* Build an execution plan for one shape (the runtime stage of Sec. III):
+ * the tile comes from the tile table (TSMM_TILE_TABLE, else tile_table.txt
+ * beside the library) keyed by layout, dtype, mode and size classes, else
+ * from built-in defaults; it is then checked against the device's limits
+ * (LDS capacity per compute unit, the analogue of Eq. (2); register budget,
+ * the analogue of Eq. (3)) and the launch geometry is derived.
+ *   m, n, k  op N: A m x k, B k x n.  op T: A k x m, B k x n.  All >= 0.
+ * The plan starts in TSMM_MODE_NATIVE on the null stream with no
+ * workspace.  Host only: no device memory is touched.
+ * Errors: INVALID_VALUE, NOT_SUPPORTED, NO_DEVICE (tsmm_plan only). */
+tsmm_status tsmm_plan(int64_t m, int64_t n, int64_t k, tsmm_layout layout,
+                      tsmm_dtype dtype, tsmm_plan_t *out);
+
+tsmm_status tsmm_plan_with_caps(int64_t m, int64_t n, int64_t k,
+                                tsmm_layout layout, tsmm_dtype dtype,
+                                const tsmm_device_caps *caps,
+                                tsmm_plan_t *out);
+
+/* Select the arithmetic (tsmm_mode) and re-derive the tile for it. */
+tsmm_status tsmm_plan_set_mode(tsmm_plan_t plan, tsmm_mode mode);
+
+/* Replace the tile (autotuner and tests).  The tile is validated against
+ * the shape and the device limits; INVALID_VALUE / NOT_SUPPORTED if it
+ * cannot run. */
+tsmm_status tsmm_plan_set_tile(tsmm_plan_t plan, const tsmm_tile *tile);
+tsmm_status tsmm_plan_get_tile(tsmm_plan_t plan, tsmm_tile *tile);
+
+/* Stream (hipStream_t, NULL = null stream) on which executes are queued. */
+tsmm_status tsmm_plan_set_stream(tsmm_plan_t plan, void *stream);
+
+/* Device scratch an execute needs (the op T partial sums: splitk * m * n
+ * binary64 values); 0 when none. */
+tsmm_status tsmm_plan_workspace_bytes(tsmm_plan_t plan, size_t *bytes);
+
+/* Attach caller-owned device scratch of at least tsmm_plan_workspace_bytes
+ * bytes.  Without it, the first execute that needs scratch allocates it
+ * and the plan owns it.  Two executes sharing one workspace must not run
+ * concurrently. */
+tsmm_status tsmm_plan_set_workspace(tsmm_plan_t plan, void *workspace,
+                                    size_t bytes);
+
+/* A one-line text description of the plan (kernel, tile, grid); writes at
+ * most len bytes including the terminating NUL. */
+tsmm_status tsmm_plan_describe(tsmm_plan_t plan, char *buf, size_t len);
+
+void tsmm_plan_destroy(tsmm_plan_t plan);
+
+/* ----------------------------------------------------------------- execute */
+
+/* C = alpha * op(A) * B + beta * C with B taken from `packed` (Algorithm 1,
+ * COMPUTE; the output line of Algorithm 1).
+ *   plan    from tsmm_plan for (m, n, k, layout, dtype); its mode must match
+ *           the packed handle's, and the handle's k, n, layout and dtype must
+ *           match the plan (SHAPE_MISMATCH otherwise).
+ *   A       device pointer, op N: m x k; op T: k x m; row-major.
+ *   C       device pointer, m x n row-major, read (if beta != 0) and written.
+ * Asynchronous on the plan's stream.
+ * Errors: INVALID_VALUE, SHAPE_MISMATCH, OUT_OF_MEMORY (lazy workspace),
+ * HIP (launch failure; text in tsmm_last_error). */
+tsmm_status tsmm_execute(tsmm_plan_t plan, const void *A, tsmm_packed_t packed,
+                         void *C, double alpha, double beta);
+
+/* ----------------------------------------------------------------- batched */
+
+/* Plan `count` independent op N multiplies that run in ONE persistent
+ * launch: instance b is m[b] x k[b] times k[b] x n[b].  Host arrays.  The
+ * plan builds a static, cost-balanced work list (16-row tiles of every
+ * instance, longest instances first) and owns its device copy.
+ * dtype: TSMM_F32 (binary32 in/out) or TSMM_BF16 (bfloat16 in, binary32
+ * out), NATIVE mode; 1 <= k[b], n[b] <= 128.
+ * Errors: INVALID_VALUE, NOT_SUPPORTED, NO_DEVICE, OUT_OF_MEMORY, HIP. */
+tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
+                              const int64_t *k, tsmm_dtype dtype,
+                              tsmm_plan_t *out);
+
+/* Bind the operands of a batched plan: host arrays of `count` device
+ * pointers / handles / scalars.  The descriptor table is copied to the
+ * device on the plan's stream from pinned staging memory, so a bind can be
+ * captured in a graph.  Every packed[b] must match (k[b], n[b], dtype). */
+tsmm_status tsmm_batched_bind(tsmm_plan_t plan, const void *const *A,
+                              const tsmm_packed_t *packed, void *const *C,
+                              const double *alpha, const double *beta);
+
+/* Run every instance of the bound batched plan in one launch on the plan's
+ * stream.  If A is not NULL the operands are bound first (as
+ * tsmm_batched_bind) when they differ from the bound ones. */
+tsmm_status tsmm_execute_batched(tsmm_plan_t plan, const void *const *A,
+                                 const tsmm_packed_t *packed, void *const *C,
+                                 const double *alpha, const double *beta);
+
+/* Capture tsmm_execute_batched of a bound plan into a HIP graph once
+ * (stream capture on the plan's stream) and instantiate it; launch it any
+ * number of times with tsmm_graph_launch.  The graph keeps the bound
+ * pointers: rebinding the plan afterwards does not change it. */
+tsmm_status tsmm_graph_create_batched(tsmm_plan_t plan, tsmm_graph_t *out);
+tsmm_status tsmm_graph_launch(tsmm_graph_t graph, void *stream);
+void tsmm_graph_destroy(tsmm_graph_t graph);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSMM_H */

@@ -1,0 +1,13 @@
+// Split-bf16 kernels, two terms / three products (binary32 inputs).
+#include "k_bf16.h"
+
+namespace tsmm {
+static const Bf16Entry kX3[] = {
+    TSMM_BE_KC(float, 1, 3, true) TSMM_BE_KC(float, 2, 3, true) TSMM_BE_KC(float, 1, 3, false)
+};
+Bf16Fn find_bf16_x3(int KC, int NT, int RT, bool vec) {
+    for (const Bf16Entry &e : kX3)
+        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec) return e.fn;
+    return nullptr;
+}
+}  // namespace tsmm

@@ -1,0 +1,68 @@
+// Device helpers shared by the libtsmm kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tsmm {
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// 16x16x4 matrix-core product for binary64 / binary32 (one A and one B
+// element per lane, four accumulator rows per lane).  Lane 16*q + j
+// supplies A(row j, k-slot q) and B(k-slot q, column j) in both types; its
+// accumulator element r holds column j of row row(q, r), which is q + 4*r
+// for V_MFMA_F64_16X16X4_F64 and 4*q + r for V_MFMA_F32_16X16X4_F32
+// (established by an on-device layout probe).
+template <typename T> struct Mfma4;
+template <> struct Mfma4<double> {
+    typedef d4v acc;
+    typedef d2v vec;  // one 16-byte vector
+    static constexpr int VW = 2;
+    static __device__ __forceinline__ int row(int q, int r) { return q + 4 * r; }
+    static __device__ __forceinline__ acc op(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma4<float> {
+    typedef f4v acc;
+    typedef f4v vec;
+    static constexpr int VW = 4;
+    static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; }
+    static __device__ __forceinline__ acc op(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// The binary64 epilogue RN(RN(alpha*acc) + RN(beta*c)); never fused.
+// beta == 0 ignores c (which the caller then never loads).
+__device__ __forceinline__ double epilogue(double alpha, double acc, double beta, double c) {
+#pragma clang fp contract(off)
+    double t = alpha * acc;
+    if (beta != 0.0) t = t + beta * c;
+    return t;
+}
+
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t h) {
+    return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// binary32 -> bfloat16 bits, round to nearest even (finite inputs; a NaN
+// input stays a NaN).
+__device__ __forceinline__ uint16_t float_to_bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <typename T> __device__ __forceinline__ double to_f64(T x) { return (double)x; }
+template <typename T> __device__ __forceinline__ T from_f64(double x) { return (T)x; }
+
+}  // namespace tsmm

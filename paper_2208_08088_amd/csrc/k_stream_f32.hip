@@ -1,0 +1,24 @@
+// binary32 instantiations of the op N streaming kernel (16x16x4 f32).
+#include "k_stream.h"
+
+namespace tsmm {
+
+static const StreamEntry kF32[] = {
+    // scalar k-slot mapping (k not a multiple of 4, or k <= 8)
+    TSMM_SE_RT1(float, 4, false) TSMM_SE_RT1(float, 8, false) TSMM_SE_RT1(float, 16, false)
+    TSMM_SE_RT1(float, 32, false) TSMM_SE_RT1(float, 64, false) TSMM_SE_RT1(float, 128, false)
+    TSMM_SE_RT1(float, 256, false)
+    TSMM_SE_RT2(float, 4, false) TSMM_SE_RT4(float, 4, false)
+    TSMM_SE_RT2(float, 8, false) TSMM_SE_RT4(float, 8, false)
+    // vector mapping
+    TSMM_SE_ALL(float, 16, true) TSMM_SE_ALL(float, 32, true) TSMM_SE_ALL(float, 64, true)
+    TSMM_SE_ALL(float, 128, true) TSMM_SE_RT1(float, 256, true) TSMM_SE_RT2(float, 256, true)
+};
+
+StreamFn find_stream_f32(int KC, int NT, int RT, bool vec) {
+    for (const StreamEntry &e : kF32)
+        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec) return e.fn;
+    return nullptr;
+}
+
+}  // namespace tsmm

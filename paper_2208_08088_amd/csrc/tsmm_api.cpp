@@ -1,0 +1,1015 @@
+// Host runtime of libtsmm: the C ABI declared in include/tsmm.h.
+//
+// It plays the part of the paper's runtime stage (Sec. III, Sec. IV-A):
+// the packed handle is the pre-pack module's output with its header
+// (Sec. IV-A.3: contiguous packed blocks plus a header that locates them);
+// the plan is the execution plan (tile from the install-time table,
+// checked against the capacity limits that Eqs. (2)-(3) express for CPU
+// caches, here LDS and registers); execute launches the COMPUTE kernels.
+// Every argument is validated before the first HIP call.
+#include <dlfcn.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cinttypes>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+
+#include "tsmm_internal.h"
+
+using namespace tsmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+tsmm_status fail(tsmm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+tsmm_status hip_fail(hipError_t e, const char *what) {
+    return fail(TSMM_ERROR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int log_level() {
+    static int lvl = [] {
+        const char *s = getenv("TSMM_LOG");
+        return s ? atoi(s) : 0;
+    }();
+    return lvl;
+}
+
+bool valid_dtype(int d) { return d == TSMM_F64 || d == TSMM_F32 || d == TSMM_BF16; }
+bool valid_layout(int l) { return l == TSMM_OP_N || l == TSMM_OP_T; }
+bool valid_mode(int m) { return m == TSMM_MODE_NATIVE || m == TSMM_MODE_BF16X3 || m == TSMM_MODE_BF16X6; }
+
+const char *dtype_name(tsmm_dtype d) { return d == TSMM_F64 ? "f64" : d == TSMM_F32 ? "f32" : "bf16"; }
+const char *mode_name(tsmm_mode m) {
+    return m == TSMM_MODE_NATIVE ? "native" : m == TSMM_MODE_BF16X3 ? "bf16x3" : "bf16x6";
+}
+const char *kernel_name(int k) {
+    switch (k) {
+    case TSMM_KERNEL_SIMPLE: return "simple";
+    case TSMM_KERNEL_STREAM: return "stream";
+    case TSMM_KERNEL_SPLITK: return "splitk";
+    case TSMM_KERNEL_SPLITBF16: return "splitbf16";
+    default: return "auto";
+    }
+}
+
+int split_terms(tsmm_dtype d, tsmm_mode m) {
+    if (d == TSMM_BF16) return 1;
+    if (m == TSMM_MODE_BF16X3) return 2;
+    if (m == TSMM_MODE_BF16X6) return 3;
+    return 0;
+}
+int split_products(tsmm_dtype d, tsmm_mode m) {
+    if (d == TSMM_BF16) return 1;
+    return m == TSMM_MODE_BF16X3 ? 3 : 6;
+}
+
+// ------------------------------------------------------------ device caps
+
+tsmm_status query_caps(tsmm_device_caps *caps, int *device) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(TSMM_ERROR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+    static std::mutex mu;
+    static std::map<int, tsmm_device_caps> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it == cache.end()) {
+        hipDeviceProp_t p;
+        e = hipGetDeviceProperties(&p, dev);
+        if (e != hipSuccess) return fail(TSMM_ERROR_NO_DEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+        tsmm_device_caps c{};
+        c.compute_units = p.multiProcessorCount;
+        c.lds_bytes_per_cu = (int32_t)p.maxSharedMemoryPerMultiProcessor;
+        int arch = 0;
+        if (sscanf(p.gcnArchName, "gfx%d", &arch) != 1) arch = 0;
+        c.gcn_arch = arch;
+        it = cache.emplace(dev, c).first;
+    }
+    *caps = it->second;
+    *device = dev;
+    if (caps->gcn_arch != 950)
+        return fail(TSMM_ERROR_NO_DEVICE, "device %d is gfx%d; this library is built for gfx950", dev,
+                    caps->gcn_arch);
+    return TSMM_SUCCESS;
+}
+
+// ------------------------------------------------------------- tile table
+//
+// Text table written by the install-time autotuner, one entry per line:
+//   <layout N|T> <dtype f64|f32|bf16> <mode native|bf16x3|bf16x6>
+//   <kc> <nt> <mclass> : <kernel> <rows_per_wave> <waves_per_wg>
+//   <wg_per_cu> <splitk> <nsplit>
+// op N: kc = packed k class, nt = 16-column tiles class, mclass = row class.
+// op T: kc = 16-row tiles of the output (m), nt = 16-column tiles (n),
+//       mclass = class of the shared dimension.
+// '#' starts a comment.
+
+struct TableKey {
+    int layout, dtype, mode, kc, nt, mclass;
+    bool operator<(const TableKey &o) const {
+        return std::tie(layout, dtype, mode, kc, nt, mclass) <
+               std::tie(o.layout, o.dtype, o.mode, o.kc, o.nt, o.mclass);
+    }
+};
+
+struct Table {
+    std::map<TableKey, tsmm_tile> entries;
+    std::string path;
+    bool loaded = false;
+    std::string error;
+};
+
+std::string library_dir() {
+    Dl_info info;
+    if (dladdr((void *)&tsmm_version, &info) && info.dli_fname) {
+        std::string p = info.dli_fname;
+        size_t s = p.find_last_of('/');
+        if (s != std::string::npos) return p.substr(0, s);
+    }
+    return ".";
+}
+
+int parse_kernel(const std::string &s) {
+    if (s == "simple") return TSMM_KERNEL_SIMPLE;
+    if (s == "stream") return TSMM_KERNEL_STREAM;
+    if (s == "splitk") return TSMM_KERNEL_SPLITK;
+    if (s == "splitbf16") return TSMM_KERNEL_SPLITBF16;
+    return -1;
+}
+
+bool parse_table_line(const std::string &line, TableKey *key, tsmm_tile *tile) {
+    std::istringstream is(line);
+    std::string lay, dt, md, colon, kern;
+    if (!(is >> lay >> dt >> md >> key->kc >> key->nt >> key->mclass >> colon >> kern)) return false;
+    if (colon != ":") return false;
+    key->layout = lay == "N" ? TSMM_OP_N : lay == "T" ? TSMM_OP_T : -1;
+    key->dtype = dt == "f64" ? TSMM_F64 : dt == "f32" ? TSMM_F32 : dt == "bf16" ? TSMM_BF16 : -1;
+    key->mode = md == "native" ? TSMM_MODE_NATIVE : md == "bf16x3" ? TSMM_MODE_BF16X3 : md == "bf16x6" ? TSMM_MODE_BF16X6 : -1;
+    if (key->layout < 0 || key->dtype < 0 || key->mode < 0) return false;
+    tsmm_tile t{};
+    t.kernel = parse_kernel(kern);
+    if (t.kernel < 0) return false;
+    if (!(is >> t.rows_per_wave >> t.waves_per_wg >> t.wg_per_cu >> t.splitk >> t.nsplit)) return false;
+    *tile = t;
+    return true;
+}
+
+Table &table() {
+    static Table tab;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *env = getenv("TSMM_TILE_TABLE");
+        tab.path = env ? env : library_dir() + "/tile_table.txt";
+        std::ifstream f(tab.path);
+        if (!f) {
+            tab.error = "cannot open " + tab.path;
+            return;
+        }
+        std::string line;
+        int lineno = 0;
+        while (std::getline(f, line)) {
+            ++lineno;
+            size_t h = line.find('#');
+            if (h != std::string::npos) line.resize(h);
+            if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+            TableKey k;
+            tsmm_tile t;
+            if (!parse_table_line(line, &k, &t)) {
+                tab.error = tab.path + ":" + std::to_string(lineno) + ": malformed entry";
+                tab.entries.clear();
+                return;
+            }
+            tab.entries[k] = t;
+        }
+        tab.loaded = true;
+    });
+    return tab;
+}
+
+int mclass_of(int64_t m) { return m < (1 << 16) ? 0 : (m < (1 << 21) ? 1 : 2); }
+
+// -------------------------------------------------------------- planning
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Which kernel family serves (layout, dtype, mode, shape)?
+int natural_kernel(const tsmm_plan_s &p) {
+    if (p.layout == TSMM_OP_T) return p.dtype == TSMM_F64 ? TSMM_KERNEL_SPLITK : TSMM_KERNEL_SIMPLE;
+    if (p.dtype == TSMM_BF16 || p.mode != TSMM_MODE_NATIVE)
+        return (kclass32(p.k) && ntclass(p.n)) ? TSMM_KERNEL_SPLITBF16 : TSMM_KERNEL_SIMPLE;
+    return (kclass4(p.k) && ntclass(p.n)) ? TSMM_KERNEL_STREAM : TSMM_KERNEL_SIMPLE;
+}
+
+int pow2_tiles(int64_t d) {  // 16-wide tiles of a small dimension, as 1, 2 or 4
+    int t = (int)((d + 15) / 16);
+    return t <= 1 ? 1 : (t <= 2 ? 2 : 4);
+}
+
+tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
+    tsmm_tile t{};
+    t.kernel = kernel;
+    t.waves_per_wg = 4;
+    t.nsplit = 1;
+    t.splitk = 1;
+    switch (kernel) {
+    case TSMM_KERNEL_STREAM: {
+        const int KC = kclass4(p.k), NT = ntclass(p.n);
+        const int w = KC * NT;
+        const bool vec = vec_mapping(p.dtype, p.k, KC);
+        t.rows_per_wave = w <= 64 ? 4 : (w <= 256 ? 2 : 1);
+        while (t.rows_per_wave > 1 && !stream_variant_exists(p.dtype, KC, NT, t.rows_per_wave, vec))
+            t.rows_per_wave /= 2;
+        t.wg_per_cu = 8;
+        break;
+    }
+    case TSMM_KERNEL_SPLITBF16:
+        t.rows_per_wave = 2;
+        while (t.rows_per_wave > 1 &&
+               !splitbf16_variant_exists(p.dtype, kclass32(p.k), ntclass(p.n), t.rows_per_wave,
+                                         split_products(p.dtype, p.mode)))
+            t.rows_per_wave /= 2;
+        t.wg_per_cu = 4;
+        break;
+    case TSMM_KERNEL_SPLITK:
+        t.rows_per_wave = 2;  // RG: 4-row groups per wavefront iteration
+        t.wg_per_cu = 2;
+        t.splitk = std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)p.caps.compute_units, (p.k + 255) / 256));
+        break;
+    default:
+        t.rows_per_wave = 1;
+        t.wg_per_cu = 1;
+        break;
+    }
+    return t;
+}
+
+// Validate a tile for the plan and derive the launch geometry.
+tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
+    tsmm_tile t = tile_in;
+    if (t.kernel == TSMM_KERNEL_AUTO) t.kernel = natural_kernel(p);
+    const int nat = natural_kernel(p);
+    if (t.kernel != nat && t.kernel != TSMM_KERNEL_SIMPLE)
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "kernel %s cannot run this plan (natural kernel %s)",
+                    kernel_name(t.kernel), kernel_name(nat));
+    if (t.kernel == TSMM_KERNEL_SIMPLE && (p.mode != TSMM_MODE_NATIVE))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes need k <= %d and n <= 256", kMaxKC);
+    tsmm_tile d = default_tile(p, t.kernel);
+    if (t.rows_per_wave == 0) t.rows_per_wave = d.rows_per_wave;
+    if (t.waves_per_wg == 0) t.waves_per_wg = d.waves_per_wg;
+    if (t.wg_per_cu == 0) t.wg_per_cu = d.wg_per_cu;
+    if (t.splitk == 0) t.splitk = d.splitk;
+    if (t.nsplit == 0) t.nsplit = d.nsplit;
+    if (t.rows_per_wave < 0 || t.waves_per_wg < 1 || t.waves_per_wg > 4 || !is_pow2(t.waves_per_wg) ||
+        t.wg_per_cu < 1 || t.wg_per_cu > 32 || t.splitk < 1 || t.splitk > 65536 || t.nsplit != 1)
+        return fail(TSMM_ERROR_INVALID_VALUE, "tile out of range (waves_per_wg 1/2/4, wg_per_cu 1..32, "
+                                              "splitk 1..65536, nsplit 1)");
+    const int64_t cus = std::max(1, p.caps.compute_units);
+    p.block = 64 * t.waves_per_wg;
+    p.workspace_bytes = 0;
+    p.grid_y = 1;
+    switch (t.kernel) {
+    case TSMM_KERNEL_STREAM: {
+        p.KC = kclass4(p.k);
+        p.NT = ntclass(p.n);
+        p.vec = vec_mapping(p.dtype, p.k, p.KC);
+        if (!stream_variant_exists(p.dtype, p.KC, p.NT, t.rows_per_wave, p.vec))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no stream kernel for KC=%d NT=%d RT=%d vec=%d", p.KC,
+                        p.NT, t.rows_per_wave, (int)p.vec);
+        const size_t lds = (size_t)(p.KC / 4) * p.NT * 64 * elem_bytes(p.dtype);
+        if (lds <= 128 * 1024 && (int64_t)lds > p.caps.lds_bytes_per_cu)  // Eq. (2) analogue
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "packed B (%zu bytes) exceeds LDS", lds);
+        const int64_t waves = ((p.m + 15) / 16 + t.rows_per_wave - 1) / t.rows_per_wave;
+        const int64_t wgs = (waves + t.waves_per_wg - 1) / t.waves_per_wg;
+        p.grid = std::max<int64_t>(1, std::min<int64_t>(wgs, cus * t.wg_per_cu));
+        break;
+    }
+    case TSMM_KERNEL_SPLITBF16: {
+        p.KC = kclass32(p.k);
+        p.NT = ntclass(p.n);
+        p.vec = false;
+        if (!splitbf16_variant_exists(p.dtype, p.KC, p.NT, t.rows_per_wave, split_products(p.dtype, p.mode)))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no split-bf16 kernel for KC=%d NT=%d RT=%d", p.KC,
+                        p.NT, t.rows_per_wave);
+        const int64_t waves = ((p.m + 15) / 16 + t.rows_per_wave - 1) / t.rows_per_wave;
+        const int64_t wgs = (waves + t.waves_per_wg - 1) / t.waves_per_wg;
+        p.grid = std::max<int64_t>(1, std::min<int64_t>(wgs, cus * t.wg_per_cu));
+        break;
+    }
+    case TSMM_KERNEL_SPLITK: {
+        const int MT = pow2_tiles(p.m), NT = pow2_tiles(p.n);
+        if (!splitk_variant_exists(MT, NT, t.rows_per_wave))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no split-k kernel for MT=%d NT=%d RG=%d", MT, NT,
+                        t.rows_per_wave);
+        p.KC = MT;
+        p.NT = NT;
+        p.grid = t.splitk;
+        p.grid_y = ((p.m + 16 * MT - 1) / (16 * MT)) * ((p.n + 16 * NT - 1) / (16 * NT));
+        p.workspace_bytes = (size_t)t.splitk * (size_t)p.m * (size_t)p.n * sizeof(double);
+        break;
+    }
+    default:
+        t.kernel = TSMM_KERNEL_SIMPLE;
+        p.grid = std::max<int64_t>(1, (p.m * p.n + 255) / 256);
+        p.block = 256;
+        break;
+    }
+    p.tile = t;
+    return TSMM_SUCCESS;
+}
+
+tsmm_status choose_tile(tsmm_plan_s &p) {
+    const int nat = natural_kernel(p);
+    Table &tab = table();
+    p.tile_from_table = false;
+    if (tab.loaded) {
+        TableKey key{};
+        key.layout = p.layout;
+        key.dtype = p.dtype;
+        key.mode = p.mode;
+        if (p.layout == TSMM_OP_N) {
+            key.kc = nat == TSMM_KERNEL_SPLITBF16 ? kclass32(p.k) : kclass4(p.k);
+            key.nt = ntclass(p.n);
+            key.mclass = mclass_of(p.m);
+        } else {
+            key.kc = pow2_tiles(p.m);
+            key.nt = pow2_tiles(p.n);
+            key.mclass = mclass_of(p.k);
+        }
+        auto it = tab.entries.find(key);
+        if (it != tab.entries.end() && it->second.kernel == nat) {
+            tsmm_plan_s trial = p;
+            if (apply_tile(trial, it->second) == TSMM_SUCCESS) {
+                p = trial;
+                p.tile_from_table = true;
+                return TSMM_SUCCESS;
+            }
+            if (log_level() >= 1)
+                fprintf(stderr, "[tsmm] table entry rejected (%s); using the default tile\n", g_err.c_str());
+        }
+    } else if (getenv("TSMM_STRICT_TABLE")) {
+        return fail(TSMM_ERROR_TABLE, "tile table: %s", tab.error.c_str());
+    } else if (log_level() >= 2) {
+        fprintf(stderr, "[tsmm] tile table not used: %s\n", tab.error.c_str());
+    }
+    tsmm_tile t{};
+    t.kernel = nat;
+    return apply_tile(p, t);
+}
+
+tsmm_status make_plan(int64_t m, int64_t n, int64_t k, tsmm_layout layout, tsmm_dtype dtype,
+                      const tsmm_device_caps *caps, int device, tsmm_plan_t *out) {
+    std::unique_ptr<tsmm_plan_s> p(new (std::nothrow) tsmm_plan_s());
+    if (!p) return fail(TSMM_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    p->m = m;
+    p->n = n;
+    p->k = k;
+    p->layout = layout;
+    p->dtype = dtype;
+    p->mode = TSMM_MODE_NATIVE;
+    p->caps = *caps;
+    p->device = device;
+    tsmm_status st = choose_tile(*p);
+    if (st != TSMM_SUCCESS) return st;
+    if (log_level() >= 1) {
+        char buf[256];
+        tsmm_plan_describe(p.get(), buf, sizeof buf);
+        fprintf(stderr, "[tsmm] plan %s\n", buf);
+    }
+    *out = p.release();
+    return TSMM_SUCCESS;
+}
+
+tsmm_status check_plan_args(int64_t m, int64_t n, int64_t k, int layout, int dtype, const void *out) {
+    if (!out) return fail(TSMM_ERROR_INVALID_VALUE, "out is NULL");
+    if (m < 0 || n < 0 || k < 0) return fail(TSMM_ERROR_INVALID_VALUE, "negative size");
+    if (!valid_layout(layout)) return fail(TSMM_ERROR_INVALID_VALUE, "bad layout %d", layout);
+    if (!valid_dtype(dtype)) return fail(TSMM_ERROR_INVALID_VALUE, "bad dtype %d", dtype);
+    if (m > (INT64_C(1) << 40) || n > (INT64_C(1) << 30) || k > (INT64_C(1) << 40))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "size beyond the library's index range");
+    if (layout == TSMM_OP_N && (n > INT32_MAX || k > INT32_MAX))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "op N needs n, k < 2^31");
+    if (layout == TSMM_OP_T && (m > INT32_MAX || n > INT32_MAX))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "op T needs m, n < 2^31");
+    return TSMM_SUCCESS;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char *tsmm_status_string(tsmm_status s) {
+    switch (s) {
+    case TSMM_SUCCESS: return "success";
+    case TSMM_ERROR_INVALID_VALUE: return "invalid value";
+    case TSMM_ERROR_SHAPE_MISMATCH: return "plan and packed operand do not match";
+    case TSMM_ERROR_NOT_SUPPORTED: return "not supported";
+    case TSMM_ERROR_TABLE: return "tile table error";
+    case TSMM_ERROR_OUT_OF_MEMORY: return "out of memory";
+    case TSMM_ERROR_NO_DEVICE: return "no usable device";
+    case TSMM_ERROR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *tsmm_last_error(void) { return g_err.c_str(); }
+
+int32_t tsmm_version(void) { return 10000; }
+
+// ------------------------------------------------------------------ pack
+
+tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, tsmm_dtype dtype,
+                      tsmm_mode mode, void *stream, tsmm_packed_t *out) {
+    g_err.clear();
+    if (!out) return fail(TSMM_ERROR_INVALID_VALUE, "out is NULL");
+    *out = nullptr;
+    if (k < 0 || n < 0) return fail(TSMM_ERROR_INVALID_VALUE, "negative size");
+    if (!valid_layout(layout)) return fail(TSMM_ERROR_INVALID_VALUE, "bad layout %d", (int)layout);
+    if (!valid_dtype(dtype)) return fail(TSMM_ERROR_INVALID_VALUE, "bad dtype %d", (int)dtype);
+    if (!valid_mode(mode)) return fail(TSMM_ERROR_INVALID_VALUE, "bad mode %d", (int)mode);
+    if (mode != TSMM_MODE_NATIVE && (dtype != TSMM_F32 || layout != TSMM_OP_N))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes take op N binary32 operands");
+    if (k * n > 0 && !B) return fail(TSMM_ERROR_INVALID_VALUE, "B is NULL");
+    if (k > INT32_MAX || n > INT32_MAX) return fail(TSMM_ERROR_NOT_SUPPORTED, "k, n must be < 2^31");
+    const int terms = split_terms(dtype, mode);
+    if (mode != TSMM_MODE_NATIVE && (!kclass32(k) || !ntclass(n)))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes need k <= %d and n <= 256", kMaxKC);
+
+    std::unique_ptr<tsmm_packed_s> P(new (std::nothrow) tsmm_packed_s());
+    if (!P) return fail(TSMM_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    P->k = k;
+    P->n = n;
+    P->layout = layout;
+    P->dtype = dtype;
+    P->mode = mode;
+    if (layout == TSMM_OP_T || k == 0 || n == 0) {  // nothing to copy
+        P->ref = B;
+        *out = P.release();
+        return TSMM_SUCCESS;
+    }
+    PackedLayout &L = P->L;
+    const size_t eb = elem_bytes(dtype);
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    L.off_rowmajor = off;
+    off = align(off + (size_t)k * n * eb);
+    if (terms > 0) {  // bf16 fragments (split planes or plain bf16)
+        L.KC = kclass32(k);
+        L.NT = ntclass(n);
+        L.terms = terms;
+        if (L.KC && L.NT) {
+            L.off_frag = off;
+            off = align(off + (size_t)L.KC * L.NT * 16 * terms * 2);
+        }
+        if (mode != TSMM_MODE_NATIVE) {
+            L.off_planes = off;
+            off = align(off + (size_t)terms * k * n * 2);
+            L.off_exps = off;
+            off = align(off + (size_t)n * 4);
+        }
+    } else {
+        L.KC = kclass4(k);
+        L.NT = ntclass(n);
+        if (L.KC && L.NT) {
+            L.vec = vec_mapping(dtype, k, L.KC);
+            L.off_frag = off;
+            off = align(off + (size_t)L.KC * L.NT * 16 * eb);
+        }
+    }
+    L.bytes = off;
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(TSMM_ERROR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+    P->device = dev;
+    e = hipMalloc(&P->dev, L.bytes);
+    if (e != hipSuccess) return fail(TSMM_ERROR_OUT_OF_MEMORY, "hipMalloc(%zu): %s", L.bytes, hipGetErrorString(e));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(P->dev);
+    e = hipMemcpyAsync(base + L.off_rowmajor, B, (size_t)k * n * eb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && L.KC && L.NT) {
+        if (terms > 0)
+            e = launch_pack_bf16(dtype, B, base + L.off_frag,
+                                 mode != TSMM_MODE_NATIVE ? base + L.off_planes : nullptr,
+                                 mode != TSMM_MODE_NATIVE ? reinterpret_cast<int32_t *>(base + L.off_exps) : nullptr,
+                                 k, n, L.KC, L.NT, terms, s);
+        else
+            e = launch_pack_frag4(dtype, B, base + L.off_frag, k, n, L.KC, L.NT, L.vec, s);
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(P->dev);
+        return hip_fail(e, "pack");
+    }
+    *out = P.release();
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_packed_bytes(tsmm_packed_t p, size_t *bytes) {
+    g_err.clear();
+    if (!p || !bytes) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
+    *bytes = p->dev ? p->L.bytes : 0;
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_unpack(tsmm_packed_t p, void *B_out, void *stream) {
+    g_err.clear();
+    if (!p) return fail(TSMM_ERROR_INVALID_VALUE, "packed is NULL");
+    if (p->layout == TSMM_OP_T) return fail(TSMM_ERROR_NOT_SUPPORTED, "op T handles hold no copy of B");
+    if (p->k * p->n == 0) return TSMM_SUCCESS;
+    if (!B_out) return fail(TSMM_ERROR_INVALID_VALUE, "B_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const char *base = static_cast<const char *>(p->dev);
+    hipError_t e;
+    if (p->mode != TSMM_MODE_NATIVE)
+        e = launch_unpack_split(base + p->L.off_planes, reinterpret_cast<const int32_t *>(base + p->L.off_exps),
+                                B_out, p->k, p->n, p->L.terms, s);
+    else
+        e = hipMemcpyAsync(B_out, base + p->L.off_rowmajor, (size_t)p->k * p->n * elem_bytes(p->dtype),
+                           hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "unpack");
+}
+
+tsmm_status tsmm_packed_split_planes(tsmm_packed_t p, void *planes_out, void *exps_out, void *stream) {
+    g_err.clear();
+    if (!p) return fail(TSMM_ERROR_INVALID_VALUE, "packed is NULL");
+    if (p->mode == TSMM_MODE_NATIVE) return fail(TSMM_ERROR_NOT_SUPPORTED, "not a split-mode handle");
+    if (p->k * p->n == 0) return TSMM_SUCCESS;
+    if (!planes_out || !exps_out) return fail(TSMM_ERROR_INVALID_VALUE, "NULL output");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const char *base = static_cast<const char *>(p->dev);
+    hipError_t e = hipMemcpyAsync(planes_out, base + p->L.off_planes, (size_t)p->L.terms * p->k * p->n * 2,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(exps_out, base + p->L.off_exps, (size_t)p->n * 4, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "split planes");
+}
+
+void tsmm_packed_destroy(tsmm_packed_t p) {
+    if (!p) return;
+    if (p->dev) (void)hipFree(p->dev);
+    delete p;
+}
+
+// ------------------------------------------------------------------ plan
+
+tsmm_status tsmm_plan(int64_t m, int64_t n, int64_t k, tsmm_layout layout, tsmm_dtype dtype,
+                      tsmm_plan_t *out) {
+    g_err.clear();
+    tsmm_status st = check_plan_args(m, n, k, layout, dtype, out);
+    if (st != TSMM_SUCCESS) return st;
+    *out = nullptr;
+    tsmm_device_caps caps;
+    int dev = 0;
+    st = query_caps(&caps, &dev);
+    if (st != TSMM_SUCCESS) return st;
+    return make_plan(m, n, k, layout, dtype, &caps, dev, out);
+}
+
+tsmm_status tsmm_plan_with_caps(int64_t m, int64_t n, int64_t k, tsmm_layout layout, tsmm_dtype dtype,
+                                const tsmm_device_caps *caps, tsmm_plan_t *out) {
+    g_err.clear();
+    tsmm_status st = check_plan_args(m, n, k, layout, dtype, out);
+    if (st != TSMM_SUCCESS) return st;
+    *out = nullptr;
+    if (!caps || caps->compute_units < 1 || caps->lds_bytes_per_cu < 1)
+        return fail(TSMM_ERROR_INVALID_VALUE, "bad device caps");
+    return make_plan(m, n, k, layout, dtype, caps, -1, out);
+}
+
+tsmm_status tsmm_plan_set_mode(tsmm_plan_t p, tsmm_mode mode) {
+    g_err.clear();
+    if (!p) return fail(TSMM_ERROR_INVALID_VALUE, "plan is NULL");
+    if (!valid_mode(mode)) return fail(TSMM_ERROR_INVALID_VALUE, "bad mode %d", (int)mode);
+    if (p->batched) return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans run NATIVE only");
+    if (mode != TSMM_MODE_NATIVE && (p->dtype != TSMM_F32 || p->layout != TSMM_OP_N))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes take op N binary32 operands");
+    if (mode != TSMM_MODE_NATIVE && (!kclass32(p->k) || !ntclass(p->n)))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes need k <= %d and n <= 256", kMaxKC);
+    tsmm_plan_s trial = *p;
+    trial.mode = mode;
+    trial.workspace = nullptr;
+    trial.owns_workspace = false;
+    tsmm_status st = choose_tile(trial);
+    if (st != TSMM_SUCCESS) return st;
+    p->mode = mode;
+    p->tile = trial.tile;
+    p->tile_from_table = trial.tile_from_table;
+    p->KC = trial.KC;
+    p->NT = trial.NT;
+    p->vec = trial.vec;
+    p->grid = trial.grid;
+    p->grid_y = trial.grid_y;
+    p->block = trial.block;
+    p->workspace_bytes = trial.workspace_bytes;
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_plan_set_tile(tsmm_plan_t p, const tsmm_tile *tile) {
+    g_err.clear();
+    if (!p || !tile) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
+    if (p->batched) return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take tiles at planning time");
+    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_SPLITBF16)
+        return fail(TSMM_ERROR_INVALID_VALUE, "bad kernel id %d", tile->kernel);
+    tsmm_plan_s trial = *p;
+    trial.workspace = nullptr;
+    trial.owns_workspace = false;
+    tsmm_status st = apply_tile(trial, *tile);
+    if (st != TSMM_SUCCESS) return st;
+    const size_t old_ws = p->workspace_bytes;
+    p->tile = trial.tile;
+    p->tile_from_table = false;
+    p->KC = trial.KC;
+    p->NT = trial.NT;
+    p->vec = trial.vec;
+    p->grid = trial.grid;
+    p->grid_y = trial.grid_y;
+    p->block = trial.block;
+    p->workspace_bytes = trial.workspace_bytes;
+    if (p->workspace_bytes > old_ws && p->owns_workspace) {  // grow lazily on next execute
+        (void)hipFree(p->workspace);
+        p->workspace = nullptr;
+        p->workspace_size = 0;
+        p->owns_workspace = false;
+    }
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_plan_get_tile(tsmm_plan_t p, tsmm_tile *tile) {
+    g_err.clear();
+    if (!p || !tile) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
+    *tile = p->tile;
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_plan_set_stream(tsmm_plan_t p, void *stream) {
+    g_err.clear();
+    if (!p) return fail(TSMM_ERROR_INVALID_VALUE, "plan is NULL");
+    p->stream = static_cast<hipStream_t>(stream);
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_plan_workspace_bytes(tsmm_plan_t p, size_t *bytes) {
+    g_err.clear();
+    if (!p || !bytes) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
+    *bytes = p->workspace_bytes;
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_plan_set_workspace(tsmm_plan_t p, void *ws, size_t bytes) {
+    g_err.clear();
+    if (!p) return fail(TSMM_ERROR_INVALID_VALUE, "plan is NULL");
+    if (ws && bytes < p->workspace_bytes)
+        return fail(TSMM_ERROR_INVALID_VALUE, "workspace of %zu bytes, the plan needs %zu", bytes, p->workspace_bytes);
+    if (p->owns_workspace && p->workspace) (void)hipFree(p->workspace);
+    p->workspace = ws;
+    p->workspace_size = ws ? bytes : 0;
+    p->owns_workspace = false;
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_plan_describe(tsmm_plan_t p, char *buf, size_t len) {
+    g_err.clear();
+    if (!p || !buf || len == 0) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
+    snprintf(buf, len,
+             "op=%c dtype=%s mode=%s m=%" PRId64 " n=%" PRId64 " k=%" PRId64
+             " kernel=%s kc=%d nt=%d vec=%d rt=%d waves=%d wg_per_cu=%d splitk=%d grid=%" PRId64 "x%" PRId64
+             " block=%d workspace=%zu table=%d",
+             p->layout == TSMM_OP_N ? 'N' : 'T', dtype_name(p->dtype), mode_name(p->mode), p->m, p->n, p->k,
+             kernel_name(p->tile.kernel), p->KC, p->NT, (int)p->vec, p->tile.rows_per_wave, p->tile.waves_per_wg,
+             p->tile.wg_per_cu, p->tile.splitk, p->grid, p->grid_y, p->block, p->workspace_bytes,
+             (int)p->tile_from_table);
+    return TSMM_SUCCESS;
+}
+
+void tsmm_plan_destroy(tsmm_plan_t p) {
+    if (!p) return;
+    if (p->owns_workspace && p->workspace) (void)hipFree(p->workspace);
+    if (p->d_desc) (void)hipFree(p->d_desc);
+    if (p->d_inst_start) (void)hipFree(p->d_inst_start);
+    if (p->d_wg_begin) (void)hipFree(p->d_wg_begin);
+    if (p->d_wg_inst) (void)hipFree(p->d_wg_inst);
+    if (p->h_desc) (void)hipHostFree(p->h_desc);
+    delete p;
+}
+
+// --------------------------------------------------------------- execute
+
+tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, void *C, double alpha,
+                         double beta) {
+    g_err.clear();
+    if (!p || !packed) return fail(TSMM_ERROR_INVALID_VALUE, "NULL plan or packed operand");
+    if (p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan: use tsmm_execute_batched");
+    if (p->device < 0) return fail(TSMM_ERROR_NO_DEVICE, "plan was built for explicit caps, not a device");
+    if (packed->k != p->k || packed->n != p->n || packed->dtype != p->dtype || packed->layout != p->layout ||
+        packed->mode != p->mode)
+        return fail(TSMM_ERROR_SHAPE_MISMATCH,
+                    "plan (k=%" PRId64 " n=%" PRId64 " %s %s) vs packed (k=%" PRId64 " n=%" PRId64 " %s %s)", p->k,
+                    p->n, dtype_name(p->dtype), mode_name(p->mode), packed->k, packed->n,
+                    dtype_name(packed->dtype), mode_name(packed->mode));
+    if (p->m == 0 || p->n == 0) return TSMM_SUCCESS;
+    if (!C) return fail(TSMM_ERROR_INVALID_VALUE, "C is NULL");
+    if (alpha != 0.0 && p->k > 0 && !A) return fail(TSMM_ERROR_INVALID_VALUE, "A is NULL");
+    const tsmm_dtype out_dt = p->dtype == TSMM_F64 ? TSMM_F64 : TSMM_F32;
+    hipStream_t s = p->stream;
+    hipError_t e;
+    if (alpha == 0.0 || p->k == 0) {
+        e = launch_scale(out_dt, C, p->m * p->n, beta, s);
+        return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "scale launch");
+    }
+    const char *base = static_cast<const char *>(packed->dev);
+    const void *Brow = p->layout == TSMM_OP_N ? base + packed->L.off_rowmajor : nullptr;
+    int kernel = p->tile.kernel;
+    if (kernel == TSMM_KERNEL_STREAM && p->vec && (reinterpret_cast<uintptr_t>(A) & 15))
+        kernel = TSMM_KERNEL_SIMPLE;  // vector loads need 16-byte aligned rows
+    switch (kernel) {
+    case TSMM_KERNEL_STREAM:
+        e = launch_stream(p->dtype, p->KC, p->NT, p->tile.rows_per_wave, p->vec, A, base + packed->L.off_frag, C,
+                          p->m, p->n, p->k, alpha, beta, p->grid, p->block, s);
+        break;
+    case TSMM_KERNEL_SPLITBF16:
+        if (reinterpret_cast<uintptr_t>(A) & 15) {
+            if (p->mode != TSMM_MODE_NATIVE)
+                return fail(TSMM_ERROR_INVALID_VALUE, "split-bf16 modes need a 16-byte aligned A");
+            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
+            break;
+        }
+        e = launch_splitbf16(p->dtype, p->KC, p->NT, p->tile.rows_per_wave, split_products(p->dtype, p->mode), A,
+                             base + packed->L.off_frag,
+                             p->mode != TSMM_MODE_NATIVE ? reinterpret_cast<const int32_t *>(base + packed->L.off_exps)
+                                                         : nullptr,
+                             C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, s);
+        break;
+    case TSMM_KERNEL_SPLITK: {
+        if (!p->workspace) {
+            void *ws = nullptr;
+            e = hipMalloc(&ws, p->workspace_bytes);
+            if (e != hipSuccess)
+                return fail(TSMM_ERROR_OUT_OF_MEMORY, "split-k workspace (%zu bytes): %s", p->workspace_bytes,
+                            hipGetErrorString(e));
+            p->workspace = ws;
+            p->workspace_size = p->workspace_bytes;
+            p->owns_workspace = true;
+        }
+        e = launch_splitk(p->KC, p->NT, p->tile.rows_per_wave, static_cast<const double *>(A),
+                          static_cast<const double *>(packed->ref), static_cast<double *>(p->workspace),
+                          static_cast<double *>(C), p->k, p->m, p->n, p->tile.splitk, alpha, beta, p->block, s);
+        break;
+    }
+    default:
+        if (p->layout == TSMM_OP_T)
+            e = launch_simple_t(p->dtype, A, packed->ref, C, p->m, p->n, p->k, alpha, beta, s);
+        else
+            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
+        break;
+    }
+    return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "kernel launch");
+}
+
+// --------------------------------------------------------------- batched
+
+tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n, const int64_t *k,
+                              tsmm_dtype dtype, tsmm_plan_t *out) {
+    g_err.clear();
+    if (!out) return fail(TSMM_ERROR_INVALID_VALUE, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > (1 << 24)) return fail(TSMM_ERROR_INVALID_VALUE, "count must be in 1..2^24");
+    if (!m || !n || !k) return fail(TSMM_ERROR_INVALID_VALUE, "NULL shape array");
+    if (dtype != TSMM_F32 && dtype != TSMM_BF16)
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take TSMM_F32 or TSMM_BF16");
+    for (int64_t b = 0; b < count; ++b) {
+        if (m[b] < 0 || m[b] > (INT64_C(1) << 40))
+            return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": bad m", b);
+        if (k[b] < 1 || k[b] > 128 || n[b] < 1 || n[b] > 128)
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "instance %" PRId64 ": batched k and n must be in 1..128", b);
+    }
+    tsmm_device_caps caps;
+    int dev = 0;
+    tsmm_status st = query_caps(&caps, &dev);
+    if (st != TSMM_SUCCESS) return st;
+
+    std::unique_ptr<tsmm_plan_s> p(new (std::nothrow) tsmm_plan_s());
+    if (!p) return fail(TSMM_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    p->batched = true;
+    p->dtype = dtype;
+    p->layout = TSMM_OP_N;
+    p->caps = caps;
+    p->device = dev;
+    p->inst.resize(count);
+    const int sa = elem_bytes(dtype);
+    std::vector<double> cost(count);
+    for (int64_t b = 0; b < count; ++b) {
+        p->inst[b] = {m[b], n[b], k[b]};
+        // bytes of one row (A row + C row) plus a per-tile latency term
+        cost[b] = (double)m[b] * (double)(k[b] * sa + n[b] * 4);
+    }
+    p->order.resize(count);
+    for (int64_t b = 0; b < count; ++b) p->order[b] = b;
+    std::stable_sort(p->order.begin(), p->order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+
+    // work-tile prefix counts in execution order
+    std::vector<int64_t> inst_start(count + 1, 0);
+    std::vector<double> tile_cost(count);
+    for (int64_t e = 0; e < count; ++e) {
+        const BatchedInstance &I = p->inst[p->order[e]];
+        const int64_t tiles = (I.m + kBatchRows - 1) / kBatchRows;
+        inst_start[e + 1] = inst_start[e] + tiles;
+        tile_cost[e] = (double)kBatchRows * (double)(I.k * sa + I.n * 4) + 2048.0;
+    }
+    p->n_work = inst_start[count];
+    const int waves = 4;
+    p->tile = tsmm_tile{TSMM_KERNEL_STREAM, 1, waves, 4, 1, 1};
+    p->block = 64 * waves;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)caps.compute_units * p->tile.wg_per_cu,
+                                                                (p->n_work + waves - 1) / waves));
+    p->grid = grid;
+
+    // contiguous cost-balanced partition of the work-tile sequence: workgroup
+    // w starts at the first tile whose preceding cost reaches w/grid of the
+    // total (tiles of one instance all cost the same)
+    double total = 0.0;
+    for (int64_t e = 0; e < count; ++e) total += tile_cost[e] * (double)(inst_start[e + 1] - inst_start[e]);
+    std::vector<int64_t> wg_begin(grid + 1, p->n_work);
+    std::vector<int32_t> wg_inst(grid, (int32_t)(count - 1));
+    {
+        wg_begin[0] = 0;
+        int64_t w = 1;
+        double cum = 0.0;
+        for (int64_t e = 0; e < count && w < grid; ++e) {
+            const int64_t nt = inst_start[e + 1] - inst_start[e];
+            const double c = tile_cost[e];
+            while (w < grid && cum + (double)nt * c >= total * (double)w / (double)grid) {
+                const double need = total * (double)w / (double)grid - cum;
+                int64_t step = (int64_t)std::ceil(need / c);
+                step = std::max<int64_t>(0, std::min<int64_t>(nt, step));
+                wg_begin[w] = std::max(wg_begin[w - 1], inst_start[e] + step);
+                ++w;
+            }
+            cum += (double)nt * c;
+        }
+        wg_begin[grid] = p->n_work;
+        int64_t inst = 0;
+        for (int64_t w2 = 0; w2 < grid; ++w2) {
+            while (inst + 1 < count && wg_begin[w2] >= inst_start[inst + 1]) ++inst;
+            wg_inst[w2] = (int32_t)inst;
+        }
+    }
+
+    hipError_t e1 = hipMalloc(&p->d_desc, sizeof(BatchDesc) * count);
+    hipError_t e2 = hipMalloc(&p->d_inst_start, sizeof(int64_t) * (count + 1));
+    hipError_t e3 = hipMalloc(&p->d_wg_begin, sizeof(int64_t) * (grid + 1));
+    hipError_t e4 = hipMalloc(&p->d_wg_inst, sizeof(int32_t) * grid);
+    hipError_t e5 = hipHostMalloc(&p->h_desc, sizeof(BatchDesc) * count, hipHostMallocDefault);
+    if (e1 || e2 || e3 || e4 || e5) {
+        tsmm_plan_destroy(p.release());
+        return fail(TSMM_ERROR_OUT_OF_MEMORY, "batched plan allocation failed");
+    }
+    hipError_t e = hipMemcpy(p->d_inst_start, inst_start.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_wg_begin, wg_begin.data(), sizeof(int64_t) * (grid + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_wg_inst, wg_inst.data(), sizeof(int32_t) * grid, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        tsmm_plan_destroy(p.release());
+        return hip_fail(e, "batched plan upload");
+    }
+    p->m = 0;
+    for (const BatchedInstance &I : p->inst) p->m += I.m;
+    if (log_level() >= 1)
+        fprintf(stderr, "[tsmm] batched plan: %" PRId64 " instances, %" PRId64 " work tiles, grid %" PRId64 "\n",
+                count, p->n_work, grid);
+    *out = p.release();
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_batched_bind(tsmm_plan_t p, const void *const *A, const tsmm_packed_t *packed, void *const *C,
+                              const double *alpha, const double *beta) {
+    g_err.clear();
+    if (!p || !p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "not a batched plan");
+    if (!A || !packed || !C) return fail(TSMM_ERROR_INVALID_VALUE, "NULL operand array");
+    const int64_t count = (int64_t)p->inst.size();
+    std::vector<BatchDesc> desc(count);
+    for (int64_t e = 0; e < count; ++e) {
+        const int64_t b = p->order[e];
+        const BatchedInstance &I = p->inst[b];
+        const tsmm_packed_s *P = packed[b];
+        if (!P) return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": packed is NULL", b);
+        if (P->k != I.k || P->n != I.n || P->dtype != p->dtype || P->layout != TSMM_OP_N ||
+            P->mode != TSMM_MODE_NATIVE || !P->dev || !P->L.KC || !P->L.NT)
+            return fail(TSMM_ERROR_SHAPE_MISMATCH, "instance %" PRId64 ": packed operand does not match", b);
+        if (I.m > 0 && (!A[b] || !C[b])) return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": NULL A or C", b);
+        const bool vec = p->dtype == TSMM_BF16 ? (I.k % 8 == 0) : P->L.vec;
+        if (vec && (reinterpret_cast<uintptr_t>(A[b]) & 15))
+            return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": A must be 16-byte aligned", b);
+        BatchDesc &d = desc[e];
+        memset(&d, 0, sizeof d);
+        d.A = A[b];
+        d.Bfrag = static_cast<const char *>(P->dev) + P->L.off_frag;
+        d.C = C[b];
+        d.alpha = alpha ? alpha[b] : 1.0;
+        d.beta = beta ? beta[b] : 0.0;
+        d.m = (d.alpha == 0.0) ? 0 : I.m;  // alpha == 0 handled below
+        d.k = (int32_t)I.k;
+        d.n = (int32_t)I.n;
+        d.KC = P->L.KC;
+        d.NT = P->L.NT;
+        d.vec = vec ? 1 : 0;
+        if (d.alpha == 0.0 && I.m > 0)
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "instance %" PRId64 ": alpha == 0 in a batched plan", b);
+    }
+    if (p->bound && desc.size() == p->bound_desc.size() &&
+        memcmp(desc.data(), p->bound_desc.data(), sizeof(BatchDesc) * count) == 0)
+        return TSMM_SUCCESS;
+    // stage through pinned memory: the copy is stream-ordered (and capturable);
+    // wait for any copy still reading the staging buffer first
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "batched bind");
+    memcpy(p->h_desc, desc.data(), sizeof(BatchDesc) * count);
+    e = hipMemcpyAsync(p->d_desc, p->h_desc, sizeof(BatchDesc) * count, hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "batched bind");
+    p->bound_desc.swap(desc);
+    p->bound = true;
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_execute_batched(tsmm_plan_t p, const void *const *A, const tsmm_packed_t *packed, void *const *C,
+                                 const double *alpha, const double *beta) {
+    g_err.clear();
+    if (!p || !p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "not a batched plan");
+    if (A) {
+        tsmm_status st = tsmm_batched_bind(p, A, packed, C, alpha, beta);
+        if (st != TSMM_SUCCESS) return st;
+    }
+    if (!p->bound) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan has no bound operands");
+    if (p->n_work == 0) return TSMM_SUCCESS;
+    hipError_t e = launch_batched(p->dtype, static_cast<const BatchDesc *>(p->d_desc),
+                                  static_cast<const int64_t *>(p->d_inst_start),
+                                  static_cast<const int64_t *>(p->d_wg_begin),
+                                  static_cast<const int32_t *>(p->d_wg_inst), p->grid, p->block, p->stream);
+    return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "batched launch");
+}
+
+tsmm_status tsmm_graph_create_batched(tsmm_plan_t p, tsmm_graph_t *out) {
+    g_err.clear();
+    if (!out) return fail(TSMM_ERROR_INVALID_VALUE, "out is NULL");
+    *out = nullptr;
+    if (!p || !p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "not a batched plan");
+    if (!p->bound) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan has no bound operands");
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "graph stream");
+    // the descriptor upload must have landed before the graph's reads
+    e = hipStreamSynchronize(p->stream);
+    std::unique_ptr<tsmm_graph_s> g(new (std::nothrow) tsmm_graph_s());
+    if (e == hipSuccess && g) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_batched(p->dtype, static_cast<const BatchDesc *>(p->d_desc),
+                                       static_cast<const int64_t *>(p->d_inst_start),
+                                       static_cast<const int64_t *>(p->d_wg_begin),
+                                       static_cast<const int32_t *>(p->d_wg_inst), p->grid, p->block, cs);
+        e = hipStreamEndCapture(cs, &g->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || !g) {
+        if (g && g->graph) (void)hipGraphDestroy(g->graph);
+        return g ? hip_fail(e, "graph capture") : fail(TSMM_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    *out = g.release();
+    return TSMM_SUCCESS;
+}
+
+tsmm_status tsmm_graph_launch(tsmm_graph_t g, void *stream) {
+    g_err.clear();
+    if (!g || !g->exec) return fail(TSMM_ERROR_INVALID_VALUE, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "graph launch");
+}
+
+void tsmm_graph_destroy(tsmm_graph_t g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libtsmm: packed-operand layout rules, plan structures and kernel
+// launchers.  Not part of the public ABI (include/tsmm.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tsmm.h"
+
+namespace tsmm {
+
+// ---------------------------------------------------------------- layout
+//
+// Matrix-core fragment order of a packed B (op N).
+//
+// The streaming kernels use the 16x16x4 matrix-core products for binary64
+// and binary32 (V_MFMA_F64_16X16X4_F64, V_MFMA_F32_16X16X4_F32).  In one
+// product, lane l = 16*q + j (q = 0..3, j = 0..15) supplies
+//   A-operand element (row j, k-slot q) and B-operand element (k-slot q,
+//   column j),
+// and receives four accumulator rows of column j: rows q + 4*r (binary64)
+// or 4*q + r (binary32), r = 0..3.
+// The k-slot -> column-of-A assignment is free as long as A and B agree,
+// so it is chosen to make every lane's A load one contiguous 16-byte
+// vector: with VW = 16 / sizeof(T) elements per vector, k-step s and slot q
+// read column
+//     col(s, q) = (s / VW) * 4*VW + q*VW + (s % VW)        (vector mapping)
+//     col(s, q) = 4*s + q                                   (scalar mapping)
+// The vector mapping is used when k % VW == 0 and KC % (4*VW) == 0 (rows
+// stay 16-byte aligned and a vector never straddles the end of a row).
+// Packed B holds, for k-step s < KC/4, column tile t < NT and lane l,
+//     frag[(s*NT + t)*64 + l] = B[col(s, q)][16*t + j]   (0 outside k x n).
+//
+// The split-bfloat16 kernels use V_MFMA_F32_16X16X32_BF16: lane 16*q + j
+// supplies 8 consecutive k-slots 8q..8q+7 of a 32-wide k-chunk.  Packed B
+// holds, per chunk c < KC/32, column tile t, plane p and lane l, 8 bfloat16
+//     bfrag[(((c*NT + t)*P + p)*64 + l)*8 + u] = plane p of
+//         B[32c + 8q + u][16t + j] * 2^-e_(16t+j)
+// where e_j is the column's power-of-two exponent (1 <= max|B[:,j]|*2^-e_j
+// < 2) and planes are the residual split hi, mid, lo.
+
+constexpr int kMaxKC = 256;  // largest packed k class of the fragment kernels
+constexpr int kMaxNT = 16;   // largest number of 16-column tiles (n <= 256)
+
+inline int elem_bytes(tsmm_dtype d) { return d == TSMM_F64 ? 8 : (d == TSMM_F32 ? 4 : 2); }
+
+// Smallest k class >= k for the 16x16x4 kernels (0 if k > kMaxKC).
+inline int kclass4(int64_t k) {
+    for (int c = 4; c <= kMaxKC; c *= 2)
+        if (k <= c) return c;
+    return 0;
+}
+// Smallest k class >= k for the bf16 16x16x32 kernels (0 if k > kMaxKC).
+inline int kclass32(int64_t k) {
+    for (int c = 32; c <= kMaxKC; c *= 2)
+        if (k <= c) return c;
+    return 0;
+}
+// Number of 16-column tiles as a power of two class (0 if n > 256).
+inline int ntclass(int64_t n) {
+    for (int c = 1; c <= kMaxNT; c *= 2)
+        if (n <= 16 * c) return c;
+    return 0;
+}
+inline bool vec_mapping(tsmm_dtype d, int64_t k, int KC) {
+    int vw = 16 / elem_bytes(d);
+    return (k % vw) == 0 && (KC % (4 * vw)) == 0;
+}
+
+// ---------------------------------------------------------------- packed
+
+struct PackedLayout {
+    int KC = 0, NT = 0;         // fragment class (0: no fragment copy)
+    bool vec = false;           // vector k-slot mapping (16x16x4 kernels)
+    int terms = 0;              // split planes (0: not a split mode)
+    size_t off_rowmajor = 0;    // k*n elements of the input type
+    size_t off_frag = 0;        // 16x16x4 fragments, or bf16 fragments
+    size_t off_planes = 0;      // split: terms*k*n uint16, row-major
+    size_t off_exps = 0;        // split: n int32
+    size_t bytes = 0;
+};
+
+}  // namespace tsmm
+
+struct tsmm_packed_s {
+    int64_t k = 0, n = 0;
+    tsmm_layout layout = TSMM_OP_N;
+    tsmm_dtype dtype = TSMM_F64;
+    tsmm_mode mode = TSMM_MODE_NATIVE;
+    int device = 0;
+    tsmm::PackedLayout L;
+    void *dev = nullptr;        // one device allocation holding every section
+    const void *ref = nullptr;  // op T: the caller's B (nothing is copied)
+};
+
+namespace tsmm {
+
+// ------------------------------------------------------------------ plan
+
+struct BatchedInstance {  // host copy of one batched instance
+    int64_t m, n, k;
+};
+
+// Device descriptor of one batched instance (bound operands).
+struct alignas(16) BatchDesc {
+    const void *A;
+    const void *Bfrag;  // packed fragments of B
+    void *C;
+    double alpha, beta;
+    int64_t m;
+    int32_t k, n;
+    int32_t KC, NT;
+    int32_t vec, pad;
+};
+
+// Rows of one batched work tile (a wavefront processes it as 16-row tiles).
+constexpr int kBatchRows = 64;
+
+}  // namespace tsmm
+
+struct tsmm_plan_s {
+    int64_t m = 0, n = 0, k = 0;
+    tsmm_layout layout = TSMM_OP_N;
+    tsmm_dtype dtype = TSMM_F64;
+    tsmm_mode mode = TSMM_MODE_NATIVE;
+    tsmm_device_caps caps{};
+    int device = 0;
+    tsmm_tile tile{};
+    bool tile_from_table = false;
+    // derived launch geometry
+    int KC = 0, NT = 0;
+    bool vec = false;
+    int64_t grid = 0;
+    int block = 0;
+    int64_t grid_y = 1;
+    size_t workspace_bytes = 0;
+    hipStream_t stream = nullptr;
+    void *workspace = nullptr;
+    size_t workspace_size = 0;
+    bool owns_workspace = false;
+    // batched: instances in execution order (longest first)
+    bool batched = false;
+    std::vector<tsmm::BatchedInstance> inst;  // caller order
+    std::vector<int64_t> order;               // execution position -> caller index
+    int64_t n_work = 0;                       // work tiles over all instances
+    void *d_desc = nullptr;                   // device BatchDesc[count] (execution order)
+    void *h_desc = nullptr;                   // pinned staging BatchDesc[count]
+    void *d_inst_start = nullptr;             // device int64[count + 1]: first work tile
+    void *d_wg_begin = nullptr;               // device int64[grid + 1]: work-tile range
+    void *d_wg_inst = nullptr;                // device int32[grid]: instance of wg_begin
+    bool bound = false;
+    std::vector<tsmm::BatchDesc> bound_desc;
+};
+
+struct tsmm_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace tsmm {
+
+// ------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.  All are asynchronous.
+
+// Pack B (k x n row-major) into the 16x16x4 fragment order.
+hipError_t launch_pack_frag4(tsmm_dtype dt, const void *B, void *frag, int64_t k, int64_t n,
+                             int KC, int NT, bool vec, hipStream_t s);
+// Split-bf16 pack: column exponents, row-major planes and fragments.
+// For TSMM_BF16 inputs (terms == 1) B is bf16 and no scaling is applied.
+hipError_t launch_pack_bf16(tsmm_dtype dt, const void *B, void *frag, void *planes, int32_t *exps,
+                            int64_t k, int64_t n, int KC, int NT, int terms, hipStream_t s);
+// Unpack a split handle: B_out[i][j] = (sum of planes) * 2^e_j (binary32).
+hipError_t launch_unpack_split(const void *planes, const int32_t *exps, void *B_out, int64_t k,
+                               int64_t n, int terms, hipStream_t s);
+
+// C = beta*C (alpha == 0 or k == 0 paths).
+hipError_t launch_scale(tsmm_dtype out_dt, void *C, int64_t count, double beta, hipStream_t s);
+
+// op N, any shape: one thread per output element, reads the row-major B.
+hipError_t launch_simple_n(tsmm_dtype dt, const void *A, const void *B, void *C, int64_t m,
+                           int64_t n, int64_t k, double alpha, double beta, hipStream_t s);
+// op T, any shape: one thread per output element.
+hipError_t launch_simple_t(tsmm_dtype dt, const void *A, const void *B, void *C, int64_t m,
+                           int64_t n, int64_t k, double alpha, double beta, hipStream_t s);
+
+// op N streaming, binary64 / binary32 16x16x4 fragments.
+hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, const void *A,
+                         const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, double alpha,
+                         double beta, int64_t grid, int block, hipStream_t s);
+bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec);
+
+// op N, split-bf16 (terms 2 or 3 of binary32 A and B; products 3 or 6) or
+// plain bf16 inputs (terms == 1).
+hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products, const void *A,
+                            const void *Bfrag, const int32_t *exps, void *C, int64_t m, int64_t n,
+                            int64_t k, double alpha, double beta, int64_t grid, int block,
+                            hipStream_t s);
+bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int products);
+
+// op T, split-k: pass 1 writes P partial m x n sums, pass 2 reduces them in
+// ascending order and applies the epilogue.
+hipError_t launch_splitk(int MT, int NT, int RG, const double *A, const double *B, double *W,
+                         double *C, int64_t K, int64_t m, int64_t n, int P, double alpha,
+                         double beta, int block, hipStream_t s);
+bool splitk_variant_exists(int MT, int NT, int RG);
+
+// Batched persistent launch: workgroup w runs work tiles
+// [wg_begin[w], wg_begin[w+1]) of the instance sequence described by
+// inst_start (prefix counts of work tiles).
+hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *inst_start,
+                          const int64_t *wg_begin, const int32_t *wg_inst, int64_t grid, int block,
+                          hipStream_t s);
+
+}  // namespace tsmm

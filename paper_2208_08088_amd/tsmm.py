@@ -1,0 +1,369 @@
+"""Python binding of libtsmm (include/tsmm.h): argument marshalling only.
+
+Every step of the multiply runs in the library's HIP kernels; this module
+checks tensor devices, types, shapes and contiguity, passes raw device
+pointers and torch's current HIP stream, and turns status codes into
+exceptions.  PyTorch provides device memory and streams.  There is no
+fallback: if ``libtsmm.so`` has not been built, every call raises.
+
+The names follow the C ABI: :func:`pack`, :func:`plan`, :func:`execute`,
+:func:`plan_batched`, ... (AutoTSMM, Algorithm 1: PACKB, the runtime
+execution plan, COMPUTE).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsmm.so")
+
+SUCCESS, INVALID_VALUE, SHAPE_MISMATCH, NOT_SUPPORTED, TABLE, OUT_OF_MEMORY, NO_DEVICE, HIP = range(8)
+F64, F32, BF16 = 0, 1, 2
+OP_N, OP_T = 0, 1
+MODE_NATIVE, MODE_BF16X3, MODE_BF16X6 = 0, 1, 2
+KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_STREAM, KERNEL_SPLITK, KERNEL_SPLITBF16 = range(5)
+
+_MODES = {"native": MODE_NATIVE, "bf16x3": MODE_BF16X3, "bf16x6": MODE_BF16X6}
+_LAYOUTS = {"N": OP_N, "T": OP_T}
+_DT_OF_TORCH = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+_TORCH_OF_DT = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
+_OUT_OF_DT = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
+
+
+class TsmmError(RuntimeError):
+    def __init__(self, status, where, detail):
+        self.status = status
+        super().__init__("%s: %s (%s)" % (where, _lib().tsmm_status_string(status).decode(), detail))
+
+
+class _Tile(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in
+                ("kernel", "rows_per_wave", "waves_per_wg", "wg_per_cu", "splitk", "nsplit")]
+
+
+class _Caps(ctypes.Structure):
+    _fields_ = [("compute_units", ctypes.c_int32), ("lds_bytes_per_cu", ctypes.c_int32),
+                ("gcn_arch", ctypes.c_int32)]
+
+
+_LIB = None
+
+# (name, restype, argtypes) of every exported entry point of include/tsmm.h
+_VP, _I64, _DBL, _I32, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_size_t
+_PVP = ctypes.POINTER(ctypes.c_void_p)
+SIGNATURES = [
+    ("tsmm_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("tsmm_last_error", ctypes.c_char_p, []),
+    ("tsmm_version", _I32, []),
+    ("tsmm_pack", ctypes.c_int, [_VP, _I64, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _PVP]),
+    ("tsmm_packed_bytes", ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
+    ("tsmm_unpack", ctypes.c_int, [_VP, _VP, _VP]),
+    ("tsmm_packed_split_planes", ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    ("tsmm_packed_destroy", None, [_VP]),
+    ("tsmm_plan", ctypes.c_int, [_I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _PVP]),
+    ("tsmm_plan_with_caps", ctypes.c_int, [_I64, _I64, _I64, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(_Caps), _PVP]),
+    ("tsmm_plan_set_mode", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("tsmm_plan_set_tile", ctypes.c_int, [_VP, ctypes.POINTER(_Tile)]),
+    ("tsmm_plan_get_tile", ctypes.c_int, [_VP, ctypes.POINTER(_Tile)]),
+    ("tsmm_plan_set_stream", ctypes.c_int, [_VP, _VP]),
+    ("tsmm_plan_workspace_bytes", ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
+    ("tsmm_plan_set_workspace", ctypes.c_int, [_VP, _VP, _SZ]),
+    ("tsmm_plan_describe", ctypes.c_int, [_VP, ctypes.c_char_p, _SZ]),
+    ("tsmm_plan_destroy", None, [_VP]),
+    ("tsmm_execute", ctypes.c_int, [_VP, _VP, _VP, _VP, _DBL, _DBL]),
+    ("tsmm_plan_batched", ctypes.c_int, [_I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                         ctypes.POINTER(_I64), ctypes.c_int, _PVP]),
+    ("tsmm_batched_bind", ctypes.c_int, [_VP, _PVP, _PVP, _PVP, ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)]),
+    ("tsmm_execute_batched", ctypes.c_int, [_VP, _PVP, _PVP, _PVP, ctypes.POINTER(_DBL),
+                                            ctypes.POINTER(_DBL)]),
+    ("tsmm_graph_create_batched", ctypes.c_int, [_VP, _PVP]),
+    ("tsmm_graph_launch", ctypes.c_int, [_VP, _VP]),
+    ("tsmm_graph_destroy", None, [_VP]),
+]
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtsmm.so is not built (%s): run `python -m paper_2208_08088_amd.build`"
+                               % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(status, where):
+    if status != SUCCESS:
+        raise TsmmError(status, where, _lib().tsmm_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _need_cuda(t, name, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous (row-major)" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def version():
+    return _lib().tsmm_version()
+
+
+# ---------------------------------------------------------------- packed
+
+class Packed:
+    """A packed small operand (tsmm_pack); reusable by any number of executes."""
+
+    def __init__(self, handle, k, n, dtype, layout, mode, keep):
+        self._h = handle
+        self.k, self.n, self.dtype, self.layout, self.mode = k, n, dtype, layout, mode
+        self._keep = keep  # op T handles refer to the caller's B
+
+    @property
+    def handle(self):
+        return self._h
+
+    def nbytes(self):
+        b = ctypes.c_size_t(0)
+        _check(_lib().tsmm_packed_bytes(self._h, ctypes.byref(b)), "tsmm_packed_bytes")
+        return b.value
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            _LIB.tsmm_packed_destroy(h)
+
+
+def pack(B: torch.Tensor, layout: str = "N", mode: str = "native") -> Packed:
+    """Pack B (k x n, row-major, on the device) once for reuse."""
+    if B.dtype not in _DT_OF_TORCH:
+        raise TypeError("B must be float64, float32 or bfloat16")
+    _need_cuda(B, "B")
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
+    k, n = B.shape
+    dt = _DT_OF_TORCH[B.dtype]
+    h = ctypes.c_void_p(0)
+    _check(_lib().tsmm_pack(_ptr(B), k, n, _LAYOUTS[layout], dt, _MODES[mode], _stream(), ctypes.byref(h)),
+           "tsmm_pack")
+    return Packed(h.value, k, n, dt, _LAYOUTS[layout], _MODES[mode], B if layout == "T" else None)
+
+
+def unpack(p: Packed) -> torch.Tensor:
+    out_dt = torch.float32 if p.mode != MODE_NATIVE else _TORCH_OF_DT[p.dtype]
+    out = torch.empty((p.k, p.n), dtype=out_dt, device="cuda")
+    _check(_lib().tsmm_unpack(p.handle, _ptr(out), _stream()), "tsmm_unpack")
+    return out
+
+
+def split_planes(p: Packed):
+    """(planes, exps): uint16 bit patterns [terms, k, n] (as int16 storage)
+    and int32 column exponents [n] of a split-mode handle."""
+    terms = {MODE_BF16X3: 2, MODE_BF16X6: 3}.get(p.mode, 0)
+    planes = torch.empty((terms, p.k, p.n), dtype=torch.int16, device="cuda")
+    exps = torch.empty((p.n,), dtype=torch.int32, device="cuda")
+    _check(_lib().tsmm_packed_split_planes(p.handle, _ptr(planes), _ptr(exps), _stream()),
+           "tsmm_packed_split_planes")
+    return planes, exps
+
+
+# ------------------------------------------------------------------ plan
+
+class Plan:
+    """An execution plan (tsmm_plan) for one shape."""
+
+    def __init__(self, handle, m, n, k, layout, dtype):
+        self._h = handle
+        self.m, self.n, self.k, self.layout, self.dtype = m, n, k, layout, dtype
+        self.mode = MODE_NATIVE
+        self._ws = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_mode(self, mode: str):
+        _check(_lib().tsmm_plan_set_mode(self._h, _MODES[mode]), "tsmm_plan_set_mode")
+        self.mode = _MODES[mode]
+        self._ws = None
+        return self
+
+    def set_tile(self, kernel=0, rows_per_wave=0, waves_per_wg=0, wg_per_cu=0, splitk=0, nsplit=0):
+        t = _Tile(kernel, rows_per_wave, waves_per_wg, wg_per_cu, splitk, nsplit)
+        _check(_lib().tsmm_plan_set_tile(self._h, ctypes.byref(t)), "tsmm_plan_set_tile")
+        self._ws = None
+        return self
+
+    def get_tile(self) -> dict:
+        t = _Tile()
+        _check(_lib().tsmm_plan_get_tile(self._h, ctypes.byref(t)), "tsmm_plan_get_tile")
+        return {f: getattr(t, f) for f, _ in _Tile._fields_}
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t(0)
+        _check(_lib().tsmm_plan_workspace_bytes(self._h, ctypes.byref(b)), "tsmm_plan_workspace_bytes")
+        return b.value
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(_lib().tsmm_plan_describe(self._h, buf, 512), "tsmm_plan_describe")
+        return buf.value.decode()
+
+    def info(self) -> dict:
+        out = {}
+        for kv in self.describe().split():
+            key, _, val = kv.partition("=")
+            out[key] = val
+        return out
+
+    def _ensure_workspace(self):
+        nb = self.workspace_bytes()
+        if nb and (self._ws is None or self._ws.numel() < nb):
+            self._ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            _check(_lib().tsmm_plan_set_workspace(self._h, _ptr(self._ws), nb), "tsmm_plan_set_workspace")
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            _LIB.tsmm_plan_destroy(h)
+
+
+def plan(m: int, n: int, k: int, layout: str = "N", dtype=torch.float64) -> Plan:
+    """Execution plan for C(m x n) = alpha*op(A)*B + beta*C with B k x n."""
+    h = ctypes.c_void_p(0)
+    dt = _DT_OF_TORCH[dtype]
+    _check(_lib().tsmm_plan(m, n, k, _LAYOUTS[layout], dt, ctypes.byref(h)), "tsmm_plan")
+    return Plan(h.value, m, n, k, _LAYOUTS[layout], dt)
+
+
+def plan_with_caps(m, n, k, layout="N", dtype=torch.float64, compute_units=256, lds_bytes_per_cu=163840,
+                   gcn_arch=950) -> Plan:
+    """Plan against explicit device properties (no GPU needed; not executable)."""
+    h = ctypes.c_void_p(0)
+    caps = _Caps(compute_units, lds_bytes_per_cu, gcn_arch)
+    dt = _DT_OF_TORCH[dtype]
+    _check(_lib().tsmm_plan_with_caps(m, n, k, _LAYOUTS[layout], dt, ctypes.byref(caps), ctypes.byref(h)),
+           "tsmm_plan_with_caps")
+    return Plan(h.value, m, n, k, _LAYOUTS[layout], dt)
+
+
+def execute(p: Plan, A: torch.Tensor, packed: Packed, C: torch.Tensor, alpha: float = 1.0,
+            beta: float = 0.0) -> torch.Tensor:
+    """C = alpha*op(A)*B + beta*C in place on torch's current stream."""
+    in_dt = _TORCH_OF_DT[p.dtype]
+    a_shape = (p.m, p.k) if p.layout == OP_N else (p.k, p.m)
+    _need_cuda(A, "A", in_dt, a_shape)
+    _need_cuda(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n))
+    if packed.layout == OP_T and packed._keep is not None:
+        _need_cuda(packed._keep, "B")
+    p._ensure_workspace()
+    lib = _lib()
+    _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
+    _check(lib.tsmm_execute(p.handle, _ptr(A), packed.handle, _ptr(C), float(alpha), float(beta)),
+           "tsmm_execute")
+    return C
+
+
+# --------------------------------------------------------------- batched
+
+class BatchedPlan:
+    """Many independent op N multiplies in one persistent launch."""
+
+    def __init__(self, handle, ms, ns, ks, dtype):
+        self._h = handle
+        self.ms, self.ns, self.ks, self.dtype = list(ms), list(ns), list(ks), dtype
+        self._bound = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _arrays(self, As, packeds, Cs, alphas, betas):
+        cnt = len(self.ms)
+        if not (len(As) == len(packeds) == len(Cs) == cnt):
+            raise ValueError("need %d A, packed and C operands" % cnt)
+        in_dt, out_dt = _TORCH_OF_DT[self.dtype], _OUT_OF_DT[self.dtype]
+        for b in range(cnt):
+            _need_cuda(As[b], "A[%d]" % b, in_dt, (self.ms[b], self.ks[b]))
+            _need_cuda(Cs[b], "C[%d]" % b, out_dt, (self.ms[b], self.ns[b]))
+        VA = ctypes.c_void_p * cnt
+        a = VA(*[t.data_ptr() for t in As])
+        pk = VA(*[p.handle for p in packeds])
+        c = VA(*[t.data_ptr() for t in Cs])
+        DA = ctypes.c_double * cnt
+        al = DA(*([1.0] * cnt if alphas is None else [float(x) for x in alphas]))
+        be = DA(*([0.0] * cnt if betas is None else [float(x) for x in betas]))
+        return a, pk, c, al, be
+
+    def bind(self, As, packeds, Cs, alphas=None, betas=None):
+        a, pk, c, al, be = self._arrays(As, packeds, Cs, alphas, betas)
+        lib = _lib()
+        _check(lib.tsmm_plan_set_stream(self._h, _stream()), "tsmm_plan_set_stream")
+        _check(lib.tsmm_batched_bind(self._h, a, pk, c, al, be), "tsmm_batched_bind")
+        self._bound = (list(As), list(packeds), list(Cs))  # keep operands alive
+        return self
+
+    def execute(self, As=None, packeds=None, Cs=None, alphas=None, betas=None):
+        lib = _lib()
+        _check(lib.tsmm_plan_set_stream(self._h, _stream()), "tsmm_plan_set_stream")
+        if As is not None:
+            self.bind(As, packeds, Cs, alphas, betas)
+        _check(lib.tsmm_execute_batched(self._h, None, None, None, None, None), "tsmm_execute_batched")
+
+    def graph(self) -> "Graph":
+        g = ctypes.c_void_p(0)
+        _check(_lib().tsmm_graph_create_batched(self._h, ctypes.byref(g)), "tsmm_graph_create_batched")
+        return Graph(g.value, self)
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            _LIB.tsmm_plan_destroy(h)
+
+
+def plan_batched(ms, ns, ks, dtype=torch.float32) -> BatchedPlan:
+    cnt = len(ms)
+    IA = ctypes.c_int64 * cnt
+    h = ctypes.c_void_p(0)
+    _check(_lib().tsmm_plan_batched(cnt, IA(*[int(x) for x in ms]), IA(*[int(x) for x in ns]),
+                                    IA(*[int(x) for x in ks]), _DT_OF_TORCH[dtype], ctypes.byref(h)),
+           "tsmm_plan_batched")
+    return BatchedPlan(h.value, ms, ns, ks, _DT_OF_TORCH[dtype])
+
+
+class Graph:
+    """A captured, instantiated batched launch (tsmm_graph_create_batched)."""
+
+    def __init__(self, handle, owner):
+        self._h = handle
+        self._owner = owner  # keeps the plan and its bound operands alive
+
+    def launch(self):
+        _check(_lib().tsmm_graph_launch(self._h, _stream()), "tsmm_graph_launch")
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            _LIB.tsmm_graph_destroy(h)

@@ -1,0 +1,185 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/tsmm.h, validates arguments before
+any HIP call, and derives plans from explicit device properties."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsmm.h")
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2208_08088_amd import tsmm
+    if not os.path.exists(tsmm.LIB_PATH):
+        pytest.skip("libtsmm.so not built")
+    tsmm._lib()
+    return tsmm
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(tsmm_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("tsmm_pack", "tsmm_plan", "tsmm_execute", "tsmm_plan_batched", "tsmm_execute_batched",
+                     "tsmm_graph_create_batched", "tsmm_last_error", "tsmm_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(T):
+    lib = ctypes.CDLL(T.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding wraps every declared entry point with a signature
+    assert sorted(n for n, _, _ in T.SIGNATURES) == declared_functions()
+
+
+def test_status_strings_and_version(T):
+    lib = T._lib()
+    for s in range(8):
+        assert lib.tsmm_status_string(s)
+    assert lib.tsmm_status_string(99) == b"unknown status"
+    assert lib.tsmm_version() == 10000
+
+
+def test_pack_validates_before_touching_hip(T):
+    lib = T._lib()
+    h = ctypes.c_void_p(0)
+    assert lib.tsmm_pack(None, 4, 4, 0, 0, 0, None, None) == T.INVALID_VALUE
+    assert lib.tsmm_pack(None, -1, 4, 0, 0, 0, None, ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_pack(None, 4, 4, 0, 0, 0, None, ctypes.byref(h)) == T.INVALID_VALUE  # NULL B
+    assert b"B is NULL" in lib.tsmm_last_error()
+    assert lib.tsmm_pack(ctypes.c_void_p(16), 4, 4, 7, 0, 0, None, ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_pack(ctypes.c_void_p(16), 4, 4, 0, 9, 0, None, ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_pack(ctypes.c_void_p(16), 4, 4, 0, 0, 5, None, ctypes.byref(h)) == T.INVALID_VALUE
+    # split modes only for binary32 op N, and only within the fragment classes
+    assert lib.tsmm_pack(ctypes.c_void_p(16), 4, 4, 0, T.F64, T.MODE_BF16X6, None, ctypes.byref(h)) == T.NOT_SUPPORTED
+    assert lib.tsmm_pack(ctypes.c_void_p(16), 4, 4, 1, T.F32, T.MODE_BF16X3, None, ctypes.byref(h)) == T.NOT_SUPPORTED
+    assert lib.tsmm_pack(ctypes.c_void_p(16), 300, 4, 0, T.F32, T.MODE_BF16X6, None, ctypes.byref(h)) == T.NOT_SUPPORTED
+    # empty operands need no device: a handle is returned
+    assert lib.tsmm_pack(None, 0, 5, 0, T.F64, 0, None, ctypes.byref(h)) == T.SUCCESS and h.value
+    nb = ctypes.c_size_t(1)
+    assert lib.tsmm_packed_bytes(h, ctypes.byref(nb)) == T.SUCCESS and nb.value == 0
+    lib.tsmm_packed_destroy(h)
+    lib.tsmm_packed_destroy(None)
+    lib.tsmm_plan_destroy(None)
+    lib.tsmm_graph_destroy(None)
+
+
+def test_plan_validation(T):
+    lib = T._lib()
+    h = ctypes.c_void_p(0)
+    caps = T._Caps(256, 163840, 950)
+    assert lib.tsmm_plan_with_caps(-1, 4, 4, 0, 0, ctypes.byref(caps), ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_plan_with_caps(4, 4, 4, 3, 0, ctypes.byref(caps), ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_plan_with_caps(4, 4, 4, 0, 5, ctypes.byref(caps), ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_plan_with_caps(4, 4, 4, 0, 0, None, ctypes.byref(h)) == T.INVALID_VALUE
+    bad = T._Caps(0, 163840, 950)
+    assert lib.tsmm_plan_with_caps(4, 4, 4, 0, 0, ctypes.byref(bad), ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_plan_with_caps(4, 4, 4, 0, 0, ctypes.byref(caps), None) == T.INVALID_VALUE
+    # a caps-only plan cannot execute
+    assert lib.tsmm_plan_with_caps(64, 8, 8, 0, 0, ctypes.byref(caps), ctypes.byref(h)) == T.SUCCESS
+    assert lib.tsmm_execute(h, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1.0, 0.0) in (
+        T.NO_DEVICE, T.SHAPE_MISMATCH)
+    lib.tsmm_plan_destroy(h)
+
+
+def test_plan_geometry_from_caps(T):
+    # op N binary64, k = n = 8, m = 2^23: streaming kernel, k class 8, one
+    # 16-column tile, vector mapping, grid capped at CUs * wg_per_cu
+    p = T.plan_with_caps(1 << 23, 8, 8, "N")
+    info = p.info()
+    assert info["kernel"] == "stream" and info["kc"] == "8" and info["nt"] == "1" and info["vec"] == "1"
+    tile = p.get_tile()
+    grid = int(info["grid"].split("x")[0])
+    assert grid == 256 * tile["wg_per_cu"]
+    # odd k: scalar mapping
+    assert T.plan_with_caps(1000, 16, 7, "N").info()["vec"] == "0"
+    # tiny m: grid shrinks to the work
+    assert int(T.plan_with_caps(16, 16, 16, "N").info()["grid"].split("x")[0]) == 1
+    # beyond the fragment classes: the any-shape kernel
+    assert T.plan_with_caps(100, 300, 16, "N").info()["kernel"] == "simple"
+    assert T.plan_with_caps(100, 16, 1000, "N").info()["kernel"] == "simple"
+
+
+def test_plan_splitk_workspace(T):
+    p = T.plan_with_caps(64, 64, 1 << 22, "T")
+    info = p.info()
+    assert info["kernel"] == "splitk"
+    P = p.get_tile()["splitk"]
+    assert 1 <= P <= 512
+    assert p.workspace_bytes() == P * 64 * 64 * 8
+    p.set_tile(kernel=T.KERNEL_SPLITK, splitk=100)
+    assert p.workspace_bytes() == 100 * 64 * 64 * 8
+    # output blocks: m = 100 > 64 -> two 64-row blocks, n = 20 -> 32-wide block
+    q = T.plan_with_caps(100, 20, 4096, "T")
+    grid = q.info()["grid"].split("x")
+    assert int(grid[1]) == 2
+
+
+def test_set_tile_validation(T):
+    p = T.plan_with_caps(4096, 16, 16, "N")
+    with pytest.raises(T.TsmmError) as e:
+        p.set_tile(kernel=T.KERNEL_SPLITK)
+    assert e.value.status == T.NOT_SUPPORTED
+    with pytest.raises(T.TsmmError) as e:
+        p.set_tile(kernel=T.KERNEL_STREAM, waves_per_wg=3)
+    assert e.value.status == T.INVALID_VALUE
+    with pytest.raises(T.TsmmError):
+        p.set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=8)  # no such instantiation
+    p.set_tile(kernel=T.KERNEL_SIMPLE)
+    assert p.info()["kernel"] == "simple"
+    p.set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=2, wg_per_cu=3)
+    # 4096 rows = 256 tiles of 16 -> 128 wavefronts -> 32 workgroups of 4
+    assert p.get_tile()["rows_per_wave"] == 2 and p.info()["grid"] == "32x1"
+    big = T.plan_with_caps(1 << 22, 16, 16, "N")
+    big.set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=2, wg_per_cu=3)
+    assert big.info()["grid"] == "768x1"
+
+
+def test_set_mode_rules(T):
+    p = T.plan_with_caps(4096, 256, 256, "N", dtype=__import__("torch").float32)
+    p.set_mode("bf16x6")
+    assert p.info()["kernel"] == "splitbf16" and p.info()["mode"] == "bf16x6"
+    q = T.plan_with_caps(4096, 16, 16, "N")
+    with pytest.raises(T.TsmmError) as e:
+        q.set_mode("bf16x3")
+    assert e.value.status == T.NOT_SUPPORTED
+
+
+def test_tile_table_parsing(tmp_path):
+    # a table is read once per process: check it in a child process
+    import subprocess
+    import sys
+    tab = tmp_path / "t.txt"
+    tab.write_text("# comment\nN f64 native 8 1 2 : stream 2 4 6 1 1\nT f64 native 4 4 2 : splitk 4 4 2 300 1\n")
+    code = (
+        "from paper_2208_08088_amd import tsmm as T\n"
+        "p = T.plan_with_caps(1 << 23, 8, 8, 'N'); i = p.info(); t = p.get_tile()\n"
+        "assert i['table'] == '1' and t['rows_per_wave'] == 2 and t['wg_per_cu'] == 6, (i, t)\n"
+        "q = T.plan_with_caps(64, 64, 1 << 22, 'T'); assert q.get_tile()['splitk'] == 300 and q.info()['table'] == '1'\n"
+        "r = T.plan_with_caps(1 << 23, 32, 32, 'N'); assert r.info()['table'] == '0'\n"
+        "print('ok')\n")
+    env = dict(os.environ, TSMM_TILE_TABLE=str(tab))
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True)
+    assert out.returncode == 0 and "ok" in out.stdout, out.stderr
+    bad = tmp_path / "bad.txt"
+    bad.write_text("N f64 native 8 1 2 : nosuchkernel 2 4 6 1 1\n")
+    code2 = ("from paper_2208_08088_amd import tsmm as T\n"
+             "p = T.plan_with_caps(1 << 23, 8, 8, 'N'); assert p.info()['table'] == '0'\n"
+             "print('ok')\n")
+    out = subprocess.run([sys.executable, "-c", code2], cwd=ROOT, env=dict(os.environ, TSMM_TILE_TABLE=str(bad)),
+                         capture_output=True, text=True)
+    assert out.returncode == 0 and "ok" in out.stdout, out.stderr
+    out = subprocess.run([sys.executable, "-c", code2], cwd=ROOT,
+                         env=dict(os.environ, TSMM_TILE_TABLE=str(bad), TSMM_STRICT_TABLE="1"),
+                         capture_output=True, text=True)
+    assert out.returncode != 0 and "tile table" in out.stderr
