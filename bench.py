@@ -134,6 +134,29 @@ def bound_of(bytes_, flops, dt):
     return ("hbm", t_hbm) if t_hbm >= t_cmp else ("mfma", t_cmp)
 
 
+def copy_ceiling(torch, nbytes=4 << 30, reps=10):
+    """Achievable HBM rate of a plain device copy (torch's copy kernel) of
+    the same order of size: read + write bytes over time."""
+    n = nbytes // 8
+    src = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    del src, dst
+    torch.cuda.empty_cache()
+    return dict(kernel="torch copy_", bytes=2 * nbytes, us=ms * 1e3, GB_s=2 * nbytes / ms / 1e6,
+                hbm_frac=2 * nbytes / ms / 1e6 / HBM_PEAK_GBS)
+
+
 def extras_opt(torch, T, I, steps, warmup):
     K, m, n = 1 << 22, 64, 64
     A = I.device_normal((K, m), I.BASE_SEED, 21, torch.float64)
@@ -271,6 +294,8 @@ def main():
     T._lib()  # fail loudly if the HIP library is missing
     torch.cuda.set_device(0)
 
+    ceiling = copy_ceiling(torch)
+    print("[bench] copy ceiling %.0f GB/s" % ceiling["GB_s"], file=sys.stderr, flush=True)
     cases = headline(torch, T, I, args)
     print("[bench] headline cases ready: %s" % ", ".join(c["tag"] for c in cases), file=sys.stderr, flush=True)
     # snapshot sampled C0 rows and check one call of each case (for the CPU leg)
@@ -315,7 +340,8 @@ def main():
                   config=dict(workload="binary64 tall-A x small-B, m=2^23, k=n in {8,32,128}, beta in {0,1}, "
                                        "packed B reused, fresh A per call", m=M_ROWS, k_n=list(KS),
                               betas=list(BETAS), step_bytes=step_bytes),
-                  hbm_frac=value / HBM_PEAK_GBS, roofline=roofline, breakdown=breakdown)
+                  hbm_frac=value / HBM_PEAK_GBS, roofline=roofline, breakdown=breakdown,
+                  copy_ceiling=ceiling)
 
     if not args.no_extras and not args.only:
         opt, keep_t = extras_opt(torch, T, I, args.steps, args.warmup)

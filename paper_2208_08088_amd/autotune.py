@@ -1,0 +1,198 @@
+"""Install-time autotuner: measures candidate tiles per shape class on this
+GPU and writes the tile table that tsmm_plan reads.
+
+    python -m paper_2208_08088_amd.autotune [--out PATH] [--classes ...]
+
+This is the paper's install-time stage together with its performance
+evaluator (AutoTSMM Sec. III; Sec. IV-A.1): for every shape class the
+candidates are generated the two ways the paper describes -- a sweep of
+multiples of the register tile under the capacity bounds (rows per
+wavefront, resident workgroups per compute unit, column groups) and the
+largest power of two that fits -- each candidate is timed on inputs larger
+than the last-level cache, and the fastest one is recorded.  Candidates the
+library rejects (capacity, missing instantiation) are skipped.
+
+The table is plain text, one entry per class (see tsmm_api.cpp), written
+atomically; classes already present are kept unless --retune is given, so
+an interrupted run resumes where it stopped.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import tsmm as T
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tile_table.txt")
+
+_DT_NAME = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}
+_KERNEL_NAME = {T.KERNEL_SIMPLE: "simple", T.KERNEL_STREAM: "stream", T.KERNEL_SPLITK: "splitk",
+                T.KERNEL_SPLITBF16: "splitbf16"}
+
+
+def mclass_of(m):
+    return 0 if m < (1 << 16) else (1 if m < (1 << 21) else 2)
+
+
+# name: (layout, dtype, mode, m, n, k) -- representative shapes of the classes
+CLASSES = {
+    "n_f64_k8": ("N", torch.float64, "native", 1 << 23, 8, 8),
+    "n_f64_k16": ("N", torch.float64, "native", 1 << 23, 16, 16),
+    "n_f64_k32": ("N", torch.float64, "native", 1 << 23, 32, 32),
+    "n_f64_k64": ("N", torch.float64, "native", 1 << 23, 64, 64),
+    "n_f64_k128": ("N", torch.float64, "native", 1 << 23, 128, 128),
+    "n_f64_k256": ("N", torch.float64, "native", 1 << 24, 256, 256),
+    "n_f32_k256": ("N", torch.float32, "native", 1 << 24, 256, 256),
+    "n_f32x6_k256": ("N", torch.float32, "bf16x6", 1 << 24, 256, 256),
+    "n_f32x3_k256": ("N", torch.float32, "bf16x3", 1 << 24, 256, 256),
+    "t_f64_64x64": ("T", torch.float64, "native", 64, 64, 1 << 22),
+}
+HEADLINE = ["n_f64_k8", "n_f64_k32", "n_f64_k128", "t_f64_64x64"]
+
+
+def candidates(p):
+    """Candidate tiles for plan p (the default tile first)."""
+    base = p.get_tile()
+    kern = base["kernel"]
+    out = [dict(base)]
+    if kern == T.KERNEL_STREAM:
+        for ns in sorted({base["nsplit"], base["nsplit"] * 2}):
+            for rt in (1, 2, 4, 8):
+                for wpc in (1, 2, 4, 8, 16):
+                    out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=wpc, splitk=1, nsplit=ns))
+    elif kern == T.KERNEL_SPLITBF16:
+        for ns in sorted({base["nsplit"], base["nsplit"] * 2}):
+            for rt in (1, 2):
+                for wpc in (1, 2, 4, 8):
+                    out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=wpc, splitk=1, nsplit=ns))
+    elif kern == T.KERNEL_SPLITK:
+        for rg in (1, 2, 4):
+            for P in (256, 512, 1024, 2048):
+                out.append(dict(kernel=kern, rows_per_wave=rg, waves_per_wg=4, wg_per_cu=1, splitk=P, nsplit=1))
+    seen, uniq = set(), []
+    for c in out:
+        key = tuple(sorted(c.items()))
+        if key not in seen:
+            seen.add(key)
+            uniq.append(c)
+    return uniq
+
+
+def time_plan(p, As, pk, C, beta, reps):
+    """Median milliseconds of one execute (HIP events on the current stream)."""
+    T.execute(p, As[0], pk, C, 1.0, beta)  # warm-up
+    times = []
+    for r in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        T.execute(p, As[(r + 1) % len(As)], pk, C, 1.0, beta)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times))
+
+
+def tune_class(name, spec, reps, log):
+    layout, dt, mode, m, n, k = spec
+    if layout == "N":
+        if mode == "native":
+            As = [I.device_uniform((m, k), I.BASE_SEED, 900 + r, dt) for r in range(2)]
+            B = I.device_uniform((k, n), I.BASE_SEED, 910, dt)
+        else:
+            As = [I.device_col_scaled_uniform(m, k, I.BASE_SEED, 900 + r, dt) for r in range(2)]
+            B = I.device_uniform((k, n), I.BASE_SEED, 910, dt)
+        pk = T.pack(B, "N", mode)
+        C = torch.zeros((m, n), dtype=dt if dt != torch.bfloat16 else torch.float32, device="cuda")
+    else:
+        As = [I.device_normal((k, m), I.BASE_SEED, 920 + r, dt) for r in range(2)]
+        B = I.device_normal((k, n), I.BASE_SEED, 930, dt)
+        pk = T.pack(B, "T")
+        C = torch.zeros((m, n), dtype=dt, device="cuda")
+    p = T.plan(m, n, k, layout, dt)
+    if mode != "native":
+        p.set_mode(mode)
+    info = p.info()
+    best = None
+    for cand in candidates(p):
+        try:
+            p.set_tile(**cand)
+        except T.TsmmError:
+            continue
+        ms = time_plan(p, As, pk, C, 0.0, reps)
+        log("  %-14s %s  %.3f ms" % (name, " ".join("%s=%d" % kv for kv in sorted(cand.items())), ms))
+        if best is None or ms < best[0]:
+            best = (ms, p.get_tile())
+    key_kc = info["kc"]
+    key_nt = info["nt"]
+    mcl = mclass_of(k if layout == "T" else m)
+    entry = "%s %s %s %s %s %d : %s %d %d %d %d %d" % (
+        layout, _DT_NAME[dt], mode, key_kc, key_nt, mcl, _KERNEL_NAME[best[1]["kernel"]],
+        best[1]["rows_per_wave"], best[1]["waves_per_wg"], best[1]["wg_per_cu"], best[1]["splitk"],
+        best[1]["nsplit"])
+    del As, B, C, pk
+    torch.cuda.empty_cache()
+    return entry, best[0]
+
+
+def read_table(path):
+    entries = {}
+    if os.path.exists(path):
+        for line in open(path):
+            body = line.split("#")[0].strip()
+            if body:
+                key = " ".join(body.split(":")[0].split())
+                entries[key] = line.rstrip("\n")
+    return entries
+
+
+def write_table(path, entries, header):
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        f.write(header)
+        for key in sorted(entries):
+            f.write(entries[key] + "\n")
+    os.replace(tmp, path)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="tile-table autotuner")
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--classes", nargs="*", default=None, help="class names (default: all)")
+    ap.add_argument("--headline", action="store_true", help="only the headline classes")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--retune", action="store_true")
+    a = ap.parse_args(argv)
+    names = a.classes or (HEADLINE if a.headline else list(CLASSES))
+    T._lib()
+    props = torch.cuda.get_device_properties(0)
+    header = ("# tile table written by paper_2208_08088_amd.autotune\n"
+              "# device: %s (%s, %d CUs); hip %s; libtsmm %d; %s\n"
+              "# layout dtype mode kc nt mclass : kernel rows_per_wave waves_per_wg wg_per_cu splitk nsplit\n"
+              % (props.name, getattr(props, "gcnArchName", "?"), props.multi_processor_count,
+                 torch.version.hip, T.version(), time.strftime("%Y-%m-%d")))
+    entries = read_table(a.out)
+    log = lambda s: print(s, flush=True)
+    for name in names:
+        spec = CLASSES[name]
+        log("[autotune] class %s" % name)
+        entry, ms = tune_class(name, spec, a.reps, log)
+        key = " ".join(entry.split(":")[0].split())
+        if key in entries and not a.retune:
+            log("[autotune] %s already in the table; kept (use --retune)" % key)
+            continue
+        entries[key] = entry + "  # %.3f ms at %s" % (ms, "x".join(str(v) for v in spec[3:]))
+        write_table(a.out, entries, header)
+        log("[autotune] %s -> %s (%.3f ms)" % (name, entry, ms))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

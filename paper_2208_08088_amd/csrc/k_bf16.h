@@ -76,36 +76,97 @@ __device__ __forceinline__ void split8(const float (&x)[8], u16x8 (&t)[TERMS]) {
     }
 }
 
-// PROD: 1 (plain bf16), 3 (two terms) or 6 (three terms).
+template <bool F32IN, int RT, int NCH> struct RawA;
+template <int RT, int NCH> struct RawA<true, RT, NCH> {
+    float v[RT][NCH][8];
+};
+template <int RT, int NCH> struct RawA<false, RT, NCH> {
+    u16x8 v[RT][NCH];
+};
+
+// PROD: 1 (plain bf16), 3 (two terms) or 6 (three terms).  NT: column tiles
+// per workgroup (one column group of the nt_total tiles when nsplit > 1,
+// with the workgroup -> (row block, group) map of k_stream.h).
 template <typename TA, int KC, int NT, int RT, int PROD, bool VEC>
 __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__ A,
                                                           const uint16_t *__restrict__ Bf,
                                                           const int32_t *__restrict__ exps,
                                                           float *__restrict__ C, int64_t m, int n, int k,
-                                                          double alpha, double beta) {
+                                                          double alpha, double beta, int nt_total, int nsplit) {
     constexpr int TERMS = PROD == 1 ? 1 : (PROD == 3 ? 2 : 3);
     constexpr int NCH = KC / 32;
-    constexpr int FRAG = NCH * NT * TERMS * 64 * 8;  // bf16 elements
-    constexpr bool BLDS = FRAG * 2 <= kBf16LdsBudget;
+    constexpr int FRAGV = NCH * NT * TERMS * 64;  // 16-byte vectors per workgroup
+    constexpr bool BLDS = FRAGV * 16 <= kBf16LdsBudget;
     constexpr bool TWO_ACC = PROD > 1;
+    constexpr bool F32IN = PROD > 1;
 
-    __shared__ u16x8 sB[BLDS ? FRAG / 8 : 1];
+    int group = 0;
+    int64_t rb = blockIdx.x, nrb = gridDim.x;
+    if (nsplit > 1) {
+        const int64_t slot = blockIdx.x >> 3;
+        group = (int)(slot % nsplit);
+        rb = (slot / nsplit) * 8 + (blockIdx.x & 7);
+        nrb = gridDim.x / nsplit;
+    }
+    const int col0 = group * NT * 16;
+
+    __shared__ u16x8 sB[BLDS ? FRAGV : 1];
+    const u16x8 *__restrict__ Bg = reinterpret_cast<const u16x8 *>(Bf);
     if constexpr (BLDS) {
-        const u16x8 *src = reinterpret_cast<const u16x8 *>(Bf);
-        for (int idx = threadIdx.x; idx < FRAG / 8; idx += blockDim.x) sB[idx] = src[idx];
+        for (int idx = threadIdx.x; idx < FRAGV; idx += blockDim.x) {
+            const int c = idx / (NT * TERMS * 64), rem = idx % (NT * TERMS * 64);
+            sB[idx] = Bg[(c * nt_total + group * NT) * TERMS * 64 + rem];
+        }
         __syncthreads();
     }
-    const u16x8 *__restrict__ Bsrc = BLDS ? sB : reinterpret_cast<const u16x8 *>(Bf);
 
     const int lane = threadIdx.x & 63;
     const int j = lane & 15;
     const int q = lane >> 4;
     const int64_t ntile = (m + 15) >> 4;
     const int wpb = blockDim.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-    const int64_t tstride = (int64_t)gridDim.x * wpb * RT;
+    const int64_t gw = rb * wpb + (threadIdx.x >> 6);
+    const int64_t tstride = nrb * wpb * RT;
 
-    for (int64_t t0 = gw * RT; t0 < ntile; t0 += tstride) {
+    // raw A of a row step: binary32 values (split modes) or bf16 vectors
+    typedef RawA<F32IN, RT, NCH> raw_t;
+    auto load_step = [&](int64_t t, raw_t &x) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t row = (t + rt) * 16 + j;
+            const bool rok = row < m;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int col = 32 * c + 8 * q;
+                if constexpr (F32IN)
+                    load_a8<float, VEC>(reinterpret_cast<const float *>(A) + row * (int64_t)k, col, k, rok, x.v[rt][c]);
+                else
+                    x.v[rt][c] = load_a8_bf16<VEC>(reinterpret_cast<const uint16_t *>(A) + row * (int64_t)k, col, k, rok);
+            }
+        }
+    };
+
+    raw_t x_cur, x_nxt;
+    int64_t t0 = gw * RT;
+    if (t0 < ntile) load_step(t0, x_cur);
+
+    for (; t0 < ntile; t0 += tstride) {
+        float cv[RT][NT][4];
+        if (beta != 0.0) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = (t0 + rt) * 16 + 4 * q + r;
+                        const int col = col0 + 16 * t + j;
+                        cv[rt][t][r] = (row < m && col < n) ? __builtin_nontemporal_load(C + row * n + col) : 0.0f;
+                    }
+        }
+        const int64_t t1 = t0 + tstride;
+        if (t1 < ntile) load_step(t1, x_nxt);
+
         f4v acc[RT][NT];
         f4v acc2[TWO_ACC ? RT : 1][TWO_ACC ? NT : 1];
 #pragma unroll
@@ -116,30 +177,25 @@ __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__
                 if constexpr (TWO_ACC) acc2[rt][t] = f4v{};
             }
 
+        // small B may live in registers; larger B is re-read per row step
         int bofs = 0;
-        asm volatile("" : "+v"(bofs));  // B is re-read per row tile, not hoisted
+        if constexpr (NCH * NT * TERMS > 8) asm volatile("" : "+v"(bofs));
 
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             u16x8 at[RT][TERMS];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                const int64_t row = (t0 + rt) * 16 + j;
-                const bool rok = row < m;
-                const int col = 32 * c + 8 * q;
-                if constexpr (PROD == 1) {
-                    at[rt][0] = load_a8_bf16<VEC>(reinterpret_cast<const uint16_t *>(A) + row * (int64_t)k, col, k, rok);
-                } else {
-                    float x[8];
-                    load_a8<float, VEC>(reinterpret_cast<const float *>(A) + row * (int64_t)k, col, k, rok, x);
-                    split8<TERMS>(x, at[rt]);
-                }
+                if constexpr (F32IN) split8<TERMS>(x_cur.v[rt][c], at[rt]);
+                else at[rt][0] = x_cur.v[rt][c];
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 u16x8 bt[TERMS];
 #pragma unroll
-                for (int p = 0; p < TERMS; ++p) bt[p] = Bsrc[bofs + ((c * NT + t) * TERMS + p) * 64 + lane];
+                for (int p = 0; p < TERMS; ++p)
+                    bt[p] = BLDS ? sB[bofs + ((c * NT + t) * TERMS + p) * 64 + lane]
+                                 : Bg[bofs + ((c * nt_total + group * NT + t) * TERMS + p) * 64 + lane];
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
                     acc[rt][t] = mfma_bf16(at[rt][0], bt[0], acc[rt][t]);
@@ -158,18 +214,8 @@ __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__
 
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int col = 16 * t + j;
+            const int col = col0 + 16 * t + j;
             const int e = (PROD > 1 && col < n) ? exps[col] : 0;
-            float cv[RT][4];
-            if (beta != 0.0) {
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t row = (t0 + rt) * 16 + 4 * q + r;
-                        cv[rt][r] = (row < m && col < n) ? C[row * n + col] : 0.0f;
-                    }
-            }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -179,25 +225,27 @@ __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__
                         double s = (double)acc[rt][t][r];
                         if constexpr (TWO_ACC) s = s + (double)acc2[rt][t][r];
                         if (PROD > 1) s = __builtin_ldexp(s, e);
-                        const double c = beta != 0.0 ? (double)cv[rt][r] : 0.0;
-                        C[row * n + col] = (float)epilogue(alpha, s, beta, c);
+                        const double cc = beta != 0.0 ? (double)cv[rt][t][r] : 0.0;
+                        __builtin_nontemporal_store((float)epilogue(alpha, s, beta, cc), C + row * n + col);
                     }
                 }
         }
+        x_cur = x_nxt;
     }
 }
 
 template <typename TA, int KC, int NT, int RT, int PROD, bool VEC>
 hipError_t run_splitbf16(const void *A, const void *Bf, const int32_t *exps, void *C, int64_t m, int64_t n,
-                         int64_t k, double alpha, double beta, int64_t grid, int block, hipStream_t s) {
+                         int64_t k, double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
+                         hipStream_t s) {
     hipLaunchKernelGGL((k_splitbf16<TA, KC, NT, RT, PROD, VEC>), dim3((unsigned)grid), dim3(block), 0, s,
                        static_cast<const TA *>(A), static_cast<const uint16_t *>(Bf), exps, static_cast<float *>(C),
-                       m, (int)n, (int)k, alpha, beta);
+                       m, (int)n, (int)k, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
 }
 
 typedef hipError_t (*Bf16Fn)(const void *, const void *, const int32_t *, void *, int64_t, int64_t, int64_t,
-                             double, double, int64_t, int, hipStream_t);
+                             double, double, int64_t, int, int, int, hipStream_t);
 struct Bf16Entry {
     int KC, NT, RT, prod, vec;
     Bf16Fn fn;

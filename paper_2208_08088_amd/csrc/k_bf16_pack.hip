@@ -108,12 +108,12 @@ bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int product
 
 hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products, const void *A, const void *Bfrag,
                             const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k, double alpha, double beta,
-                            int64_t grid, int block, hipStream_t s) {
+                            int64_t grid, int block, int nt_total, int nsplit, hipStream_t s) {
     const int vw = dt == TSMM_BF16 ? 8 : 4;  // elements per 16-byte vector
     const bool vec = (k % vw) == 0;
     Bf16Fn fn = find_bf16(dt, KC, NT, vec ? RT : 1, products, vec);
-    if (!fn) return hipErrorInvalidValue;
-    return fn(A, Bfrag, exps, C, m, n, k, alpha, beta, grid, block, s);
+    if (!fn || nsplit < 1 || NT * nsplit != nt_total) return hipErrorInvalidValue;
+    return fn(A, Bfrag, exps, C, m, n, k, alpha, beta, grid, block, nt_total, nsplit, s);
 }
 
 }  // namespace tsmm

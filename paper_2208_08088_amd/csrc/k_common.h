@@ -62,6 +62,50 @@ __device__ __forceinline__ uint16_t float_to_bf16_bits(float x) {
     return (uint16_t)(u >> 16);
 }
 
+// Raw buffer access (the hardware clamps every access against the byte
+// count of the resource: out-of-range loads return 0, out-of-range stores
+// are dropped).  The range check covers the per-lane offset only, so every
+// offset that must be checked goes into `voff`; `aux` 2 marks the access
+// non-temporal (streamed once).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// A value that is the same in every lane, moved to scalar registers (the
+// compiler cannot always prove it, and a buffer resource must be scalar).
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, int64_t bytes) {
+    const int64_t b = bytes < 0 ? 0 : (bytes > (int64_t)0xFFFFFFFF ? (int64_t)0xFFFFFFFF : bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)(uint32_t)b, 0x00020000);
+}
+
+template <typename T> struct BufIO;
+template <> struct BufIO<double> {
+    static __device__ __forceinline__ d2v load_vec(__amdgpu_buffer_rsrc_t r, int voff) {
+        return __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 2));
+    }
+    static __device__ __forceinline__ double load1(__amdgpu_buffer_rsrc_t r, int voff) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 2));
+    }
+    static __device__ __forceinline__ void store1(double v, __amdgpu_buffer_rsrc_t r, int voff) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, 0, 2);
+    }
+};
+template <> struct BufIO<float> {
+    static __device__ __forceinline__ f4v load_vec(__amdgpu_buffer_rsrc_t r, int voff) {
+        return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 2));
+    }
+    static __device__ __forceinline__ float load1(__amdgpu_buffer_rsrc_t r, int voff) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 2));
+    }
+    static __device__ __forceinline__ void store1(float v, __amdgpu_buffer_rsrc_t r, int voff) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0, 2);
+    }
+};
+
 template <typename T> __device__ __forceinline__ double to_f64(T x) { return (double)x; }
 template <typename T> __device__ __forceinline__ T from_f64(double x) { return (T)x; }
 

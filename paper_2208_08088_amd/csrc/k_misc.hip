@@ -151,10 +151,10 @@ bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec) {
 
 hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, const void *A,
                          const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, double alpha,
-                         double beta, int64_t grid, int block, hipStream_t s) {
+                         double beta, int64_t grid, int block, int nt_total, int nsplit, hipStream_t s) {
     StreamFn fn = find_stream(dt, KC, NT, RT, vec);
-    if (!fn) return hipErrorInvalidValue;
-    return fn(A, Bfrag, C, m, n, k, alpha, beta, grid, block, s);
+    if (!fn || nsplit < 1 || NT * nsplit != nt_total) return hipErrorInvalidValue;
+    return fn(A, Bfrag, C, m, n, k, alpha, beta, grid, block, nt_total, nsplit, s);
 }
 
 }  // namespace tsmm

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kSplitBlock) void k_splitk_pass1(const double *__re
     const int nbn = (n + BN - 1) / BN;
     const int m0 = (blockIdx.y / nbn) * BM, n0 = (blockIdx.y % nbn) * BN;
     const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
-    const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwave = blockDim.x >> 6;
     const int64_t r0 = (int64_t)p * rows_per_split;
     const int64_t r1 = r0 + rows_per_split < K ? r0 + rows_per_split : K;
 
@@ -46,27 +46,46 @@ __global__ __launch_bounds__(kSplitBlock) void k_splitk_pass1(const double *__re
 #pragma unroll
     for (int b = 0; b < NT; ++b) bcol[b] = n0 + 16 * b + j < n;
 
-    // wavefront w takes the 4*RG-row groups w, w + nwave, w + 2*nwave, ...
-    for (int64_t g = r0 + (int64_t)wave * 4 * RG; g < r1; g += (int64_t)nwave * 4 * RG) {
-        double av[RG][MT], bv[RG][NT];
+    // Wavefront w takes the 4*RG-row groups w, w + nwave, w + 2*nwave, ...
+    // of its range.  Software pipeline: the next group's rows are in flight
+    // while the current group's products run.  Rows are read through
+    // buffer resources whose byte count ends at row r1, so rows past the
+    // range read 0.
+    const int64_t gstride = (int64_t)nwave * 4 * RG;
+    auto load = [&](int64_t g, double (&av)[RG][MT], double (&bv)[RG][NT]) {
+        const int64_t rr = uniform64(r0 + g);  // first row of the group
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + rr * m + m0, ((r1 - rr) * m - m0) * 8);
+        const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + rr * n + n0, ((r1 - rr) * n - n0) * 8);
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) {
-            const int64_t row = g + 4 * rg + q;
-            const bool ok = row < r1;
-            const double *arow = A + row * m + m0 + j;
-            const double *brow = B + row * n + n0 + j;
+            const int row = 4 * rg + q;
 #pragma unroll
-            for (int a = 0; a < MT; ++a) av[rg][a] = (ok && acol[a]) ? __builtin_nontemporal_load(arow + 16 * a) : 0.0;
+            for (int a = 0; a < MT; ++a)
+                av[rg][a] = acol[a] ? BufIO<double>::load1(ra, (row * m + 16 * a + j) * 8) : 0.0;
 #pragma unroll
-            for (int b = 0; b < NT; ++b) bv[rg][b] = (ok && bcol[b]) ? __builtin_nontemporal_load(brow + 16 * b) : 0.0;
+            for (int b = 0; b < NT; ++b)
+                bv[rg][b] = bcol[b] ? BufIO<double>::load1(rb, (row * n + 16 * b + j) * 8) : 0.0;
         }
+    };
+    double a_cur[RG][MT], b_cur[RG][NT], a_nxt[RG][MT], b_nxt[RG][NT];
+    int64_t g = (int64_t)__builtin_amdgcn_readfirstlane(wave) * 4 * RG;
+    if (r0 + g < r1) load(g, a_cur, b_cur);
+    for (; r0 + g < r1; g += gstride) {
+        if (r0 + g + gstride < r1) load(g + gstride, a_nxt, b_nxt);
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
             for (int a = 0; a < MT; ++a)
 #pragma unroll
                 for (int b = 0; b < NT; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rg][a], bv[rg][b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rg][a], b_cur[rg][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+            for (int a = 0; a < MT; ++a) a_cur[rg][a] = a_nxt[rg][a];
+#pragma unroll
+            for (int b = 0; b < NT; ++b) b_cur[rg][b] = b_nxt[rg][b];
+        }
     }
 
     // combine the wavefronts in the fixed order ((w0 + w1) + w2) + ...
@@ -90,15 +109,32 @@ __global__ __launch_bounds__(kSplitBlock) void k_splitk_pass1(const double *__re
     }
 }
 
-__global__ void k_splitk_pass2(const double *__restrict__ W, double *__restrict__ C, int64_t mn,
-                               int P, double alpha, double beta) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= mn) return;
-    double s = W[e];
-#pragma unroll 16
-    for (int p = 1; p < P; ++p) s = s + W[(int64_t)p * mn + e];
-    const double c = beta != 0.0 ? C[e] : 0.0;
-    C[e] = epilogue(alpha, s, beta, c);
+// Pass 2: 16 outputs per workgroup; thread (seg, o) sums the partials of
+// segment seg (P split into 16 contiguous segments) in ascending order,
+// then the 16 segment sums are added in ascending order.  The summation
+// tree depends only on P, so a plan's result is bitwise repeatable.
+constexpr int kP2Out = 16, kP2Seg = 16;
+__global__ __launch_bounds__(kP2Out *kP2Seg) void k_splitk_pass2(const double *__restrict__ W, double *__restrict__ C,
+                                                                 int64_t mn, int P, double alpha, double beta) {
+    __shared__ double part[kP2Seg][kP2Out];
+    const int o = threadIdx.x % kP2Out, seg = threadIdx.x / kP2Out;
+    const int64_t e = (int64_t)blockIdx.x * kP2Out + o;
+    const int per = (P + kP2Seg - 1) / kP2Seg;
+    const int p0 = seg * per, p1 = p0 + per < P ? p0 + per : P;
+    double s = 0.0;
+    if (e < mn && p0 < p1) {
+        s = W[(int64_t)p0 * mn + e];
+#pragma unroll 8
+        for (int p = p0 + 1; p < p1; ++p) s = s + W[(int64_t)p * mn + e];
+    }
+    part[seg][o] = s;
+    __syncthreads();
+    if (seg == 0 && e < mn) {
+        double t = part[0][o];
+        for (int g = 1; g < kP2Seg; ++g) t = t + part[g][o];
+        const double c = beta != 0.0 ? C[e] : 0.0;
+        C[e] = epilogue(alpha, t, beta, c);
+    }
 }
 
 typedef void (*SplitFn)(const double *, const double *, double *, int64_t, int, int, int64_t);
@@ -134,7 +170,7 @@ hipError_t launch_splitk(int MT, int NT, int RG, const double *A, const double *
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t mn = m * n;
-    hipLaunchKernelGGL(k_splitk_pass2, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_splitk_pass2, dim3((unsigned)((mn + kP2Out - 1) / kP2Out)), dim3(kP2Out * kP2Seg), 0, s,
                        (const double *)W, C, mn, P, alpha, beta);
     return hipGetLastError();
 }

@@ -25,11 +25,68 @@ namespace tsmm {
 constexpr int kStreamBlock = 256;
 constexpr int kStreamLdsBudget = 128 * 1024;
 
+// Workgroup -> (row block, column group).  With nsplit column groups, the
+// nsplit workgroups that share a row block get ids 8 apart, so they land on
+// the same XCD (ids are dealt to the 8 XCDs round robin) at about the same
+// time, and the second read of their A rows hits that XCD's L2.
+struct BlockMap {
+    int group;     // column group of this workgroup
+    int64_t rb;    // row-block index among the gridDim.x / nsplit row blocks
+    int64_t nrb;   // number of row blocks
+};
+__device__ __forceinline__ BlockMap block_map(int nsplit) {
+    BlockMap b;
+    if (nsplit == 1) {
+        b.group = 0;
+        b.rb = blockIdx.x;
+        b.nrb = gridDim.x;
+    } else {
+        const int64_t slot = blockIdx.x >> 3;
+        b.group = (int)(slot % nsplit);
+        b.rb = (slot / nsplit) * 8 + (blockIdx.x & 7);
+        b.nrb = gridDim.x / nsplit;
+    }
+    return b;
+}
+
+// A rows of row tiles t .. t+RT-1 into registers: one buffer resource per
+// 16-row tile (its byte count ends at row m, so rows beyond m read 0);
+// kmask bit p (or s) says whether this lane's columns are inside k.
+template <typename T, int KC, int RT, bool VEC>
+__device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m, int k, int64_t t, int voffA,
+                                              uint32_t kmask, T (&a)[RT][KC / 4]) {
+    typedef typename Mfma4<T>::vec vec_t;
+    constexpr int VW = Mfma4<T>::VW;
+    constexpr int S = KC / 4;
+    constexpr int SZ = (int)sizeof(T);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t row0 = uniform64((t + rt) * 16);
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, (m - row0) * (int64_t)k * SZ);
+        if constexpr (VEC) {
+#pragma unroll
+            for (int p = 0; p < S / VW; ++p) {
+                vec_t v = {};
+                if (kmask & (1u << p)) v = BufIO<T>::load_vec(ra, voffA + p * 4 * VW * SZ);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) a[rt][p * VW + e] = v[e];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) a[rt][s] = (kmask & (1u << s)) ? BufIO<T>::load1(ra, voffA + 4 * s * SZ) : T(0);
+        }
+    }
+}
+
+// KC: packed k class; NT: 16-column tiles per workgroup (all of n, or one
+// column group of it); RT: 16-row tiles per wavefront step; VEC: vector
+// k-slot mapping.  nt_total is the number of column tiles of the packed B.
 template <typename T, int KC, int NT, int RT, bool VEC>
 __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A,
                                                           const T *__restrict__ Bf,
                                                           T *__restrict__ C, int64_t m, int n,
-                                                          int k, double alpha, double beta) {
+                                                          int k, double alpha, double beta,
+                                                          int nt_total, int nsplit) {
     typedef Mfma4<T> M;
     typedef typename M::acc acc_t;
     typedef typename M::vec vec_t;
@@ -39,50 +96,80 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A
     constexpr bool BLDS = FRAG * (int)sizeof(T) <= kStreamLdsBudget;
     static_assert(!VEC || (KC % (4 * VW)) == 0, "vector mapping needs KC % (4*VW) == 0");
 
+    const BlockMap bm = block_map(nsplit);
+    const int col0 = bm.group * NT * 16;
+
     __shared__ T sB[BLDS ? FRAG : 1];
     if constexpr (BLDS) {
-        for (int idx = threadIdx.x * VW; idx < FRAG; idx += blockDim.x * VW)
-            *reinterpret_cast<vec_t *>(&sB[idx]) = *reinterpret_cast<const vec_t *>(&Bf[idx]);
+        // this workgroup's column tiles of every k-step
+        for (int idx = threadIdx.x * VW; idx < FRAG; idx += blockDim.x * VW) {
+            const int s = idx / (NT * 64), rem = idx % (NT * 64);
+            *reinterpret_cast<vec_t *>(&sB[idx]) =
+                *reinterpret_cast<const vec_t *>(&Bf[(s * nt_total + bm.group * NT) * 64 + rem]);
+        }
         __syncthreads();
     }
-    const T *__restrict__ Bsrc = BLDS ? sB : Bf;
 
     const int lane = threadIdx.x & 63;
     const int j = lane & 15;
     const int q = lane >> 4;
     const int64_t ntile = (m + 15) >> 4;
     const int wpb = blockDim.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-    const int64_t tstride = (int64_t)gridDim.x * wpb * RT;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t gw = bm.rb * wpb + wave;
+    const int64_t tstride = bm.nrb * wpb * RT;
+    constexpr int SZ = (int)sizeof(T);
 
-    for (int64_t t0 = gw * RT; t0 < ntile; t0 += tstride) {
-        T a[RT][S];
+    // Per-lane byte offsets, fixed for the whole kernel.  Rows are addressed
+    // through one buffer resource per 16-row tile whose byte count ends at
+    // the last row of the matrix, so rows beyond m read 0 and are not
+    // written; columns beyond k (ragged k) and beyond n are masked here.
+    const int voffA = VEC ? (j * k + q * VW) * SZ : (j * k + q) * SZ;
+    int voffC[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) voffC[r] = (M::row(q, r) * n + j) * SZ;
+    const bool kfull = k == KC;
+    uint32_t kmask = 0;  // bit s (or p): this lane's A column is inside k
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int col = VEC ? (s / VW) * 4 * VW + q * VW : 4 * s + q;
+        if (kfull || col < k) kmask |= 1u << (VEC ? s / VW : s);
+    }
+    uint32_t nmask = 0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        if (col0 + 16 * t + j < n) nmask |= 1u << t;
+
+    // Software pipeline: the A rows of the next step are in flight while
+    // this step's products and epilogue run; this step's C rows (beta != 0)
+    // are requested before the next A rows, so waiting for them does not
+    // wait for the prefetch.
+    T a_cur[RT][S], a_nxt[RT][S];
+    int64_t t0 = gw * RT;
+    if (t0 < ntile) stream_load_a<T, KC, RT, VEC>(A, m, k, t0, voffA, kmask, a_cur);
+    for (; t0 < ntile; t0 += tstride) {
+        __amdgpu_buffer_rsrc_t rc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-            const int64_t row = (t0 + rt) * 16 + j;
-            const bool rok = row < m;
-            const T *arow = A + row * (int64_t)k;
-            if constexpr (VEC) {
-#pragma unroll
-                for (int p = 0; p < S / VW; ++p) {
-                    const int col = p * 4 * VW + q * VW;
-                    vec_t v = {};
-                    if (rok && col < k) v = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(arow + col));
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) a[rt][p * VW + e] = v[e];
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    const int col = 4 * s + q;
-                    a[rt][s] = (rok && col < k) ? arow[col] : T(0);
-                }
-            }
+            const int64_t row0 = uniform64((t0 + rt) * 16);
+            rc[rt] = make_rsrc(C + row0 * n + col0, ((m - row0) * (int64_t)n - col0) * SZ);
         }
+        T cv[RT][NT][4];
+        if (beta != 0.0) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        cv[rt][t][r] = (nmask & (1u << t)) ? BufIO<T>::load1(rc[rt], voffC[r] + 16 * t * SZ) : T(0);
+        }
+        const int64_t t1 = t0 + tstride;
+        if (t1 < ntile) stream_load_a<T, KC, RT, VEC>(A, m, k, t1, voffA, kmask, a_nxt);
 
         // B fragments small enough for registers may be hoisted out of the
         // row loop by the compiler; larger ones are re-read from LDS (or L2)
-        // for every row tile, which the opaque offset enforces.
+        // for every row step, which the opaque offset enforces.
         int bofs = 0;
         if constexpr (S * NT > 32) asm volatile("" : "+v"(bofs));
 
@@ -96,52 +183,44 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A
         for (int s = 0; s < S; ++s) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const T b = Bsrc[bofs + (s * NT + t) * 64 + lane];
+                const T b = BLDS ? sB[bofs + (s * NT + t) * 64 + lane]
+                                 : Bf[bofs + (s * nt_total + bm.group * NT + t) * 64 + lane];
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) acc[rt][t] = M::op(a[rt][s], b, acc[rt][t]);
+                for (int rt = 0; rt < RT; ++rt) acc[rt][t] = M::op(a_cur[rt][s], b, acc[rt][t]);
             }
         }
 
-        // epilogue, one column tile at a time: lane (q, j) holds rows
-        // M::row(q, r) of column 16t + j
+        // epilogue: lane (q, j) holds rows M::row(q, r) of column 16t + j
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int col = 16 * t + j;
-            T cv[RT][4];
-            if (beta != 0.0) {
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t row = (t0 + rt) * 16 + M::row(q, r);
-                        cv[rt][r] = (row < m && col < n) ? C[row * n + col] : T(0);
+                for (int r = 0; r < 4; ++r)
+                    if (nmask & (1u << t)) {
+                        const double c = beta != 0.0 ? (double)cv[rt][t][r] : 0.0;
+                        BufIO<T>::store1((T)epilogue(alpha, (double)acc[rt][t][r], beta, c), rc[rt],
+                                         voffC[r] + 16 * t * SZ);
                     }
-            }
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = (t0 + rt) * 16 + M::row(q, r);
-                    if (row < m && col < n) {
-                        const double c = beta != 0.0 ? (double)cv[rt][r] : 0.0;
-                        C[row * n + col] = (T)epilogue(alpha, (double)acc[rt][t][r], beta, c);
-                    }
-                }
-        }
+            for (int s = 0; s < S; ++s) a_cur[rt][s] = a_nxt[rt][s];
     }
 }
 
 template <typename T, int KC, int NT, int RT, bool VEC>
 hipError_t run_stream(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k,
-                      double alpha, double beta, int64_t grid, int block, hipStream_t s) {
+                      double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
+                      hipStream_t s) {
     hipLaunchKernelGGL((k_stream<T, KC, NT, RT, VEC>), dim3((unsigned)grid), dim3(block), 0, s,
                        static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C),
-                       m, (int)n, (int)k, alpha, beta);
+                       m, (int)n, (int)k, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
 }
 
 typedef hipError_t (*StreamFn)(const void *, const void *, void *, int64_t, int64_t, int64_t,
-                               double, double, int64_t, int, hipStream_t);
+                               double, double, int64_t, int, int, int, hipStream_t);
 struct StreamEntry {
     int KC, NT, RT, vec;
     StreamFn fn;
@@ -157,4 +236,5 @@ struct StreamEntry {
 #define TSMM_SE_RT2(T, KC, V) \
     TSMM_SE(T, KC, 1, 2, V) TSMM_SE(T, KC, 2, 2, V) TSMM_SE(T, KC, 4, 2, V) TSMM_SE(T, KC, 8, 2, V)
 #define TSMM_SE_RT4(T, KC, V) TSMM_SE(T, KC, 1, 4, V) TSMM_SE(T, KC, 2, 4, V) TSMM_SE(T, KC, 4, 4, V)
+#define TSMM_SE_RT8(T, KC, V) TSMM_SE(T, KC, 1, 8, V) TSMM_SE(T, KC, 2, 8, V)
 #define TSMM_SE_ALL(T, KC, V) TSMM_SE_RT1(T, KC, V) TSMM_SE_RT2(T, KC, V) TSMM_SE_RT4(T, KC, V)

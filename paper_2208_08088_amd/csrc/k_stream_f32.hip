@@ -11,7 +11,7 @@ static const StreamEntry kF32[] = {
     TSMM_SE_RT2(float, 4, false) TSMM_SE_RT4(float, 4, false)
     TSMM_SE_RT2(float, 8, false) TSMM_SE_RT4(float, 8, false)
     // vector mapping
-    TSMM_SE_ALL(float, 16, true) TSMM_SE_ALL(float, 32, true) TSMM_SE_ALL(float, 64, true)
+    TSMM_SE_ALL(float, 16, true) TSMM_SE_RT8(float, 16, true) TSMM_SE_ALL(float, 32, true) TSMM_SE_ALL(float, 64, true)
     TSMM_SE_ALL(float, 128, true) TSMM_SE_RT1(float, 256, true) TSMM_SE_RT2(float, 256, true)
 };
 

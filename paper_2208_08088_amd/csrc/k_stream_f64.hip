@@ -10,9 +10,10 @@ static const StreamEntry kF64[] = {
     TSMM_SE_RT1(double, 256, false)
     TSMM_SE_RT2(double, 4, false) TSMM_SE_RT4(double, 4, false)
     // vector mapping (even k)
-    TSMM_SE_ALL(double, 8, true) TSMM_SE_ALL(double, 16, true) TSMM_SE_ALL(double, 32, true)
+    TSMM_SE_ALL(double, 8, true) TSMM_SE_ALL(double, 16, true) TSMM_SE_RT8(double, 8, true)
+    TSMM_SE_RT8(double, 16, true) TSMM_SE_ALL(double, 32, true)
     TSMM_SE_ALL(double, 64, true) TSMM_SE_RT1(double, 128, true) TSMM_SE_RT2(double, 128, true)
-    TSMM_SE_RT1(double, 256, true)
+    TSMM_SE_RT1(double, 256, true) TSMM_SE_RT2(double, 256, true)
 };
 
 StreamFn find_stream_f64(int KC, int NT, int RT, bool vec) {

@@ -212,6 +212,8 @@ int mclass_of(int64_t m) { return m < (1 << 16) ? 0 : (m < (1 << 21) ? 1 : 2); }
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
+constexpr size_t kLdsBudget = 128 * 1024;  // packed-B bytes a workgroup may keep in LDS
+
 // Which kernel family serves (layout, dtype, mode, shape)?
 int natural_kernel(const tsmm_plan_s &p) {
     if (p.layout == TSMM_OP_T) return p.dtype == TSMM_F64 ? TSMM_KERNEL_SPLITK : TSMM_KERNEL_SIMPLE;
@@ -236,20 +238,29 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
         const int KC = kclass4(p.k), NT = ntclass(p.n);
         const int w = KC * NT;
         const bool vec = vec_mapping(p.dtype, p.k, KC);
+        // column groups: the smallest split whose B slice fits the LDS budget
+        t.nsplit = 1;
+        while ((size_t)(KC / 4) * (NT / t.nsplit) * 64 * elem_bytes(p.dtype) > kLdsBudget && t.nsplit < NT)
+            t.nsplit *= 2;
+        const int NTs = NT / t.nsplit;
         t.rows_per_wave = w <= 64 ? 4 : (w <= 256 ? 2 : 1);
-        while (t.rows_per_wave > 1 && !stream_variant_exists(p.dtype, KC, NT, t.rows_per_wave, vec))
+        while (t.rows_per_wave > 1 && !stream_variant_exists(p.dtype, KC, NTs, t.rows_per_wave, vec))
             t.rows_per_wave /= 2;
         t.wg_per_cu = 8;
         break;
     }
-    case TSMM_KERNEL_SPLITBF16:
-        t.rows_per_wave = 2;
+    case TSMM_KERNEL_SPLITBF16: {
+        const int KC = kclass32(p.k), NT = ntclass(p.n), terms = std::max(1, split_terms(p.dtype, p.mode));
+        t.nsplit = 1;
+        while ((size_t)(KC / 32) * (NT / t.nsplit) * terms * 64 * 16 > kLdsBudget && t.nsplit < NT) t.nsplit *= 2;
+        const int NTs = NT / t.nsplit;
+        t.rows_per_wave = KC * NTs <= 1024 ? 2 : 1;
         while (t.rows_per_wave > 1 &&
-               !splitbf16_variant_exists(p.dtype, kclass32(p.k), ntclass(p.n), t.rows_per_wave,
-                                         split_products(p.dtype, p.mode)))
+               !splitbf16_variant_exists(p.dtype, KC, NTs, t.rows_per_wave, split_products(p.dtype, p.mode)))
             t.rows_per_wave /= 2;
         t.wg_per_cu = 4;
         break;
+    }
     case TSMM_KERNEL_SPLITK:
         t.rows_per_wave = 2;  // RG: 4-row groups per wavefront iteration
         t.wg_per_cu = 2;
@@ -261,6 +272,17 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
         break;
     }
     return t;
+}
+
+// Workgroups of a grid-stride op N launch: enough for the row tiles, at
+// most wg_per_cu per compute unit; with column groups the row-block count is
+// a multiple of 8 so that a row block's groups share an XCD.
+int64_t row_grid(const tsmm_plan_s &p, const tsmm_tile &t, int64_t cus) {
+    const int64_t waves = ((p.m + 15) / 16 + t.rows_per_wave - 1) / t.rows_per_wave;
+    const int64_t wgs = (waves + t.waves_per_wg - 1) / t.waves_per_wg;
+    int64_t rows = std::max<int64_t>(1, std::min<int64_t>(wgs, cus * t.wg_per_cu / t.nsplit));
+    if (t.nsplit > 1) rows = (rows + 7) / 8 * 8;
+    return rows * t.nsplit;
 }
 
 // Validate a tile for the plan and derive the launch geometry.
@@ -280,9 +302,12 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
     if (t.splitk == 0) t.splitk = d.splitk;
     if (t.nsplit == 0) t.nsplit = d.nsplit;
     if (t.rows_per_wave < 0 || t.waves_per_wg < 1 || t.waves_per_wg > 4 || !is_pow2(t.waves_per_wg) ||
-        t.wg_per_cu < 1 || t.wg_per_cu > 32 || t.splitk < 1 || t.splitk > 65536 || t.nsplit != 1)
+        t.wg_per_cu < 1 || t.wg_per_cu > 32 || t.splitk < 1 || t.splitk > 65536 || t.nsplit < 1 ||
+        t.nsplit > 16 || !is_pow2(t.nsplit))
         return fail(TSMM_ERROR_INVALID_VALUE, "tile out of range (waves_per_wg 1/2/4, wg_per_cu 1..32, "
-                                              "splitk 1..65536, nsplit 1)");
+                                              "splitk 1..65536, nsplit 1/2/4/8/16)");
+    if (t.nsplit > 1 && t.kernel != TSMM_KERNEL_STREAM && t.kernel != TSMM_KERNEL_SPLITBF16)
+        return fail(TSMM_ERROR_INVALID_VALUE, "nsplit applies to the op N fragment kernels only");
     const int64_t cus = std::max(1, p.caps.compute_units);
     p.block = 64 * t.waves_per_wg;
     p.workspace_bytes = 0;
@@ -292,27 +317,28 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         p.KC = kclass4(p.k);
         p.NT = ntclass(p.n);
         p.vec = vec_mapping(p.dtype, p.k, p.KC);
-        if (!stream_variant_exists(p.dtype, p.KC, p.NT, t.rows_per_wave, p.vec))
-            return fail(TSMM_ERROR_NOT_SUPPORTED, "no stream kernel for KC=%d NT=%d RT=%d vec=%d", p.KC,
-                        p.NT, t.rows_per_wave, (int)p.vec);
-        const size_t lds = (size_t)(p.KC / 4) * p.NT * 64 * elem_bytes(p.dtype);
-        if (lds <= 128 * 1024 && (int64_t)lds > p.caps.lds_bytes_per_cu)  // Eq. (2) analogue
-            return fail(TSMM_ERROR_NOT_SUPPORTED, "packed B (%zu bytes) exceeds LDS", lds);
-        const int64_t waves = ((p.m + 15) / 16 + t.rows_per_wave - 1) / t.rows_per_wave;
-        const int64_t wgs = (waves + t.waves_per_wg - 1) / t.waves_per_wg;
-        p.grid = std::max<int64_t>(1, std::min<int64_t>(wgs, cus * t.wg_per_cu));
+        if (t.nsplit > p.NT) return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d > %d column tiles", t.nsplit, p.NT);
+        const int NTs = p.NT / t.nsplit;
+        if (!stream_variant_exists(p.dtype, p.KC, NTs, t.rows_per_wave, p.vec))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no stream kernel for KC=%d NT=%d RT=%d vec=%d", p.KC, NTs,
+                        t.rows_per_wave, (int)p.vec);
+        // Eq. (2) analogue: the workgroup's slice of packed B must fit the LDS
+        const size_t lds = (size_t)(p.KC / 4) * NTs * 64 * elem_bytes(p.dtype);
+        if (lds <= kLdsBudget && (int64_t)lds > p.caps.lds_bytes_per_cu)
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "packed B slice (%zu bytes) exceeds LDS", lds);
+        p.grid = row_grid(p, t, cus);
         break;
     }
     case TSMM_KERNEL_SPLITBF16: {
         p.KC = kclass32(p.k);
         p.NT = ntclass(p.n);
         p.vec = false;
-        if (!splitbf16_variant_exists(p.dtype, p.KC, p.NT, t.rows_per_wave, split_products(p.dtype, p.mode)))
-            return fail(TSMM_ERROR_NOT_SUPPORTED, "no split-bf16 kernel for KC=%d NT=%d RT=%d", p.KC,
-                        p.NT, t.rows_per_wave);
-        const int64_t waves = ((p.m + 15) / 16 + t.rows_per_wave - 1) / t.rows_per_wave;
-        const int64_t wgs = (waves + t.waves_per_wg - 1) / t.waves_per_wg;
-        p.grid = std::max<int64_t>(1, std::min<int64_t>(wgs, cus * t.wg_per_cu));
+        if (t.nsplit > p.NT) return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d > %d column tiles", t.nsplit, p.NT);
+        const int NTs = p.NT / t.nsplit;
+        if (!splitbf16_variant_exists(p.dtype, p.KC, NTs, t.rows_per_wave, split_products(p.dtype, p.mode)))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no split-bf16 kernel for KC=%d NT=%d RT=%d", p.KC, NTs,
+                        t.rows_per_wave);
+        p.grid = row_grid(p, t, cus);
         break;
     }
     case TSMM_KERNEL_SPLITK: {
@@ -693,11 +719,11 @@ tsmm_status tsmm_plan_describe(tsmm_plan_t p, char *buf, size_t len) {
     if (!p || !buf || len == 0) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
     snprintf(buf, len,
              "op=%c dtype=%s mode=%s m=%" PRId64 " n=%" PRId64 " k=%" PRId64
-             " kernel=%s kc=%d nt=%d vec=%d rt=%d waves=%d wg_per_cu=%d splitk=%d grid=%" PRId64 "x%" PRId64
+             " kernel=%s kc=%d nt=%d vec=%d rt=%d waves=%d wg_per_cu=%d splitk=%d nsplit=%d grid=%" PRId64 "x%" PRId64
              " block=%d workspace=%zu table=%d",
              p->layout == TSMM_OP_N ? 'N' : 'T', dtype_name(p->dtype), mode_name(p->mode), p->m, p->n, p->k,
              kernel_name(p->tile.kernel), p->KC, p->NT, (int)p->vec, p->tile.rows_per_wave, p->tile.waves_per_wg,
-             p->tile.wg_per_cu, p->tile.splitk, p->grid, p->grid_y, p->block, p->workspace_bytes,
+             p->tile.wg_per_cu, p->tile.splitk, p->tile.nsplit, p->grid, p->grid_y, p->block, p->workspace_bytes,
              (int)p->tile_from_table);
     return TSMM_SUCCESS;
 }
@@ -744,8 +770,9 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
         kernel = TSMM_KERNEL_SIMPLE;  // vector loads need 16-byte aligned rows
     switch (kernel) {
     case TSMM_KERNEL_STREAM:
-        e = launch_stream(p->dtype, p->KC, p->NT, p->tile.rows_per_wave, p->vec, A, base + packed->L.off_frag, C,
-                          p->m, p->n, p->k, alpha, beta, p->grid, p->block, s);
+        e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec, A,
+                          base + packed->L.off_frag, C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, p->NT,
+                          p->tile.nsplit, s);
         break;
     case TSMM_KERNEL_SPLITBF16:
         if (reinterpret_cast<uintptr_t>(A) & 15) {
@@ -754,11 +781,11 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
             e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
             break;
         }
-        e = launch_splitbf16(p->dtype, p->KC, p->NT, p->tile.rows_per_wave, split_products(p->dtype, p->mode), A,
-                             base + packed->L.off_frag,
+        e = launch_splitbf16(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave,
+                             split_products(p->dtype, p->mode), A, base + packed->L.off_frag,
                              p->mode != TSMM_MODE_NATIVE ? reinterpret_cast<const int32_t *>(base + packed->L.off_exps)
                                                          : nullptr,
-                             C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, s);
+                             C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, p->NT, p->tile.nsplit, s);
         break;
     case TSMM_KERNEL_SPLITK: {
         if (!p->workspace) {
@@ -837,11 +864,15 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
         tile_cost[e] = (double)kBatchRows * (double)(I.k * sa + I.n * 4) + 2048.0;
     }
     p->n_work = inst_start[count];
-    const int waves = 4;
-    p->tile = tsmm_tile{TSMM_KERNEL_STREAM, 1, waves, 4, 1, 1};
+    for (const BatchedInstance &I : p->inst) {
+        const int KC = dtype == TSMM_BF16 ? kclass32(I.k) : kclass4(I.k);
+        p->batch_lds = std::max(p->batch_lds, batched_lds_bytes(dtype, KC, ntclass(I.n)));
+    }
+    const int waves = 4;  // the batched kernel's fixed workgroup: 4 wavefronts x 32 rows
+    p->tile = tsmm_tile{TSMM_KERNEL_STREAM, 2, waves, 4, 1, 1};
     p->block = 64 * waves;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)caps.compute_units * p->tile.wg_per_cu,
-                                                                (p->n_work + waves - 1) / waves));
+                                                                p->n_work));
     p->grid = grid;
 
     // contiguous cost-balanced partition of the work-tile sequence: workgroup
@@ -884,7 +915,12 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
         tsmm_plan_destroy(p.release());
         return fail(TSMM_ERROR_OUT_OF_MEMORY, "batched plan allocation failed");
     }
-    hipError_t e = hipMemcpy(p->d_inst_start, inst_start.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
+    hipError_t e = prepare_batched(dtype, p->batch_lds);
+    if (e != hipSuccess) {
+        tsmm_plan_destroy(p.release());
+        return hip_fail(e, "batched kernel attributes");
+    }
+    e = hipMemcpy(p->d_inst_start, inst_start.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_wg_begin, wg_begin.data(), sizeof(int64_t) * (grid + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_wg_inst, wg_inst.data(), sizeof(int32_t) * grid, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -963,7 +999,8 @@ tsmm_status tsmm_execute_batched(tsmm_plan_t p, const void *const *A, const tsmm
     hipError_t e = launch_batched(p->dtype, static_cast<const BatchDesc *>(p->d_desc),
                                   static_cast<const int64_t *>(p->d_inst_start),
                                   static_cast<const int64_t *>(p->d_wg_begin),
-                                  static_cast<const int32_t *>(p->d_wg_inst), p->grid, p->block, p->stream);
+                                  static_cast<const int32_t *>(p->d_wg_inst), p->grid, p->block, p->batch_lds,
+                                  p->stream);
     return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "batched launch");
 }
 
@@ -984,7 +1021,8 @@ tsmm_status tsmm_graph_create_batched(tsmm_plan_t p, tsmm_graph_t *out) {
         hipError_t le = launch_batched(p->dtype, static_cast<const BatchDesc *>(p->d_desc),
                                        static_cast<const int64_t *>(p->d_inst_start),
                                        static_cast<const int64_t *>(p->d_wg_begin),
-                                       static_cast<const int32_t *>(p->d_wg_inst), p->grid, p->block, cs);
+                                       static_cast<const int32_t *>(p->d_wg_inst), p->grid, p->block, p->batch_lds,
+                                       cs);
         e = hipStreamEndCapture(cs, &g->graph);
         if (le != hipSuccess) e = le;
     }

@@ -119,7 +119,7 @@ struct alignas(16) BatchDesc {
 };
 
 // Rows of one batched work tile (a wavefront processes it as 16-row tiles).
-constexpr int kBatchRows = 64;
+constexpr int kBatchRows = 128;
 
 }  // namespace tsmm
 
@@ -153,6 +153,7 @@ struct tsmm_plan_s {
     void *d_inst_start = nullptr;             // device int64[count + 1]: first work tile
     void *d_wg_begin = nullptr;               // device int64[grid + 1]: work-tile range
     void *d_wg_inst = nullptr;                // device int32[grid]: instance of wg_begin
+    size_t batch_lds = 0;                     // dynamic LDS of the batched launch
     bool bound = false;
     std::vector<tsmm::BatchDesc> bound_desc;
 };
@@ -189,17 +190,19 @@ hipError_t launch_simple_t(tsmm_dtype dt, const void *A, const void *B, void *C,
                            int64_t n, int64_t k, double alpha, double beta, hipStream_t s);
 
 // op N streaming, binary64 / binary32 16x16x4 fragments.
+// NT: column tiles per workgroup; nt_total = NT * nsplit column tiles of
+// the packed B.  With nsplit > 1, grid must be a multiple of 8 * nsplit.
 hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, const void *A,
                          const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, double alpha,
-                         double beta, int64_t grid, int block, hipStream_t s);
+                         double beta, int64_t grid, int block, int nt_total, int nsplit, hipStream_t s);
 bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec);
 
 // op N, split-bf16 (terms 2 or 3 of binary32 A and B; products 3 or 6) or
 // plain bf16 inputs (terms == 1).
 hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products, const void *A,
                             const void *Bfrag, const int32_t *exps, void *C, int64_t m, int64_t n,
-                            int64_t k, double alpha, double beta, int64_t grid, int block,
-                            hipStream_t s);
+                            int64_t k, double alpha, double beta, int64_t grid, int block, int nt_total,
+                            int nsplit, hipStream_t s);
 bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int products);
 
 // op T, split-k: pass 1 writes P partial m x n sums, pass 2 reduces them in
@@ -211,9 +214,13 @@ bool splitk_variant_exists(int MT, int NT, int RG);
 
 // Batched persistent launch: workgroup w runs work tiles
 // [wg_begin[w], wg_begin[w+1]) of the instance sequence described by
-// inst_start (prefix counts of work tiles).
+// inst_start (prefix counts of work tiles).  lds_bytes: the largest packed
+// B of the batch (batched_lds_bytes); prepare_batched must have been called
+// with at least that size.  block must be 256.
+size_t batched_lds_bytes(tsmm_dtype dt, int KC, int NT);
+hipError_t prepare_batched(tsmm_dtype dt, size_t lds_bytes);
 hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *inst_start,
                           const int64_t *wg_begin, const int32_t *wg_inst, int64_t grid, int block,
-                          hipStream_t s);
+                          size_t lds_bytes, hipStream_t s);
 
 }  // namespace tsmm

@@ -134,7 +134,7 @@ def test_set_tile_validation(T):
         p.set_tile(kernel=T.KERNEL_STREAM, waves_per_wg=3)
     assert e.value.status == T.INVALID_VALUE
     with pytest.raises(T.TsmmError):
-        p.set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=8)  # no such instantiation
+        p.set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=16)  # no such instantiation
     p.set_tile(kernel=T.KERNEL_SIMPLE)
     assert p.info()["kernel"] == "simple"
     p.set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=2, wg_per_cu=3)
