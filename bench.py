@@ -40,6 +40,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}
 M_ROWS = 1 << 23
+CPU_SAMPLE_ROWS = 6 << 20  # rows of each sub-case the CPU oracle recomputes (about 10 s of work)
 KS = (8, 32, 128)
 BETAS = (0.0, 1.0)
 
@@ -126,6 +127,29 @@ def run_headline(torch, T, cases, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return wall, timer.per_key_ms()
+
+
+def kernel_source_hash():
+    """First 16 hex digits of sha256 over the binary64 streaming kernel's sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_common.h", "k_stream.h", "k_stream_f64.hip"):
+        with open(os.path.join(ROOT, "paper_2208_08088_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(case):
+    """HBM bytes per launch of `case` from the committed rocprofv3 counter
+    summary, or None when there is none or the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", "k_stream_f64_%s_pmc.txt" % {
+        "k128b1": "k128_n128_beta1_m2p23"}.get(case, case))
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
+    if kv.get("case") != case or kv.get("source_hash") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def bound_of(bytes_, flops, dt):
@@ -259,7 +283,7 @@ def cpu_baseline(torch, I, cases, target_s=15.0):
     import oracle
     oracle.build()
     cores = len(os.sched_getaffinity(0))
-    rows = I.sample_rows(M_ROWS, 1 << 17, 3)
+    rows = I.sample_rows(M_ROWS, CPU_SAMPLE_ROWS, 3)
     idx = torch.from_numpy(rows).cuda()
     tot_bytes, tot_s, worst = 0, 0.0, 0.0
     per = []
@@ -299,7 +323,7 @@ def main():
     cases = headline(torch, T, I, args)
     print("[bench] headline cases ready: %s" % ", ".join(c["tag"] for c in cases), file=sys.stderr, flush=True)
     # snapshot sampled C0 rows and check one call of each case (for the CPU leg)
-    rows = I.sample_rows(M_ROWS, 1 << 17, 3)
+    rows = I.sample_rows(M_ROWS, CPU_SAMPLE_ROWS, 3)
     idx = torch.from_numpy(rows).cuda()
     for c in cases:
         c["C0s"] = c["C"][idx].cpu().numpy()
@@ -329,7 +353,7 @@ def main():
     else:
         ach, peak, unit = c["flops"] / ms / 1e9, PEAK_TFLOPS["f64"], "TFLOP/s"
     roofline = dict(kernel="k_stream<double,%d,%d> (%s)" % (c["k"], c["n"] // 16, c["tag"]), bound=bnd,
-                    achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=None,
+                    achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=measured_traffic(c["tag"]),
                     per_launch_bytes=c["bytes"], per_launch_flops=c["flops"], avg_launch_us=ms * 1e3)
     print("[bench] headline done: %.1f GB/s" % value, file=sys.stderr, flush=True)
 

@@ -99,7 +99,11 @@ typedef enum tsmm_kernel {
     TSMM_KERNEL_STREAM = 2,   /* op N streaming: packed B fragments, A rows
                                  streamed through registers, matrix cores     */
     TSMM_KERNEL_SPLITK = 3,   /* op T: split-k partials + ordered reduce      */
-    TSMM_KERNEL_SPLITBF16 = 4 /* op N, TSMM_F32 in BF16X3 / BF16X6 mode       */
+    TSMM_KERNEL_SPLITBF16 = 4, /* op N, TSMM_F32 in BF16X3 / BF16X6 mode and
+                                  TSMM_BF16 inputs: bf16 matrix cores          */
+    TSMM_KERNEL_VALU64 = 5     /* op N binary64 on the vector ALU: one row per
+                                  lane, k % 8 == 0, n a multiple of the
+                                  column block                               */
 } tsmm_kernel;
 
 /* One entry of the tile table: the register/LDS blocking and launch shape
@@ -107,7 +111,9 @@ typedef enum tsmm_kernel {
  * thread split, Sec. IV-A.1 and IV-A.2).  Zero in a field means "default". */
 typedef struct tsmm_tile {
     int32_t kernel;        /* tsmm_kernel                                   */
-    int32_t rows_per_wave; /* 16-row tiles a wavefront owns at a time: 1,2,4 */
+    int32_t rows_per_wave; /* 16-row tiles a wavefront owns at a time: 1,2,4,
+                              8 (TSMM_KERNEL_VALU64: C columns per
+                              wavefront, 16 or 32)                       */
     int32_t waves_per_wg;  /* wavefronts per workgroup: 1..16               */
     int32_t wg_per_cu;     /* resident workgroups per compute unit (grid =
                               CUs * wg_per_cu, capped by the work): 1..32   */

@@ -34,7 +34,7 @@ DEFAULT_TABLE = os.path.join(HERE, "tile_table.txt")
 
 _DT_NAME = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}
 _KERNEL_NAME = {T.KERNEL_SIMPLE: "simple", T.KERNEL_STREAM: "stream", T.KERNEL_SPLITK: "splitk",
-                T.KERNEL_SPLITBF16: "splitbf16"}
+                T.KERNEL_SPLITBF16: "splitbf16", T.KERNEL_VALU64: "valu64"}
 
 
 def mclass_of(m):
@@ -67,6 +67,12 @@ def candidates(p):
             for rt in (1, 2, 4, 8):
                 for wpc in (1, 2, 4, 8, 16):
                     out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=wpc, splitk=1, nsplit=ns))
+        if p.dtype == T.F64 and p.layout == T.OP_N and p.k % 8 == 0 and p.n % 16 == 0:
+            # the binary64 vector-ALU kernel (rows_per_wave = columns per wavefront)
+            for nb in (16, 32):
+                for wpc in (1, 2, 3, 4, 8):
+                    out.append(dict(kernel=T.KERNEL_VALU64, rows_per_wave=nb, waves_per_wg=4, wg_per_cu=wpc,
+                                    splitk=1, nsplit=1))
     elif kern == T.KERNEL_SPLITBF16:
         for ns in sorted({base["nsplit"], base["nsplit"] * 2}):
             for rt in (1, 2):
@@ -126,7 +132,10 @@ def tune_class(name, spec, reps, log):
             p.set_tile(**cand)
         except T.TsmmError:
             continue
+        # op N classes are timed with beta = 0 and beta = 1 (both are used)
         ms = time_plan(p, As, pk, C, 0.0, reps)
+        if layout == "N":
+            ms += time_plan(p, As, pk, C, 1.0, reps)
         log("  %-14s %s  %.3f ms" % (name, " ".join("%s=%d" % kv for kv in sorted(cand.items())), ms))
         if best is None or ms < best[0]:
             best = (ms, p.get_tile())
@@ -188,7 +197,8 @@ def main(argv=None):
         if key in entries and not a.retune:
             log("[autotune] %s already in the table; kept (use --retune)" % key)
             continue
-        entries[key] = entry + "  # %.3f ms at %s" % (ms, "x".join(str(v) for v in spec[3:]))
+        entries[key] = entry + "  # %.3f ms at %s%s" % (ms, "x".join(str(v) for v in spec[3:]),
+                                                       " (beta 0 + beta 1)" if spec[0] == "N" else "")
         write_table(a.out, entries, header)
         log("[autotune] %s -> %s (%.3f ms)" % (name, entry, ms))
     return 0

@@ -84,6 +84,147 @@ template <int RT, int NCH> struct RawA<false, RT, NCH> {
     u16x8 v[RT][NCH];
 };
 
+// A of row tiles t .. t+RT-1: binary32 values (split modes) or bf16
+// vectors.  Vector loads go through one buffer resource per 16-row tile
+// sized to the rows that exist (rows beyond m read 0); columns beyond k
+// read through kOOB.
+template <typename TA, int KC, int RT, int PROD, bool VEC>
+__device__ __forceinline__ void bf16_load_step(const TA *__restrict__ A, int64_t m, int k, int64_t t, int j, int q,
+                                               RawA<(PROD > 1), RT, KC / 32> &x) {
+    constexpr int NCH = KC / 32;
+    constexpr bool F32IN = PROD > 1;
+    constexpr int SZ = F32IN ? 4 : 2;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t row0 = uniform64((t + rt) * 16);
+        if constexpr (VEC) {
+            const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, tile_rows(m, row0) * (int64_t)k * SZ);
+            const int voff0 = j * k * SZ;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int col = 32 * c + 8 * q;
+                if constexpr (F32IN) {
+                    const f4v v0 = BufIO<float>::load_vec(ra, col < k ? voff0 + col * SZ : kOOB);
+                    const f4v v1 = BufIO<float>::load_vec(ra, col + 4 < k ? voff0 + (col + 4) * SZ : kOOB);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        x.v[rt][c][e] = v0[e];
+                        x.v[rt][c][4 + e] = v1[e];
+                    }
+                } else {
+                    x.v[rt][c] = __builtin_bit_cast(
+                        u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, col < k ? voff0 + col * SZ : kOOB, 0, 2));
+                }
+            }
+        } else {
+            const int64_t row = row0 + j;
+            const bool rok = row < m;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int col = 32 * c + 8 * q;
+                if constexpr (F32IN)
+                    load_a8<float, false>(reinterpret_cast<const float *>(A) + row * (int64_t)k, col, k, rok,
+                                          x.v[rt][c]);
+                else
+                    x.v[rt][c] = load_a8_bf16<false>(reinterpret_cast<const uint16_t *>(A) + row * (int64_t)k, col, k,
+                                                     rok);
+            }
+        }
+    }
+}
+
+// One row step: products of tiles t.. from x_use while tiles tnext.. load
+// into x_load; C is read through a resource that is empty when beta == 0.
+template <typename TA, int KC, int NT, int RT, int PROD, bool VEC>
+__device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 *__restrict__ Bsrc, int bstride,
+                                          const int32_t *__restrict__ exps, float *__restrict__ C, int64_t m, int n,
+                                          int k, double alpha, double beta, int col0, int64_t t, int64_t tnext,
+                                          int j, int q, int lane, const RawA<(PROD > 1), RT, KC / 32> &x_use,
+                                          RawA<(PROD > 1), RT, KC / 32> &x_load) {
+    constexpr int TERMS = PROD == 1 ? 1 : (PROD == 3 ? 2 : 3);
+    constexpr int NCH = KC / 32;
+    constexpr bool TWO_ACC = PROD > 1;
+    constexpr bool F32IN = PROD > 1;
+
+    __amdgpu_buffer_rsrc_t rc[RT], rl[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t row0 = uniform64((t + rt) * 16);
+        const int64_t bytes = (tile_rows(m, row0) * (int64_t)n - col0) * 4;
+        rc[rt] = make_rsrc(C + row0 * n + col0, bytes);
+        rl[rt] = make_rsrc(C + row0 * n + col0, beta != 0.0 ? bytes : 0);
+    }
+    auto coff = [=](int tt, int r) { return (col0 + 16 * tt + j < n) ? ((4 * q + r) * n + 16 * tt + j) * 4 : kOOB; };
+    float cv[RT][NT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<float>::load1(rl[rt], coff(tt, r));
+    bf16_load_step<TA, KC, RT, PROD, VEC>(A, m, k, tnext, j, q, x_load);
+    __builtin_amdgcn_sched_barrier(0);
+
+    f4v acc[RT][NT];
+    f4v acc2[TWO_ACC ? RT : 1][TWO_ACC ? NT : 1];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+            acc[rt][tt] = f4v{};
+            if constexpr (TWO_ACC) acc2[rt][tt] = f4v{};
+        }
+
+    // small B may live in registers; larger B is re-read per row step
+    int bofs = 0;
+    if constexpr (NCH * NT * TERMS > 8) asm volatile("" : "+v"(bofs));
+
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        u16x8 at[RT][TERMS];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            if constexpr (F32IN) split8<TERMS>(x_use.v[rt][c], at[rt]);
+            else at[rt][0] = x_use.v[rt][c];
+        }
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+            u16x8 bt[TERMS];
+#pragma unroll
+            for (int p = 0; p < TERMS; ++p) bt[p] = Bsrc[bofs + ((c * bstride + tt) * TERMS + p) * 64 + lane];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                acc[rt][tt] = mfma_bf16(at[rt][0], bt[0], acc[rt][tt]);
+                if constexpr (PROD >= 3) {
+                    acc2[rt][tt] = mfma_bf16(at[rt][0], bt[1], acc2[rt][tt]);
+                    acc2[rt][tt] = mfma_bf16(at[rt][1], bt[0], acc2[rt][tt]);
+                }
+                if constexpr (PROD == 6) {
+                    acc2[rt][tt] = mfma_bf16(at[rt][0], bt[2], acc2[rt][tt]);
+                    acc2[rt][tt] = mfma_bf16(at[rt][1], bt[1], acc2[rt][tt]);
+                    acc2[rt][tt] = mfma_bf16(at[rt][2], bt[0], acc2[rt][tt]);
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+        const int col = col0 + 16 * tt + j;
+        const int e = (PROD > 1 && col < n) ? exps[col] : 0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double sacc = (double)acc[rt][tt][r];
+                if constexpr (TWO_ACC) sacc = sacc + (double)acc2[rt][tt][r];
+                if constexpr (PROD > 1) sacc = __builtin_ldexp(sacc, e);
+                BufIO<float>::store1((float)epilogue(alpha, sacc, beta, (double)cv[rt][tt][r]), rc[rt], coff(tt, r));
+            }
+    }
+}
+
 // PROD: 1 (plain bf16), 3 (two terms) or 6 (three terms).  NT: column tiles
 // per workgroup (one column group of the nt_total tiles when nsplit > 1,
 // with the workgroup -> (row block, group) map of k_stream.h).
@@ -125,112 +266,23 @@ __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__
     const int q = lane >> 4;
     const int64_t ntile = (m + 15) >> 4;
     const int wpb = blockDim.x >> 6;
-    const int64_t gw = rb * wpb + (threadIdx.x >> 6);
+    const int64_t gw = rb * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tstride = nrb * wpb * RT;
 
-    // raw A of a row step: binary32 values (split modes) or bf16 vectors
-    typedef RawA<F32IN, RT, NCH> raw_t;
-    auto load_step = [&](int64_t t, raw_t &x) {
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int64_t row = (t + rt) * 16 + j;
-            const bool rok = row < m;
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int col = 32 * c + 8 * q;
-                if constexpr (F32IN)
-                    load_a8<float, VEC>(reinterpret_cast<const float *>(A) + row * (int64_t)k, col, k, rok, x.v[rt][c]);
-                else
-                    x.v[rt][c] = load_a8_bf16<VEC>(reinterpret_cast<const uint16_t *>(A) + row * (int64_t)k, col, k, rok);
-            }
-        }
-    };
-
-    raw_t x_cur, x_nxt;
-    int64_t t0 = gw * RT;
-    if (t0 < ntile) load_step(t0, x_cur);
-
-    for (; t0 < ntile; t0 += tstride) {
-        float cv[RT][NT][4];
-        if (beta != 0.0) {
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t row = (t0 + rt) * 16 + 4 * q + r;
-                        const int col = col0 + 16 * t + j;
-                        cv[rt][t][r] = (row < m && col < n) ? __builtin_nontemporal_load(C + row * n + col) : 0.0f;
-                    }
-        }
-        const int64_t t1 = t0 + tstride;
-        if (t1 < ntile) load_step(t1, x_nxt);
-
-        f4v acc[RT][NT];
-        f4v acc2[TWO_ACC ? RT : 1][TWO_ACC ? NT : 1];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                acc[rt][t] = f4v{};
-                if constexpr (TWO_ACC) acc2[rt][t] = f4v{};
-            }
-
-        // small B may live in registers; larger B is re-read per row step
-        int bofs = 0;
-        if constexpr (NCH * NT * TERMS > 8) asm volatile("" : "+v"(bofs));
-
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            u16x8 at[RT][TERMS];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                if constexpr (F32IN) split8<TERMS>(x_cur.v[rt][c], at[rt]);
-                else at[rt][0] = x_cur.v[rt][c];
-            }
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                u16x8 bt[TERMS];
-#pragma unroll
-                for (int p = 0; p < TERMS; ++p)
-                    bt[p] = BLDS ? sB[bofs + ((c * NT + t) * TERMS + p) * 64 + lane]
-                                 : Bg[bofs + ((c * nt_total + group * NT + t) * TERMS + p) * 64 + lane];
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    acc[rt][t] = mfma_bf16(at[rt][0], bt[0], acc[rt][t]);
-                    if constexpr (PROD >= 3) {
-                        acc2[rt][t] = mfma_bf16(at[rt][0], bt[1], acc2[rt][t]);
-                        acc2[rt][t] = mfma_bf16(at[rt][1], bt[0], acc2[rt][t]);
-                    }
-                    if constexpr (PROD == 6) {
-                        acc2[rt][t] = mfma_bf16(at[rt][0], bt[2], acc2[rt][t]);
-                        acc2[rt][t] = mfma_bf16(at[rt][1], bt[1], acc2[rt][t]);
-                        acc2[rt][t] = mfma_bf16(at[rt][2], bt[0], acc2[rt][t]);
-                    }
-                }
-            }
-        }
-
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int col = col0 + 16 * t + j;
-            const int e = (PROD > 1 && col < n) ? exps[col] : 0;
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = (t0 + rt) * 16 + 4 * q + r;
-                    if (row < m && col < n) {
-                        double s = (double)acc[rt][t][r];
-                        if constexpr (TWO_ACC) s = s + (double)acc2[rt][t][r];
-                        if (PROD > 1) s = __builtin_ldexp(s, e);
-                        const double cc = beta != 0.0 ? (double)cv[rt][t][r] : 0.0;
-                        __builtin_nontemporal_store((float)epilogue(alpha, s, beta, cc), C + row * n + col);
-                    }
-                }
-        }
-        x_cur = x_nxt;
+    const u16x8 *__restrict__ Bsrc = BLDS ? sB : Bg + group * NT * TERMS * 64;
+    const int bstride = BLDS ? NT : nt_total;  // column tiles per k-chunk in Bsrc
+    // Ping-pong over two register sets, steps in pairs with no branch between
+    // them (a pair's second step may lie past the last tile: its loads read
+    // 0 and its stores are dropped).
+    RawA<F32IN, RT, NCH> x0, x1;
+    int64_t t = gw * RT;
+    if (t >= ntile) return;
+    bf16_load_step<TA, KC, RT, PROD, VEC>(A, m, k, t, j, q, x0);
+    for (; t < ntile; t += 2 * tstride) {
+        bf16_step<TA, KC, NT, RT, PROD, VEC>(A, Bsrc, bstride, exps, C, m, n, k, alpha, beta, col0, t, t + tstride,
+                                             j, q, lane, x0, x1);
+        bf16_step<TA, KC, NT, RT, PROD, VEC>(A, Bsrc, bstride, exps, C, m, n, k, alpha, beta, col0, t + tstride,
+                                             t + 2 * tstride, j, q, lane, x1, x0);
     }
 }
 

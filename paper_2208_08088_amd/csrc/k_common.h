@@ -82,6 +82,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, in
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)(uint32_t)b, 0x00020000);
 }
 
+// Byte offset outside any tile-sized resource: an access through it reads
+// 0 or is dropped.
+constexpr int kOOB = 0x40000000;
+
+// Rows of the 16-row tile starting at row0 that exist in an m-row matrix.
+__device__ __forceinline__ int64_t tile_rows(int64_t m, int64_t row0) {
+    const int64_t r = m - row0;
+    return r < 0 ? 0 : (r > 16 ? 16 : r);
+}
+
 template <typename T> struct BufIO;
 template <> struct BufIO<double> {
     static __device__ __forceinline__ d2v load_vec(__amdgpu_buffer_rsrc_t r, int voff) {

@@ -67,25 +67,31 @@ __global__ __launch_bounds__(kSplitBlock) void k_splitk_pass1(const double *__re
                 bv[rg][b] = bcol[b] ? BufIO<double>::load1(rb, (row * n + 16 * b + j) * 8) : 0.0;
         }
     };
-    double a_cur[RG][MT], b_cur[RG][NT], a_nxt[RG][MT], b_nxt[RG][NT];
-    int64_t g = (int64_t)__builtin_amdgcn_readfirstlane(wave) * 4 * RG;
-    if (r0 + g < r1) load(g, a_cur, b_cur);
-    for (; r0 + g < r1; g += gstride) {
-        if (r0 + g + gstride < r1) load(g + gstride, a_nxt, b_nxt);
+    auto mma = [&](const double (&av)[RG][MT], const double (&bv)[RG][NT]) {
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
             for (int a = 0; a < MT; ++a)
 #pragma unroll
                 for (int b = 0; b < NT; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rg][a], b_cur[rg][b], acc[a][b], 0, 0, 0);
-#pragma unroll
-        for (int rg = 0; rg < RG; ++rg) {
-#pragma unroll
-            for (int a = 0; a < MT; ++a) a_cur[rg][a] = a_nxt[rg][a];
-#pragma unroll
-            for (int b = 0; b < NT; ++b) b_cur[rg][b] = b_nxt[rg][b];
-        }
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rg][a], bv[rg][b], acc[a][b], 0, 0, 0);
+    };
+    // Ping-pong over two register sets, in pairs of groups with no branch
+    // between them (past r1 the resources are empty and reads return 0, so
+    // a pair's second group may lie beyond the range); the scheduling
+    // barriers keep each prefetch ahead of the products it overlaps.
+    double a0[RG][MT], b0[RG][NT], a1[RG][MT], b1[RG][NT];
+    int64_t g = (int64_t)__builtin_amdgcn_readfirstlane(wave) * 4 * RG;
+    if (r0 + g < r1) load(g, a0, b0);
+    for (; r0 + g < r1; g += 2 * gstride) {
+        load(g + gstride, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(g + 2 * gstride, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // combine the wavefronts in the fixed order ((w0 + w1) + w2) + ...

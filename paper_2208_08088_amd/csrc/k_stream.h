@@ -49,12 +49,13 @@ __device__ __forceinline__ BlockMap block_map(int nsplit) {
     return b;
 }
 
-// A rows of row tiles t .. t+RT-1 into registers: one buffer resource per
-// 16-row tile (its byte count ends at row m, so rows beyond m read 0);
-// kmask bit p (or s) says whether this lane's columns are inside k.
+// A rows of row tiles t .. t+RT-1 into registers.  One buffer resource per
+// 16-row tile, sized to the tile's rows that exist, so rows beyond m read
+// 0; a lane whose columns lie beyond k (ragged k) reads through the offset
+// kOOB instead of branching.  voff0 is the lane's row offset j*k*sizeof(T).
 template <typename T, int KC, int RT, bool VEC>
-__device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m, int k, int64_t t, int voffA,
-                                              uint32_t kmask, T (&a)[RT][KC / 4]) {
+__device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m, int k, bool kfull, int64_t t,
+                                              int voff0, int q, T (&a)[RT][KC / 4]) {
     typedef typename Mfma4<T>::vec vec_t;
     constexpr int VW = Mfma4<T>::VW;
     constexpr int S = KC / 4;
@@ -62,20 +63,102 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((t + rt) * 16);
-        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, (m - row0) * (int64_t)k * SZ);
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, tile_rows(m, row0) * (int64_t)k * SZ);
         if constexpr (VEC) {
 #pragma unroll
             for (int p = 0; p < S / VW; ++p) {
-                vec_t v = {};
-                if (kmask & (1u << p)) v = BufIO<T>::load_vec(ra, voffA + p * 4 * VW * SZ);
+                const int col = p * 4 * VW + q * VW;
+                const vec_t v = BufIO<T>::load_vec(ra, (kfull || col < k) ? voff0 + col * SZ : kOOB);
 #pragma unroll
                 for (int e = 0; e < VW; ++e) a[rt][p * VW + e] = v[e];
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < S; ++s) a[rt][s] = (kmask & (1u << s)) ? BufIO<T>::load1(ra, voffA + 4 * s * SZ) : T(0);
+            for (int s = 0; s < S; ++s) {
+                const int col = 4 * s + q;
+                a[rt][s] = BufIO<T>::load1(ra, (kfull || col < k) ? voff0 + col * SZ : kOOB);
+            }
         }
     }
+}
+
+// One row step of the streaming kernel: tiles t .. t+RT-1 are multiplied
+// with the A rows already in a_use while the rows of tiles tnext.. stream
+// into a_load.  C rows are read through a resource that is empty when
+// beta == 0 (no traffic, no branch), before the prefetch is issued, so the
+// epilogue's wait for them does not include the prefetch.
+template <typename T, int KC, int NT, int RT, bool VEC>
+__device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__restrict__ Bsrc, int bstride,
+                                            T *__restrict__ C, int64_t m, int n, int k, bool kfull, double alpha,
+                                            double beta, int col0, int64_t t, int64_t tnext, int voff0, int q,
+                                            int lane, int j, const T (&a_use)[RT][KC / 4],
+                                            T (&a_load)[RT][KC / 4]) {
+    typedef Mfma4<T> M;
+    typedef typename M::acc acc_t;
+    constexpr int S = KC / 4;
+    constexpr int SZ = (int)sizeof(T);
+
+    __amdgpu_buffer_rsrc_t rc[RT], rl[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t row0 = uniform64((t + rt) * 16);
+        const int64_t bytes = (tile_rows(m, row0) * (int64_t)n - col0) * SZ;
+        rc[rt] = make_rsrc(C + row0 * n + col0, bytes);
+        rl[rt] = make_rsrc(C + row0 * n + col0, beta != 0.0 ? bytes : 0);
+    }
+    // byte offset of accumulator element (tt, r): row M::row(q, r), column
+    // col0 + 16*tt + j of the tile; kOOB for columns beyond n
+    auto coff = [=](int tt, int r) {
+        return (col0 + 16 * tt + j < n) ? (M::row(q, r) * n + 16 * tt + j) * SZ : kOOB;
+    };
+    T cv[RT][NT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<T>::load1(rl[rt], coff(tt, r));
+
+    // past the last tile the resource holds no rows: the loads return 0
+    // without touching memory
+    stream_load_a<T, KC, RT, VEC>(A, m, k, kfull, tnext, voff0, q, a_load);
+    // all loads of this step are issued before any product: the scheduler
+    // must not sink the prefetch below the products it is meant to overlap
+    __builtin_amdgcn_sched_barrier(0);
+
+    // B fragments small enough for registers may be hoisted out of the row
+    // loop by the compiler; larger ones are re-read from LDS (or L2) every
+    // step, which the opaque offset enforces.
+    int bofs = 0;
+    if constexpr (S * NT > 32) asm volatile("" : "+v"(bofs));
+
+    acc_t acc[RT][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) acc[rt][tt] = acc_t{};
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+            const T b = Bsrc[bofs + (s * bstride + tt) * 64 + lane];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc[rt][tt] = M::op(a_use[rt][s], b, acc[rt][tt]);
+        }
+    }
+
+    // the epilogue (and its wait for C) follows the products
+    __builtin_amdgcn_sched_barrier(0);
+
+    // epilogue: lane (q, j) holds rows M::row(q, r) of column 16*tt + j
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                BufIO<T>::store1((T)epilogue(alpha, (double)acc[rt][tt][r], beta, (double)cv[rt][tt][r]), rc[rt],
+                                 coff(tt, r));
 }
 
 // KC: packed k class; NT: 16-column tiles per workgroup (all of n, or one
@@ -121,91 +204,30 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A
     constexpr int SZ = (int)sizeof(T);
 
     // Per-lane byte offsets, fixed for the whole kernel.  Rows are addressed
-    // through one buffer resource per 16-row tile whose byte count ends at
-    // the last row of the matrix, so rows beyond m read 0 and are not
-    // written; columns beyond k (ragged k) and beyond n are masked here.
-    const int voffA = VEC ? (j * k + q * VW) * SZ : (j * k + q) * SZ;
-    int voffC[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) voffC[r] = (M::row(q, r) * n + j) * SZ;
+    // through one buffer resource per 16-row tile sized to the rows of the
+    // tile that exist, so rows beyond m read 0 and are not written; lanes
+    // whose column lies beyond k (ragged k) or n get the offset kOOB, which
+    // is outside every tile, instead of a branch.
     const bool kfull = k == KC;
-    uint32_t kmask = 0;  // bit s (or p): this lane's A column is inside k
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int col = VEC ? (s / VW) * 4 * VW + q * VW : 4 * s + q;
-        if (kfull || col < k) kmask |= 1u << (VEC ? s / VW : s);
-    }
-    uint32_t nmask = 0;
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-        if (col0 + 16 * t + j < n) nmask |= 1u << t;
+    const int voff0 = j * k * SZ;
 
-    // Software pipeline: the A rows of the next step are in flight while
-    // this step's products and epilogue run; this step's C rows (beta != 0)
-    // are requested before the next A rows, so waiting for them does not
-    // wait for the prefetch.
-    T a_cur[RT][S], a_nxt[RT][S];
-    int64_t t0 = gw * RT;
-    if (t0 < ntile) stream_load_a<T, KC, RT, VEC>(A, m, k, t0, voffA, kmask, a_cur);
-    for (; t0 < ntile; t0 += tstride) {
-        __amdgpu_buffer_rsrc_t rc[RT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int64_t row0 = uniform64((t0 + rt) * 16);
-            rc[rt] = make_rsrc(C + row0 * n + col0, ((m - row0) * (int64_t)n - col0) * SZ);
-        }
-        T cv[RT][NT][4];
-        if (beta != 0.0) {
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        cv[rt][t][r] = (nmask & (1u << t)) ? BufIO<T>::load1(rc[rt], voffC[r] + 16 * t * SZ) : T(0);
-        }
-        const int64_t t1 = t0 + tstride;
-        if (t1 < ntile) stream_load_a<T, KC, RT, VEC>(A, m, k, t1, voffA, kmask, a_nxt);
-
-        // B fragments small enough for registers may be hoisted out of the
-        // row loop by the compiler; larger ones are re-read from LDS (or L2)
-        // for every row step, which the opaque offset enforces.
-        int bofs = 0;
-        if constexpr (S * NT > 32) asm volatile("" : "+v"(bofs));
-
-        acc_t acc[RT][NT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[rt][t] = acc_t{};
-
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const T b = BLDS ? sB[bofs + (s * NT + t) * 64 + lane]
-                                 : Bf[bofs + (s * nt_total + bm.group * NT + t) * 64 + lane];
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) acc[rt][t] = M::op(a_cur[rt][s], b, acc[rt][t]);
-            }
-        }
-
-        // epilogue: lane (q, j) holds rows M::row(q, r) of column 16t + j
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (nmask & (1u << t)) {
-                        const double c = beta != 0.0 ? (double)cv[rt][t][r] : 0.0;
-                        BufIO<T>::store1((T)epilogue(alpha, (double)acc[rt][t][r], beta, c), rc[rt],
-                                         voffC[r] + 16 * t * SZ);
-                    }
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int s = 0; s < S; ++s) a_cur[rt][s] = a_nxt[rt][s];
+    // Software pipeline, ping-pong over two register sets (the paper's
+    // KERNEL_M1 / KERNEL_M2 alternation, Sec. IV-B.2): while one set feeds
+    // this step's products, the next step's A rows stream into the other.
+    T a0[RT][S], a1[RT][S];
+    int64_t t = gw * RT;
+    if (t >= ntile) return;
+    stream_load_a<T, KC, RT, VEC>(A, m, k, kfull, t, voff0, q, a0);
+    const T *__restrict__ Bsrc = BLDS ? sB : Bf + bm.group * NT * 64;
+    const int bstride = BLDS ? NT : nt_total;  // column tiles per k-step in Bsrc
+    // Steps go in pairs with no branch between them (a branch would let the
+    // compiler sink the prefetch past it); a pair's second step may lie past
+    // the last tile, where its loads return 0 and its stores are dropped.
+    for (; t < ntile; t += 2 * tstride) {
+        stream_step<T, KC, NT, RT, VEC>(A, Bsrc, bstride, C, m, n, k, kfull, alpha, beta, col0, t, t + tstride,
+                                        voff0, q, lane, j, a0, a1);
+        stream_step<T, KC, NT, RT, VEC>(A, Bsrc, bstride, C, m, n, k, kfull, alpha, beta, col0, t + tstride,
+                                        t + 2 * tstride, voff0, q, lane, j, a1, a0);
     }
 }
 

@@ -68,6 +68,7 @@ const char *kernel_name(int k) {
     case TSMM_KERNEL_STREAM: return "stream";
     case TSMM_KERNEL_SPLITK: return "splitk";
     case TSMM_KERNEL_SPLITBF16: return "splitbf16";
+    case TSMM_KERNEL_VALU64: return "valu64";
     default: return "auto";
     }
 }
@@ -154,6 +155,7 @@ int parse_kernel(const std::string &s) {
     if (s == "stream") return TSMM_KERNEL_STREAM;
     if (s == "splitk") return TSMM_KERNEL_SPLITK;
     if (s == "splitbf16") return TSMM_KERNEL_SPLITBF16;
+    if (s == "valu64") return TSMM_KERNEL_VALU64;
     return -1;
 }
 
@@ -222,6 +224,21 @@ int natural_kernel(const tsmm_plan_s &p) {
     return (kclass4(p.k) && ntclass(p.n)) ? TSMM_KERNEL_STREAM : TSMM_KERNEL_SIMPLE;
 }
 
+// binary64 op N shapes the vector-ALU kernel can run
+bool valu64_ok(const tsmm_plan_s &p) {
+    return p.layout == TSMM_OP_N && p.dtype == TSMM_F64 && p.mode == TSMM_MODE_NATIVE && p.k > 0 && p.k % 8 == 0 &&
+           p.n > 0 && p.n % 16 == 0 && p.k <= 8192;
+}
+
+// Can kernel family `kernel` run this plan?
+bool eligible(const tsmm_plan_s &p, int kernel) {
+    switch (kernel) {
+    case TSMM_KERNEL_SIMPLE: return p.mode == TSMM_MODE_NATIVE;
+    case TSMM_KERNEL_VALU64: return valu64_ok(p);
+    default: return kernel == natural_kernel(p);
+    }
+}
+
 int pow2_tiles(int64_t d) {  // 16-wide tiles of a small dimension, as 1, 2 or 4
     int t = (int)((d + 15) / 16);
     return t <= 1 ? 1 : (t <= 2 ? 2 : 4);
@@ -261,6 +278,10 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
         t.wg_per_cu = 4;
         break;
     }
+    case TSMM_KERNEL_VALU64:
+        t.rows_per_wave = p.n % 32 == 0 ? 32 : 16;  // columns per wavefront
+        t.wg_per_cu = 2;
+        break;
     case TSMM_KERNEL_SPLITK:
         t.rows_per_wave = 2;  // RG: 4-row groups per wavefront iteration
         t.wg_per_cu = 2;
@@ -289,12 +310,12 @@ int64_t row_grid(const tsmm_plan_s &p, const tsmm_tile &t, int64_t cus) {
 tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
     tsmm_tile t = tile_in;
     if (t.kernel == TSMM_KERNEL_AUTO) t.kernel = natural_kernel(p);
-    const int nat = natural_kernel(p);
-    if (t.kernel != nat && t.kernel != TSMM_KERNEL_SIMPLE)
+    if (!eligible(p, t.kernel)) {
+        if (t.kernel == TSMM_KERNEL_SIMPLE)
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes need k <= %d and n <= 256", kMaxKC);
         return fail(TSMM_ERROR_NOT_SUPPORTED, "kernel %s cannot run this plan (natural kernel %s)",
-                    kernel_name(t.kernel), kernel_name(nat));
-    if (t.kernel == TSMM_KERNEL_SIMPLE && (p.mode != TSMM_MODE_NATIVE))
-        return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes need k <= %d and n <= 256", kMaxKC);
+                    kernel_name(t.kernel), kernel_name(natural_kernel(p)));
+    }
     tsmm_tile d = default_tile(p, t.kernel);
     if (t.rows_per_wave == 0) t.rows_per_wave = d.rows_per_wave;
     if (t.waves_per_wg == 0) t.waves_per_wg = d.waves_per_wg;
@@ -341,6 +362,22 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         p.grid = row_grid(p, t, cus);
         break;
     }
+    case TSMM_KERNEL_VALU64: {
+        const int NB = t.rows_per_wave;
+        if (!valu64_variant_exists(NB) || p.n % NB != 0)
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no vector-ALU kernel with %d columns per wavefront for n=%" PRId64,
+                        NB, p.n);
+        if (t.waves_per_wg != 4 || t.nsplit != 1)
+            return fail(TSMM_ERROR_INVALID_VALUE, "the vector-ALU kernel runs 4 wavefronts and no column split");
+        p.KC = kclass4(p.k);
+        p.NT = ntclass(p.n);
+        p.vec = false;
+        const int64_t ncg = p.n / NB;
+        p.grid_y = (ncg + 3) / 4;
+        const int64_t tiles = (p.m + 63) / 64;
+        p.grid = std::max<int64_t>(1, std::min<int64_t>(tiles, std::max<int64_t>(1, cus * t.wg_per_cu / p.grid_y)));
+        break;
+    }
     case TSMM_KERNEL_SPLITK: {
         const int MT = pow2_tiles(p.m), NT = pow2_tiles(p.n);
         if (!splitk_variant_exists(MT, NT, t.rows_per_wave))
@@ -382,7 +419,7 @@ tsmm_status choose_tile(tsmm_plan_s &p) {
             key.mclass = mclass_of(p.k);
         }
         auto it = tab.entries.find(key);
-        if (it != tab.entries.end() && it->second.kernel == nat) {
+        if (it != tab.entries.end() && eligible(p, it->second.kernel)) {
             tsmm_plan_s trial = p;
             if (apply_tile(trial, it->second) == TSMM_SUCCESS) {
                 p = trial;
@@ -655,7 +692,7 @@ tsmm_status tsmm_plan_set_tile(tsmm_plan_t p, const tsmm_tile *tile) {
     g_err.clear();
     if (!p || !tile) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
     if (p->batched) return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take tiles at planning time");
-    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_SPLITBF16)
+    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_VALU64)
         return fail(TSMM_ERROR_INVALID_VALUE, "bad kernel id %d", tile->kernel);
     tsmm_plan_s trial = *p;
     trial.workspace = nullptr;
@@ -773,6 +810,14 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
         e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec, A,
                           base + packed->L.off_frag, C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, p->NT,
                           p->tile.nsplit, s);
+        break;
+    case TSMM_KERNEL_VALU64:
+        if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(C)) & 15) {
+            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
+            break;
+        }
+        e = launch_valu64(p->tile.rows_per_wave, static_cast<const double *>(A), static_cast<const double *>(Brow),
+                          static_cast<double *>(C), p->m, p->n, p->k, alpha, beta, p->grid, s);
         break;
     case TSMM_KERNEL_SPLITBF16:
         if (reinterpret_cast<uintptr_t>(A) & 15) {

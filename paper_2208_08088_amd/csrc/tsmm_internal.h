@@ -205,6 +205,13 @@ hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products,
                             int nsplit, hipStream_t s);
 bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int products);
 
+// op N binary64 on the vector ALU: NB columns per wavefront (16, 32),
+// B row-major; requires n % NB == 0 and k % 8 == 0.  grid = 64-row tiles
+// walked by each column-group block.
+hipError_t launch_valu64(int NB, const double *A, const double *B, double *C, int64_t m, int64_t n, int64_t k,
+                         double alpha, double beta, int64_t grid, hipStream_t s);
+bool valu64_variant_exists(int NB);
+
 // op T, split-k: pass 1 writes P partial m x n sums, pass 2 reduces them in
 // ascending order and applies the epilogue.
 hipError_t launch_splitk(int MT, int NT, int RG, const double *A, const double *B, double *W,

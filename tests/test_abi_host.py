@@ -183,3 +183,20 @@ def test_tile_table_parsing(tmp_path):
                          env=dict(os.environ, TSMM_TILE_TABLE=str(bad), TSMM_STRICT_TABLE="1"),
                          capture_output=True, text=True)
     assert out.returncode != 0 and "tile table" in out.stderr
+
+
+def test_valu64_tile_rules(T):
+    p = T.plan_with_caps(1 << 20, 128, 128, "N")
+    p.set_tile(kernel=T.KERNEL_VALU64, rows_per_wave=32, waves_per_wg=4, wg_per_cu=2)
+    info = p.info()
+    # 128 columns / 32 per wavefront = 4 column groups = one group of 4 wavefronts
+    assert info["kernel"] == "valu64" and info["grid"] == "512x1"
+    with pytest.raises(T.TsmmError):  # n not a multiple of the column block
+        T.plan_with_caps(1000, 40, 128, "N").set_tile(kernel=T.KERNEL_VALU64, rows_per_wave=32)
+    with pytest.raises(T.TsmmError):  # k not a multiple of 8
+        T.plan_with_caps(1000, 32, 12, "N").set_tile(kernel=T.KERNEL_VALU64, rows_per_wave=16)
+    with pytest.raises(T.TsmmError):  # binary32 is not served by it
+        T.plan_with_caps(1000, 32, 32, "N", dtype=__import__("torch").float32).set_tile(kernel=T.KERNEL_VALU64)
+    q = T.plan_with_caps(1000, 256, 64, "N")
+    q.set_tile(kernel=T.KERNEL_VALU64, rows_per_wave=16)
+    assert q.info()["grid"].endswith("x4")

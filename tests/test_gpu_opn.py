@@ -202,3 +202,25 @@ def test_large_sampled_rows_2pow23_k8():
     T.execute(p, A, pk, C, 1.0, 1.0)
     ref = oracle.gemm_n(host(A[idx]), Bh, C0s, 1.0, 1.0)
     assert_normwise(host(C[idx]), ref, 1e-12)
+
+
+@pytest.mark.parametrize("m,k,n", [(1, 8, 16), (63, 16, 32), (65, 64, 64), (1000, 128, 128), (777, 256, 256),
+                                   (200, 24, 48), (4099, 128, 32)])
+def test_valu64_kernel(m, k, n):
+    # the binary64 vector-ALU kernel: ascending-l FMA chains per output, so
+    # small integers are exact; uniform inputs agree to 1e-12
+    seed = 6000 + m + k + n
+    A = I.host_ints((m, k), seed, 1, -8, 8)
+    B = I.host_ints((k, n), seed, 2, -8, 8)
+    C0 = I.host_ints((m, n), seed, 3, -8, 8)
+    for nb in (16, 32):
+        if n % nb:
+            continue
+        tile = dict(kernel=T.KERNEL_VALU64, rows_per_wave=nb, waves_per_wg=4, wg_per_cu=2)
+        C, p = run(A, B, C0, 1.5, 0.5, tile=tile)
+        assert p.info()["kernel"] == "valu64"
+        assert np.array_equal(C, oracle.gemm_n(A, B, C0, 1.5, 0.5))
+        Au = I.host_uniform((m, k), seed, 4)
+        Bu = I.host_uniform((k, n), seed, 5)
+        Cu, _ = run(Au, Bu, None, -0.5, 0.0, tile=tile)
+        assert_normwise(Cu, oracle.gemm_n(Au, Bu, None, -0.5, 0.0), 1e-12)
