@@ -101,9 +101,15 @@ typedef enum tsmm_kernel {
     TSMM_KERNEL_SPLITK = 3,   /* op T: split-k partials + ordered reduce      */
     TSMM_KERNEL_SPLITBF16 = 4, /* op N, TSMM_F32 in BF16X3 / BF16X6 mode and
                                   TSMM_BF16 inputs: bf16 matrix cores          */
-    TSMM_KERNEL_VALU64 = 5     /* op N binary64 on the vector ALU: one row per
+    TSMM_KERNEL_VALU64 = 5,    /* op N binary64 on the vector ALU: one row per
                                   lane, k % 8 == 0, n a multiple of the
                                   column block                               */
+    TSMM_KERNEL_WIDE = 6       /* op N TSMM_F32 (native, BF16X3, BF16X6) with
+                                  n = 128 or 256, k <= 256, k % 8 == 0: a
+                                  wavefront owns whole rows of C in 32x32
+                                  matrix-core accumulators, packed B streams
+                                  through LDS in 32-row slabs; A and C 16-byte
+                                  aligned                                    */
 } tsmm_kernel;
 
 /* One entry of the tile table: the register/LDS blocking and launch shape
@@ -113,7 +119,8 @@ typedef struct tsmm_tile {
     int32_t kernel;        /* tsmm_kernel                                   */
     int32_t rows_per_wave; /* 16-row tiles a wavefront owns at a time: 1,2,4,
                               8 (TSMM_KERNEL_VALU64: C columns per
-                              wavefront, 16 or 32)                       */
+                              wavefront, 16 or 32; TSMM_KERNEL_WIDE:
+                              32-row tiles, 2, or 4 when n = 128)        */
     int32_t waves_per_wg;  /* wavefronts per workgroup: 1..16               */
     int32_t wg_per_cu;     /* resident workgroups per compute unit (grid =
                               CUs * wg_per_cu, capped by the work): 1..32   */

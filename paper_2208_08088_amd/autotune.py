@@ -34,7 +34,7 @@ DEFAULT_TABLE = os.path.join(HERE, "tile_table.txt")
 
 _DT_NAME = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}
 _KERNEL_NAME = {T.KERNEL_SIMPLE: "simple", T.KERNEL_STREAM: "stream", T.KERNEL_SPLITK: "splitk",
-                T.KERNEL_SPLITBF16: "splitbf16", T.KERNEL_VALU64: "valu64"}
+                T.KERNEL_SPLITBF16: "splitbf16", T.KERNEL_VALU64: "valu64", T.KERNEL_WIDE: "wide"}
 
 
 def mclass_of(m):
@@ -57,13 +57,48 @@ CLASSES = {
 HEADLINE = ["n_f64_k8", "n_f64_k32", "n_f64_k128", "t_f64_64x64"]
 
 
+def _pow2_class(x, lo, hi):
+    c = lo
+    while c <= hi:
+        if x <= c:
+            return c
+        c *= 2
+    return 0
+
+
+def table_key(layout, dt, mode, m, n, k):
+    """(kc, nt, mclass) of the table entry tsmm_plan looks up for a shape."""
+    if layout == "T":
+        tiles = lambda d: 1 if (d + 15) // 16 <= 1 else (2 if (d + 15) // 16 <= 2 else 4)
+        return tiles(m), tiles(n), mclass_of(k)
+    bf16_family = dt == torch.bfloat16 or mode != "native"
+    kc = _pow2_class(k, 32, 256) if bf16_family else _pow2_class(k, 4, 256)
+    return kc, _pow2_class((n + 15) // 16, 1, 16), mclass_of(m)
+
+
+def natural_kernel(p):
+    if p.layout == T.OP_T:
+        return T.KERNEL_SPLITK
+    return T.KERNEL_SPLITBF16 if (p.dtype == T.BF16 or p.mode != T.MODE_NATIVE) else T.KERNEL_STREAM
+
+
 def candidates(p):
-    """Candidate tiles for plan p (the default tile first)."""
+    """Candidate tiles for plan p (the plan's current tile first)."""
     base = p.get_tile()
-    kern = base["kernel"]
     out = [dict(base)]
+    # the natural family's default tile, whatever the plan picked
+    nat = dict(base)
+    if base["kernel"] != natural_kernel(p):
+        try:
+            p.set_tile(kernel=natural_kernel(p))
+            nat = p.get_tile()
+            out.append(dict(nat))
+        except T.TsmmError:
+            nat = None
+        p.set_tile(**base)
+    kern = nat["kernel"] if nat else None
     if kern == T.KERNEL_STREAM:
-        for ns in sorted({base["nsplit"], base["nsplit"] * 2}):
+        for ns in sorted({nat["nsplit"], nat["nsplit"] * 2}):
             for rt in (1, 2, 4, 8):
                 for wpc in (1, 2, 4, 8, 16):
                     out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=wpc, splitk=1, nsplit=ns))
@@ -74,7 +109,7 @@ def candidates(p):
                     out.append(dict(kernel=T.KERNEL_VALU64, rows_per_wave=nb, waves_per_wg=4, wg_per_cu=wpc,
                                     splitk=1, nsplit=1))
     elif kern == T.KERNEL_SPLITBF16:
-        for ns in sorted({base["nsplit"], base["nsplit"] * 2}):
+        for ns in sorted({nat["nsplit"], nat["nsplit"] * 2}):
             for rt in (1, 2):
                 for wpc in (1, 2, 4, 8):
                     out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=wpc, splitk=1, nsplit=ns))
@@ -82,6 +117,10 @@ def candidates(p):
         for rg in (1, 2, 4):
             for P in (256, 512, 1024, 2048):
                 out.append(dict(kernel=kern, rows_per_wave=rg, waves_per_wg=4, wg_per_cu=1, splitk=P, nsplit=1))
+    if p.dtype == T.F32 and p.layout == T.OP_N and p.n in (128, 256) and 0 < p.k <= 256 and p.k % 8 == 0:
+        # the wide kernels (32-row tiles per wavefront; 4 only at n = 128)
+        for rt in ((2, 4) if p.n == 128 else (2,)):
+            out.append(dict(kernel=T.KERNEL_WIDE, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=1, splitk=1, nsplit=1))
     seen, uniq = set(), []
     for c in out:
         key = tuple(sorted(c.items()))
@@ -125,7 +164,6 @@ def tune_class(name, spec, reps, log):
     p = T.plan(m, n, k, layout, dt)
     if mode != "native":
         p.set_mode(mode)
-    info = p.info()
     best = None
     for cand in candidates(p):
         try:
@@ -139,10 +177,8 @@ def tune_class(name, spec, reps, log):
         log("  %-14s %s  %.3f ms" % (name, " ".join("%s=%d" % kv for kv in sorted(cand.items())), ms))
         if best is None or ms < best[0]:
             best = (ms, p.get_tile())
-    key_kc = info["kc"]
-    key_nt = info["nt"]
-    mcl = mclass_of(k if layout == "T" else m)
-    entry = "%s %s %s %s %s %d : %s %d %d %d %d %d" % (
+    key_kc, key_nt, mcl = table_key(layout, dt, mode, m, n, k)
+    entry = "%s %s %s %d %d %d : %s %d %d %d %d %d" % (
         layout, _DT_NAME[dt], mode, key_kc, key_nt, mcl, _KERNEL_NAME[best[1]["kernel"]],
         best[1]["rows_per_wave"], best[1]["waves_per_wg"], best[1]["wg_per_cu"], best[1]["splitk"],
         best[1]["nsplit"])

@@ -69,6 +69,7 @@ const char *kernel_name(int k) {
     case TSMM_KERNEL_SPLITK: return "splitk";
     case TSMM_KERNEL_SPLITBF16: return "splitbf16";
     case TSMM_KERNEL_VALU64: return "valu64";
+    case TSMM_KERNEL_WIDE: return "wide";
     default: return "auto";
     }
 }
@@ -156,6 +157,7 @@ int parse_kernel(const std::string &s) {
     if (s == "splitk") return TSMM_KERNEL_SPLITK;
     if (s == "splitbf16") return TSMM_KERNEL_SPLITBF16;
     if (s == "valu64") return TSMM_KERNEL_VALU64;
+    if (s == "wide") return TSMM_KERNEL_WIDE;
     return -1;
 }
 
@@ -212,6 +214,14 @@ int mclass_of(int64_t m) { return m < (1 << 16) ? 0 : (m < (1 << 21) ? 1 : 2); }
 
 // -------------------------------------------------------------- planning
 
+// Shapes the wide kernels serve (op N binary32, n = 128 or 256, k <= 256,
+// k % 8 == 0); the packed handle then carries their image.
+bool wide_shape(tsmm_layout layout, tsmm_dtype dtype, int64_t k, int64_t n) {
+    return layout == TSMM_OP_N && dtype == TSMM_F32 && (n == 128 || n == 256) && k > 0 && k <= kMaxKC &&
+           k % 8 == 0;
+}
+int wide_kc(int64_t k) { return std::max(64, kclass32(k)); }
+
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 constexpr size_t kLdsBudget = 128 * 1024;  // packed-B bytes a workgroup may keep in LDS
@@ -224,6 +234,9 @@ int natural_kernel(const tsmm_plan_s &p) {
     return (kclass4(p.k) && ntclass(p.n)) ? TSMM_KERNEL_STREAM : TSMM_KERNEL_SIMPLE;
 }
 
+bool wide_ok(const tsmm_plan_s &p) { return wide_shape(p.layout, p.dtype, p.k, p.n); }
+int wide_products(const tsmm_plan_s &p) { return p.mode == TSMM_MODE_NATIVE ? 0 : split_products(p.dtype, p.mode); }
+
 // binary64 op N shapes the vector-ALU kernel can run
 bool valu64_ok(const tsmm_plan_s &p) {
     return p.layout == TSMM_OP_N && p.dtype == TSMM_F64 && p.mode == TSMM_MODE_NATIVE && p.k > 0 && p.k % 8 == 0 &&
@@ -235,6 +248,7 @@ bool eligible(const tsmm_plan_s &p, int kernel) {
     switch (kernel) {
     case TSMM_KERNEL_SIMPLE: return p.mode == TSMM_MODE_NATIVE;
     case TSMM_KERNEL_VALU64: return valu64_ok(p);
+    case TSMM_KERNEL_WIDE: return wide_ok(p);
     default: return kernel == natural_kernel(p);
     }
 }
@@ -281,6 +295,10 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
     case TSMM_KERNEL_VALU64:
         t.rows_per_wave = p.n % 32 == 0 ? 32 : 16;  // columns per wavefront
         t.wg_per_cu = 2;
+        break;
+    case TSMM_KERNEL_WIDE:
+        t.rows_per_wave = p.n == 128 ? 4 : 2;  // 32-row tiles: 256 accumulator registers
+        t.wg_per_cu = 1;
         break;
     case TSMM_KERNEL_SPLITK:
         t.rows_per_wave = 2;  // RG: 4-row groups per wavefront iteration
@@ -378,6 +396,20 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         p.grid = std::max<int64_t>(1, std::min<int64_t>(tiles, std::max<int64_t>(1, cus * t.wg_per_cu / p.grid_y)));
         break;
     }
+    case TSMM_KERNEL_WIDE: {
+        p.KC = wide_kc(p.k);
+        p.NT = (int)(p.n / 32);
+        p.vec = true;
+        if (!wide_variant_exists(wide_products(p), p.KC, p.NT, t.rows_per_wave))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no wide kernel for KC=%d n=%" PRId64 " RT=%d", p.KC, p.n,
+                        t.rows_per_wave);
+        if (t.waves_per_wg != 4 || t.wg_per_cu != 1 || t.nsplit != 1)
+            return fail(TSMM_ERROR_INVALID_VALUE,
+                        "the wide kernel runs one workgroup of 4 wavefronts per compute unit, no column split");
+        const int64_t tiles = (p.m + wide_rows_per_wg(t.rows_per_wave) - 1) / wide_rows_per_wg(t.rows_per_wave);
+        p.grid = std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
+        break;
+    }
     case TSMM_KERNEL_SPLITK: {
         const int MT = pow2_tiles(p.m), NT = pow2_tiles(p.n);
         if (!splitk_variant_exists(MT, NT, t.rows_per_wave))
@@ -434,8 +466,10 @@ tsmm_status choose_tile(tsmm_plan_s &p) {
     } else if (log_level() >= 2) {
         fprintf(stderr, "[tsmm] tile table not used: %s\n", tab.error.c_str());
     }
+    // no table entry: the wide kernels where they apply (they read and split
+    // A once at any n), else the natural family
     tsmm_tile t{};
-    t.kernel = nat;
+    t.kernel = wide_ok(p) ? TSMM_KERNEL_WIDE : nat;
     return apply_tile(p, t);
 }
 
@@ -560,6 +594,12 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
             off = align(off + (size_t)L.KC * L.NT * 16 * eb);
         }
     }
+    if (wide_shape(layout, dtype, k, n)) {
+        L.wide_KC = wide_kc(k);
+        L.wide_NT = (int)(n / 32);
+        L.off_wide = off;
+        off = align(off + wide_image_bytes(L.wide_KC, L.wide_NT, terms));
+    }
     L.bytes = off;
 
     int dev = 0;
@@ -580,6 +620,9 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
         else
             e = launch_pack_frag4(dtype, B, base + L.off_frag, k, n, L.KC, L.NT, L.vec, s);
     }
+    if (e == hipSuccess && L.wide_KC)  // after the split planes it reads
+        e = launch_pack_wide(B, terms > 0 ? base + L.off_planes : nullptr, base + L.off_wide, k, n, L.wide_KC,
+                             L.wide_NT, terms, s);
     if (e != hipSuccess) {
         (void)hipFree(P->dev);
         return hip_fail(e, "pack");
@@ -692,7 +735,7 @@ tsmm_status tsmm_plan_set_tile(tsmm_plan_t p, const tsmm_tile *tile) {
     g_err.clear();
     if (!p || !tile) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
     if (p->batched) return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take tiles at planning time");
-    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_VALU64)
+    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_WIDE)
         return fail(TSMM_ERROR_INVALID_VALUE, "bad kernel id %d", tile->kernel);
     tsmm_plan_s trial = *p;
     trial.workspace = nullptr;
@@ -831,6 +874,20 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
                              p->mode != TSMM_MODE_NATIVE ? reinterpret_cast<const int32_t *>(base + packed->L.off_exps)
                                                          : nullptr,
                              C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, p->NT, p->tile.nsplit, s);
+        break;
+    case TSMM_KERNEL_WIDE:
+        if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(C)) & 15) {
+            if (p->mode != TSMM_MODE_NATIVE)
+                return fail(TSMM_ERROR_INVALID_VALUE, "split-bf16 modes need 16-byte aligned A and C");
+            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
+            break;
+        }
+        if (!packed->L.wide_KC || packed->L.wide_KC != p->KC)
+            return fail(TSMM_ERROR_SHAPE_MISMATCH, "packed operand has no image for the wide kernel");
+        e = launch_wide(wide_products(*p), p->KC, p->NT, p->tile.rows_per_wave, A, base + packed->L.off_wide,
+                        p->mode != TSMM_MODE_NATIVE ? reinterpret_cast<const int32_t *>(base + packed->L.off_exps)
+                                                    : nullptr,
+                        C, p->m, p->n, p->k, alpha, beta, p->grid, s);
         break;
     case TSMM_KERNEL_SPLITK: {
         if (!p->workspace) {

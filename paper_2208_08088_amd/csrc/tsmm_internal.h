@@ -43,6 +43,16 @@ namespace tsmm {
 //         B[32c + 8q + u][16t + j] * 2^-e_(16t+j)
 // where e_j is the column's power-of-two exponent (1 <= max|B[:,j]|*2^-e_j
 // < 2) and planes are the residual split hi, mid, lo.
+//
+// The wide kernels (k_wide.hip; binary32 B with n = 128 or 256, k <= 256,
+// k % 8 == 0) use the 32x32 products.  Their image holds, per 32-row chunk
+// c < KC/32 of B, fragment f < F, 32-column tile t < NT = n/32 and lane
+// l = 32q + j, one 16-byte vector:
+//   native (F = 4, f = h):       B[32c + 8h + 4q + u][col(t, j)], u < 4
+//   split  (F = 2T, f = s*T + p): plane p of
+//                                B[32c + 16s + 8(e/4) + 4q + e%4][col(t, j)], e < 8
+// at wfrag[((c*F + f)*NT + t)*64 + l], col(t, j) = 128(t/4) + 4j + t%4, and
+// 0 outside k x n.
 
 constexpr int kMaxKC = 256;  // largest packed k class of the fragment kernels
 constexpr int kMaxNT = 16;   // largest number of 16-column tiles (n <= 256)
@@ -82,6 +92,8 @@ struct PackedLayout {
     size_t off_frag = 0;        // 16x16x4 fragments, or bf16 fragments
     size_t off_planes = 0;      // split: terms*k*n uint16, row-major
     size_t off_exps = 0;        // split: n int32
+    int wide_KC = 0, wide_NT = 0;  // wide-kernel image (0: none)
+    size_t off_wide = 0;
     size_t bytes = 0;
 };
 
@@ -178,6 +190,17 @@ hipError_t launch_pack_bf16(tsmm_dtype dt, const void *B, void *frag, void *plan
 // Unpack a split handle: B_out[i][j] = (sum of planes) * 2^e_j (binary32).
 hipError_t launch_unpack_split(const void *planes, const int32_t *exps, void *B_out, int64_t k,
                                int64_t n, int terms, hipStream_t s);
+
+// Wide kernels (op N binary32 A and C, n = 32*NT with NT 4 or 8, k <= KC,
+// k % 8 == 0).  products: 0 (binary32 products), 3 or 6 (split modes).
+size_t wide_image_bytes(int KC, int NT, int terms);
+hipError_t launch_pack_wide(const void *Bf32, const void *planes, void *W, int64_t k, int64_t n, int KC, int NT,
+                            int terms, hipStream_t s);
+bool wide_variant_exists(int products, int KC, int NT, int RT);
+int64_t wide_rows_per_wg(int RT);
+hipError_t launch_wide(int products, int KC, int NT, int RT, const void *A, const void *W, const int32_t *exps,
+                       void *C, int64_t m, int64_t n, int64_t k, double alpha, double beta, int64_t grid,
+                       hipStream_t s);
 
 // C = beta*C (alpha == 0 or k == 0 paths).
 hipError_t launch_scale(tsmm_dtype out_dt, void *C, int64_t count, double beta, hipStream_t s);

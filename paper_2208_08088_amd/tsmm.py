@@ -24,7 +24,7 @@ SUCCESS, INVALID_VALUE, SHAPE_MISMATCH, NOT_SUPPORTED, TABLE, OUT_OF_MEMORY, NO_
 F64, F32, BF16 = 0, 1, 2
 OP_N, OP_T = 0, 1
 MODE_NATIVE, MODE_BF16X3, MODE_BF16X6 = 0, 1, 2
-KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_STREAM, KERNEL_SPLITK, KERNEL_SPLITBF16, KERNEL_VALU64 = range(6)
+KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_STREAM, KERNEL_SPLITK, KERNEL_SPLITBF16, KERNEL_VALU64, KERNEL_WIDE = range(7)
 
 _MODES = {"native": MODE_NATIVE, "bf16x3": MODE_BF16X3, "bf16x6": MODE_BF16X6}
 _LAYOUTS = {"N": OP_N, "T": OP_T}

@@ -146,7 +146,7 @@ def test_set_tile_validation(T):
 
 
 def test_set_mode_rules(T):
-    p = T.plan_with_caps(4096, 256, 256, "N", dtype=__import__("torch").float32)
+    p = T.plan_with_caps(4096, 64, 256, "N", dtype=__import__("torch").float32)
     p.set_mode("bf16x6")
     assert p.info()["kernel"] == "splitbf16" and p.info()["mode"] == "bf16x6"
     q = T.plan_with_caps(4096, 16, 16, "N")
@@ -200,3 +200,40 @@ def test_valu64_tile_rules(T):
     q = T.plan_with_caps(1000, 256, 64, "N")
     q.set_tile(kernel=T.KERNEL_VALU64, rows_per_wave=16)
     assert q.info()["grid"].endswith("x4")
+
+
+def test_wide_tile_rules(T):
+    f32 = __import__("torch").float32
+    # n = 256: two 32-row tiles per wavefront, 256 rows per workgroup, one
+    # workgroup per compute unit
+    p = T.plan_with_caps(1 << 24, 256, 256, "N", dtype=f32)
+    p.set_tile(kernel=T.KERNEL_WIDE)
+    t, info = p.get_tile(), p.info()
+    assert info["kernel"] == "wide" and t["rows_per_wave"] == 2 and t["wg_per_cu"] == 1
+    assert info["grid"] == "256x1" and info["kc"] == "256" and info["nt"] == "8"
+    for mode in ("bf16x3", "bf16x6"):
+        q = T.plan_with_caps(1000, 256, 256, "N", dtype=f32).set_mode(mode)
+        q.set_tile(kernel=T.KERNEL_WIDE)
+        assert q.info()["grid"] == "4x1"  # 1000 rows -> 4 workgroup tiles of 256
+    # n = 128: four 32-row tiles, k = 40 -> packed k class 64
+    r = T.plan_with_caps(70001, 128, 40, "N", dtype=f32)
+    r.set_tile(kernel=T.KERNEL_WIDE)
+    assert r.get_tile()["rows_per_wave"] == 4 and r.info()["kc"] == "64" and r.info()["grid"] == "137x1"
+    r.set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=2)
+    assert r.info()["grid"] == "256x1"
+    bad = [
+        (dict(m=1000, n=192, k=256, dtype=f32), {}),                     # n not 128 / 256
+        (dict(m=1000, n=256, k=100, dtype=f32), {}),                     # k % 8 != 0
+        (dict(m=1000, n=256, k=512, dtype=f32), {}),                     # k > 256
+        (dict(m=1000, n=256, k=256, dtype=__import__("torch").float64), {}),  # binary64
+        (dict(m=1000, n=256, k=256, dtype=f32), dict(rows_per_wave=4)),  # 512 accumulators
+        (dict(m=1000, n=256, k=256, dtype=f32), dict(wg_per_cu=2)),
+        (dict(m=1000, n=256, k=256, dtype=f32), dict(nsplit=2)),
+    ]
+    for shape, extra in bad:
+        with pytest.raises(T.TsmmError):
+            T.plan_with_caps(shape["m"], shape["n"], shape["k"], "N", dtype=shape["dtype"]).set_tile(
+                kernel=T.KERNEL_WIDE, **extra)
+    # op T never
+    with pytest.raises(T.TsmmError):
+        T.plan_with_caps(256, 256, 4096, "T", dtype=f32).set_tile(kernel=T.KERNEL_WIDE)
