@@ -120,7 +120,8 @@ typedef struct tsmm_tile {
     int32_t rows_per_wave; /* 16-row tiles a wavefront owns at a time: 1,2,4,
                               8 (TSMM_KERNEL_VALU64: C columns per
                               wavefront, 16 or 32; TSMM_KERNEL_WIDE:
-                              32-row tiles, 2, or 4 when n = 128)        */
+                              32-row tiles, 2, or 4 for native mode at
+                              n = 128)                                  */
     int32_t waves_per_wg;  /* wavefronts per workgroup: 1..16               */
     int32_t wg_per_cu;     /* resident workgroups per compute unit (grid =
                               CUs * wg_per_cu, capped by the work): 1..32   */

@@ -297,7 +297,8 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
         t.wg_per_cu = 2;
         break;
     case TSMM_KERNEL_WIDE:
-        t.rows_per_wave = p.n == 128 ? 4 : 2;  // 32-row tiles: 256 accumulator registers
+        // 32-row tiles: 256 accumulator registers (the split modes keep two)
+        t.rows_per_wave = (p.n == 128 && p.mode == TSMM_MODE_NATIVE) ? 4 : 2;
         t.wg_per_cu = 1;
         break;
     case TSMM_KERNEL_SPLITK:

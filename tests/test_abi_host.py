@@ -221,6 +221,11 @@ def test_wide_tile_rules(T):
     assert r.get_tile()["rows_per_wave"] == 4 and r.info()["kc"] == "64" and r.info()["grid"] == "137x1"
     r.set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=2)
     assert r.info()["grid"] == "256x1"
+    r.set_mode("bf16x6")  # split modes: two 32-row tiles only
+    r.set_tile(kernel=T.KERNEL_WIDE)
+    assert r.get_tile()["rows_per_wave"] == 2
+    with pytest.raises(T.TsmmError):
+        r.set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=4)
     bad = [
         (dict(m=1000, n=192, k=256, dtype=f32), {}),                     # n not 128 / 256
         (dict(m=1000, n=256, k=100, dtype=f32), {}),                     # k % 8 != 0

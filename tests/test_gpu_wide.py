@@ -46,6 +46,8 @@ SHAPES = [(4096, 256, 256, 0), (1000, 256, 256, 0), (70001, 128, 128, 4), (70001
 @pytest.mark.parametrize("mode", ["native", "bf16x6", "bf16x3"])
 @pytest.mark.parametrize("m,k,n,rt", SHAPES)
 def test_wide_against_fp64(mode, m, k, n, rt):
+    if rt == 4 and mode != "native":
+        pytest.skip("four 32-row tiles per wavefront are built for binary32 products only")
     seed = 700 + m % 97 + k + n
     A = I.col_scaled_uniform(m, k, seed, 1)
     B = I.host_uniform((k, n), seed, 2, dtype=np.float32)
