@@ -135,7 +135,7 @@ __device__ __forceinline__ void bf16_load_step(const TA *__restrict__ A, int64_t
 
 // One row step: products of tiles t.. from x_use while tiles tnext.. load
 // into x_load; C is read through a resource that is empty when beta == 0.
-template <typename TA, int KC, int NT, int RT, int PROD, bool VEC>
+template <typename TA, int KC, int NT, int RT, int PROD, bool VEC, bool CPRE = true>
 __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 *__restrict__ Bsrc, int bstride,
                                           const int32_t *__restrict__ exps, float *__restrict__ C, int64_t m, int n,
                                           int k, double alpha, double beta, int col0, int64_t t, int64_t tnext,
@@ -156,12 +156,14 @@ __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 
     }
     auto coff = [=](int tt, int r) { return (col0 + 16 * tt + j < n) ? ((4 * q + r) * n + 16 * tt + j) * 4 : kOOB; };
     float cv[RT][NT][4];
+    if constexpr (CPRE) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int tt = 0; tt < NT; ++tt)
+            for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<float>::load1(rl[rt], coff(tt, r));
+                for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<float>::load1(rl[rt], coff(tt, r));
+    }
     bf16_load_step<TA, KC, RT, PROD, VEC>(A, m, k, tnext, j, q, x_load);
     __builtin_amdgcn_sched_barrier(0);
 
@@ -217,6 +219,8 @@ __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                // without the C prefetch, C is read here (beta != 0 only)
+                if constexpr (!CPRE) cv[rt][tt][r] = beta != 0.0 ? BufIO<float>::load1(rl[rt], coff(tt, r)) : 0.0f;
                 double sacc = (double)acc[rt][tt][r];
                 if constexpr (TWO_ACC) sacc = sacc + (double)acc2[rt][tt][r];
                 if constexpr (PROD > 1) sacc = __builtin_ldexp(sacc, e);

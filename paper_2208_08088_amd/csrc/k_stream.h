@@ -87,7 +87,7 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 // into a_load.  C rows are read through a resource that is empty when
 // beta == 0 (no traffic, no branch), before the prefetch is issued, so the
 // epilogue's wait for them does not include the prefetch.
-template <typename T, int KC, int NT, int RT, bool VEC>
+template <typename T, int KC, int NT, int RT, bool VEC, bool CPRE = true>
 __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__restrict__ Bsrc, int bstride,
                                             T *__restrict__ C, int64_t m, int n, int k, bool kfull, double alpha,
                                             double beta, int col0, int64_t t, int64_t tnext, int voff0, int q,
@@ -112,12 +112,14 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
         return (col0 + 16 * tt + j < n) ? (M::row(q, r) * n + 16 * tt + j) * SZ : kOOB;
     };
     T cv[RT][NT][4];
+    if constexpr (CPRE) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int tt = 0; tt < NT; ++tt)
+            for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<T>::load1(rl[rt], coff(tt, r));
+                for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<T>::load1(rl[rt], coff(tt, r));
+    }
 
     // past the last tile the resource holds no rows: the loads return 0
     // without touching memory
@@ -150,15 +152,19 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
     // the epilogue (and its wait for C) follows the products
     __builtin_amdgcn_sched_barrier(0);
 
-    // epilogue: lane (q, j) holds rows M::row(q, r) of column 16*tt + j
+    // epilogue: lane (q, j) holds rows M::row(q, r) of column 16*tt + j.
+    // Without the C prefetch (CPRE false: variants whose registers are
+    // spoken for), C is read here, and only when beta != 0.
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 4; ++r) {
+                if constexpr (!CPRE) cv[rt][tt][r] = beta != 0.0 ? BufIO<T>::load1(rl[rt], coff(tt, r)) : (T)0;
                 BufIO<T>::store1((T)epilogue(alpha, (double)acc[rt][tt][r], beta, (double)cv[rt][tt][r]), rc[rt],
                                  coff(tt, r));
+            }
 }
 
 // KC: packed k class; NT: 16-column tiles per workgroup (all of n, or one

@@ -971,8 +971,10 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
         const int KC = dtype == TSMM_BF16 ? kclass32(I.k) : kclass4(I.k);
         p->batch_lds = std::max(p->batch_lds, batched_lds_bytes(dtype, KC, ntclass(I.n)));
     }
-    const int waves = 4;  // the batched kernel's fixed workgroup: 4 wavefronts x 32 rows
-    p->tile = tsmm_tile{TSMM_KERNEL_STREAM, 2, waves, 4, 1, 1};
+    // the batched kernel's fixed workgroup (kBatchWaves wavefronts), one per
+    // compute unit (two wavefronts per SIMD)
+    const int waves = kBatchWaves;
+    p->tile = tsmm_tile{TSMM_KERNEL_STREAM, 0, waves, 1, 1, 1};
     p->block = 64 * waves;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)caps.compute_units * p->tile.wg_per_cu,
                                                                 p->n_work));

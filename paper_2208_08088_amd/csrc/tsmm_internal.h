@@ -130,8 +130,10 @@ struct alignas(16) BatchDesc {
     int32_t vec, pad;
 };
 
-// Rows of one batched work tile (a wavefront processes it as 16-row tiles).
+// Rows of one batched work tile (the unit of the host's schedule) and
+// wavefronts per workgroup of the batched kernel.
 constexpr int kBatchRows = 128;
+constexpr int kBatchWaves = 8;
 
 }  // namespace tsmm
 
