@@ -94,6 +94,8 @@ __device__ __forceinline__ void bf16_load_step(const TA *__restrict__ A, int64_t
     constexpr int NCH = KC / 32;
     constexpr bool F32IN = PROD > 1;
     constexpr int SZ = F32IN ? 4 : 2;
+    // rows of 1 KiB and more: default cache policy (see stream_load_a)
+    constexpr int AUX = KC * SZ >= 1024 ? 0 : 2;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((t + rt) * 16);
@@ -104,8 +106,8 @@ __device__ __forceinline__ void bf16_load_step(const TA *__restrict__ A, int64_t
             for (int c = 0; c < NCH; ++c) {
                 const int col = 32 * c + 8 * q;
                 if constexpr (F32IN) {
-                    const f4v v0 = BufIO<float>::load_vec(ra, col < k ? voff0 + col * SZ : kOOB);
-                    const f4v v1 = BufIO<float>::load_vec(ra, col + 4 < k ? voff0 + (col + 4) * SZ : kOOB);
+                    const f4v v0 = BufIO<float>::load_vec<AUX>(ra, col < k ? voff0 + col * SZ : kOOB);
+                    const f4v v1 = BufIO<float>::load_vec<AUX>(ra, col + 4 < k ? voff0 + (col + 4) * SZ : kOOB);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         x.v[rt][c][e] = v0[e];
@@ -113,7 +115,7 @@ __device__ __forceinline__ void bf16_load_step(const TA *__restrict__ A, int64_t
                     }
                 } else {
                     x.v[rt][c] = __builtin_bit_cast(
-                        u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, col < k ? voff0 + col * SZ : kOOB, 0, 2));
+                        u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, col < k ? voff0 + col * SZ : kOOB, 0, AUX));
                 }
             }
         } else {

@@ -93,23 +93,31 @@ __device__ __forceinline__ int64_t tile_rows(int64_t m, int64_t row0) {
 }
 
 template <typename T> struct BufIO;
+// AUX is the cache policy of a load: 2 (streaming) where each instruction
+// covers whole 128-byte lines, 0 (default) where it covers part of a line
+// that the next loads of the same wavefront complete (a streaming load
+// would not keep the line for them).
 template <> struct BufIO<double> {
+    template <int AUX = 2>
     static __device__ __forceinline__ d2v load_vec(__amdgpu_buffer_rsrc_t r, int voff) {
-        return __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 2));
+        return __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, AUX));
     }
+    template <int AUX = 2>
     static __device__ __forceinline__ double load1(__amdgpu_buffer_rsrc_t r, int voff) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 2));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, AUX));
     }
     static __device__ __forceinline__ void store1(double v, __amdgpu_buffer_rsrc_t r, int voff) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, 0, 2);
     }
 };
 template <> struct BufIO<float> {
+    template <int AUX = 2>
     static __device__ __forceinline__ f4v load_vec(__amdgpu_buffer_rsrc_t r, int voff) {
-        return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 2));
+        return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, AUX));
     }
+    template <int AUX = 2>
     static __device__ __forceinline__ float load1(__amdgpu_buffer_rsrc_t r, int voff) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 2));
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, AUX));
     }
     static __device__ __forceinline__ void store1(float v, __amdgpu_buffer_rsrc_t r, int voff) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0, 2);

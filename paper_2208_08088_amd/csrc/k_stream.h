@@ -60,6 +60,12 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
     constexpr int VW = Mfma4<T>::VW;
     constexpr int S = KC / 4;
     constexpr int SZ = (int)sizeof(T);
+    // one load instruction covers 64 bytes (vector mapping) of each of 16
+    // rows.  Rows of 1 KiB and more are read with the default cache policy,
+    // so that the loads of a step share each line through the cache (one
+    // streaming load per line part was measured to refetch it: 7% slower at
+    // k = 128 binary64); shorter rows stream (measured faster at k <= 32).
+    constexpr int AUX = KC * SZ >= 1024 ? 0 : 2;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((t + rt) * 16);
@@ -68,7 +74,7 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 #pragma unroll
             for (int p = 0; p < S / VW; ++p) {
                 const int col = p * 4 * VW + q * VW;
-                const vec_t v = BufIO<T>::load_vec(ra, (kfull || col < k) ? voff0 + col * SZ : kOOB);
+                const vec_t v = BufIO<T>::template load_vec<AUX>(ra, (kfull || col < k) ? voff0 + col * SZ : kOOB);
 #pragma unroll
                 for (int e = 0; e < VW; ++e) a[rt][p * VW + e] = v[e];
             }
@@ -76,7 +82,7 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int col = 4 * s + q;
-                a[rt][s] = BufIO<T>::load1(ra, (kfull || col < k) ? voff0 + col * SZ : kOOB);
+                a[rt][s] = BufIO<T>::template load1<AUX>(ra, (kfull || col < k) ? voff0 + col * SZ : kOOB);
             }
         }
     }

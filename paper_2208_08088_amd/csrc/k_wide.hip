@@ -52,7 +52,10 @@ __device__ __forceinline__ int64_t tile_rows32(int64_t m, int64_t row0) {
 }
 
 // The lane's A vectors h0 <= h < h1 of chunk c for RT row tiles (rows past
-// m and columns past k read 0).  The lane offset is made opaque so that the
+// m and columns past k read 0).  One load instruction covers 32 bytes of
+// each of 32 rows, so the loads keep the default cache policy: the four
+// loads of a chunk then share each 128-byte line (streaming loads were
+// measured to refetch it).  The lane offset is made opaque so that the
 // compiler recomputes the per-chunk offsets at each use instead of keeping
 // all of them live across the tile loop.
 template <int RT, int H0, int H1>
