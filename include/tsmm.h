@@ -258,6 +258,10 @@ void tsmm_plan_destroy(tsmm_plan_t plan);
  *           match the plan (SHAPE_MISMATCH otherwise).
  *   A       device pointer, op N: m x k; op T: k x m; row-major.
  *   C       device pointer, m x n row-major, read (if beta != 0) and written.
+ * Any alignment of the element type is accepted; the vectorised kernels
+ * need 16-byte aligned A (and C, where they store 16-byte vectors) and the
+ * plan then runs the any-shape kernel instead (split-bf16 modes report
+ * INVALID_VALUE).
  * Asynchronous on the plan's stream.
  * Errors: INVALID_VALUE, SHAPE_MISMATCH, OUT_OF_MEMORY (lazy workspace),
  * HIP (launch failure; text in tsmm_last_error). */
@@ -268,8 +272,11 @@ tsmm_status tsmm_execute(tsmm_plan_t plan, const void *A, tsmm_packed_t packed,
 
 /* Plan `count` independent op N multiplies that run in ONE persistent
  * launch: instance b is m[b] x k[b] times k[b] x n[b].  Host arrays.  The
- * plan builds a static, cost-balanced work list (16-row tiles of every
- * instance, longest instances first) and owns its device copy.
+ * plan cuts the instances into chunks of rows (instances of one kernel
+ * variant together, longest first) that the launch's workgroups take from
+ * a device counter; the plan owns that counter, which every launch leaves
+ * at zero, so the launches (or graph replays) of one plan must not overlap
+ * in time.  Results do not depend on which workgroup takes which chunk.
  * dtype: TSMM_F32 (binary32 in/out) or TSMM_BF16 (bfloat16 in, binary32
  * out), NATIVE mode; 1 <= k[b], n[b] <= 128.
  * Errors: INVALID_VALUE, NOT_SUPPORTED, NO_DEVICE, OUT_OF_MEMORY, HIP. */
@@ -280,7 +287,11 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
 /* Bind the operands of a batched plan: host arrays of `count` device
  * pointers / handles / scalars.  The descriptor table is copied to the
  * device on the plan's stream from pinned staging memory, so a bind can be
- * captured in a graph.  Every packed[b] must match (k[b], n[b], dtype). */
+ * captured in a graph.  Every packed[b] must match (k[b], n[b], dtype).
+ * A[b] must be 16-byte aligned when k[b] allows vector loads (binary32: k
+ * a multiple of 4; bfloat16: of 8) and C[b] when binary32 C is stored in
+ * vectors (vector loads, n a multiple of 4, n > 48); INVALID_VALUE
+ * otherwise. */
 tsmm_status tsmm_batched_bind(tsmm_plan_t plan, const void *const *A,
                               const tsmm_packed_t *packed, void *const *C,
                               const double *alpha, const double *beta);
@@ -292,10 +303,13 @@ tsmm_status tsmm_execute_batched(tsmm_plan_t plan, const void *const *A,
                                  const tsmm_packed_t *packed, void *const *C,
                                  const double *alpha, const double *beta);
 
-/* Capture tsmm_execute_batched of a bound plan into a HIP graph once
- * (stream capture on the plan's stream) and instantiate it; launch it any
- * number of times with tsmm_graph_launch.  The graph keeps the bound
- * pointers: rebinding the plan afterwards does not change it. */
+/* Capture the batched launch of a bound plan into a HIP graph once (on a
+ * capture stream of its own, after the plan's stream has drained) and
+ * instantiate it; launch it any number of times with tsmm_graph_launch on
+ * any stream.  The graph reads the plan's descriptor table and work
+ * counter when it runs: a later tsmm_batched_bind changes the operands it
+ * uses (order the bind and the launches on one stream), and its launches
+ * must not overlap those of the plan.  The plan must outlive the graph. */
 tsmm_status tsmm_graph_create_batched(tsmm_plan_t plan, tsmm_graph_t *out);
 tsmm_status tsmm_graph_launch(tsmm_graph_t graph, void *stream);
 void tsmm_graph_destroy(tsmm_graph_t graph);

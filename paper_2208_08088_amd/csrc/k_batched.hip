@@ -1,18 +1,11 @@
 // Batched op N: many independent tall-and-skinny multiplies, each with its
 // own packed B, in ONE persistent launch.
 //
-// The host cuts every instance into work tiles of kBatchRows rows, orders
-// the instances longest first and gives each workgroup one contiguous,
-// cost-balanced range of the work-tile sequence (a static schedule: no
-// counters or queues, so a launch is deterministic and needs no reset,
-// which also makes it safe to capture in a graph and replay).  The
-// workgroup walks its range as one segment per instance it meets: it copies
-// that instance's packed B into LDS (the per-core resident block of B of the
-// paper's Sec. IV-A.2), then its wavefronts stream the segment's rows with
-// the software-pipelined row steps of the single-instance kernels,
-// specialised for the instance's (k class, n class, mapping): binary32
-// inputs use the 16x16x4 f32 product and fragments of k_stream.h, bfloat16
-// inputs the 16x16x32 bf16 product and fragments of k_bf16.h.
+// The host cuts every instance into chunks of kBatchChunk rows and orders
+// the instances by kernel variant; workgroups take chunks from a counter
+// (dynamic schedule, see k_batched).  Binary32 inputs use the 16x16x4 f32
+// product and fragments of k_stream.h, bfloat16 inputs the 16x16x32 bf16
+// product and fragments of k_bf16.h.
 #include "k_bf16.h"
 #include "k_common.h"
 #include "k_stream.h"
@@ -36,7 +29,7 @@ template <int KC, int NT> constexpr int batch_rt_bf16() { return batch_rt(batch_
 // Rows [row_a, row_b) of a binary32 instance: the streaming kernel's
 // pipelined row steps (k_stream.h) over this segment, with the segment end
 // as the row limit (rows past it read 0 and are not written).
-template <int KC, int NT, bool VEC>
+template <int KC, int NT, bool VEC, bool IL>
 __device__ __forceinline__ void segment_f32(const BatchDesc &d, int64_t row_a, int64_t row_b,
                                             const float *__restrict__ sB, int wave) {
     constexpr int RT = batch_rt_f32<KC, NT>();
@@ -55,10 +48,10 @@ __device__ __forceinline__ void segment_f32(const BatchDesc &d, int64_t row_a, i
     float a0[RT][S], a1[RT][S];
     stream_load_a<float, KC, RT, VEC>(A, row_b, k, kfull, t, voff0, q, a0);
     for (; t < tend; t += 2 * tstride) {
-        stream_step<float, KC, NT, RT, VEC, CPRE>(A, sB, NT, C, row_b, n, k, kfull, d.alpha, d.beta, 0, t,
-                                                  t + tstride, voff0, q, lane, j, a0, a1);
-        stream_step<float, KC, NT, RT, VEC, CPRE>(A, sB, NT, C, row_b, n, k, kfull, d.alpha, d.beta, 0,
-                                                  t + tstride, t + 2 * tstride, voff0, q, lane, j, a1, a0);
+        stream_step<float, KC, NT, RT, VEC, IL, CPRE>(A, sB, NT, C, row_b, n, k, kfull, d.alpha, d.beta, 0, t,
+                                                      t + tstride, voff0, q, lane, j, a0, a1);
+        stream_step<float, KC, NT, RT, VEC, IL, CPRE>(A, sB, NT, C, row_b, n, k, kfull, d.alpha, d.beta, 0,
+                                                      t + tstride, t + 2 * tstride, voff0, q, lane, j, a1, a0);
     }
 }
 
@@ -86,12 +79,28 @@ __device__ __forceinline__ void segment_bf16(const BatchDesc &d, int64_t row_a, 
     }
 }
 
-#define TSMM_CASE_NT(BODY, KC, V)                                       \
-    switch (d.NT) {                                                     \
-    case 1: BODY<KC, 1, V>(d, row_a, row_b, sB, wave); break;           \
-    case 2: BODY<KC, 2, V>(d, row_a, row_b, sB, wave); break;           \
-    case 4: BODY<KC, 4, V>(d, row_a, row_b, sB, wave); break;           \
-    default: BODY<KC, 8, V>(d, row_a, row_b, sB, wave); break;          \
+// binary32 with n % 4 == 0 and at least 4 column tiles uses the
+// interleaved column order (16-byte C vectors)
+#define TSMM_CASE_NT(BODY, KC, V)                                                                  \
+    switch (d.NT) {                                                                                \
+    case 1: BODY<KC, 1, V, false>(d, row_a, row_b, sB, wave); break;                               \
+    case 2: BODY<KC, 2, V, false>(d, row_a, row_b, sB, wave); break;                               \
+    case 4:                                                                                        \
+        if (d.il) BODY<KC, 4, V, true>(d, row_a, row_b, sB, wave);                                 \
+        else BODY<KC, 4, V, false>(d, row_a, row_b, sB, wave);                                     \
+        break;                                                                                     \
+    default:                                                                                       \
+        if (d.il) BODY<KC, 8, V, true>(d, row_a, row_b, sB, wave);                                 \
+        else BODY<KC, 8, V, false>(d, row_a, row_b, sB, wave);                                     \
+        break;                                                                                     \
+    }
+
+#define TSMM_CASE_NT_BF16(BODY, KC, V)                          \
+    switch (d.NT) {                                             \
+    case 1: BODY<KC, 1, V>(d, row_a, row_b, sB, wave); break;   \
+    case 2: BODY<KC, 2, V>(d, row_a, row_b, sB, wave); break;   \
+    case 4: BODY<KC, 4, V>(d, row_a, row_b, sB, wave); break;   \
+    default: BODY<KC, 8, V>(d, row_a, row_b, sB, wave); break;  \
     }
 
 __device__ __forceinline__ void run_segment_f32(const BatchDesc &d, int64_t row_a, int64_t row_b, const float *sB,
@@ -119,46 +128,61 @@ __device__ __forceinline__ void run_segment_bf16(const BatchDesc &d, int64_t row
                                                  int wave) {
     if (d.vec) {
         switch (d.KC) {
-        case 32: TSMM_CASE_NT(segment_bf16, 32, true) break;
-        case 64: TSMM_CASE_NT(segment_bf16, 64, true) break;
-        default: TSMM_CASE_NT(segment_bf16, 128, true) break;
+        case 32: TSMM_CASE_NT_BF16(segment_bf16, 32, true) break;
+        case 64: TSMM_CASE_NT_BF16(segment_bf16, 64, true) break;
+        default: TSMM_CASE_NT_BF16(segment_bf16, 128, true) break;
         }
     } else {
         switch (d.KC) {
-        case 32: TSMM_CASE_NT(segment_bf16, 32, false) break;
-        case 64: TSMM_CASE_NT(segment_bf16, 64, false) break;
-        default: TSMM_CASE_NT(segment_bf16, 128, false) break;
+        case 32: TSMM_CASE_NT_BF16(segment_bf16, 32, false) break;
+        case 64: TSMM_CASE_NT_BF16(segment_bf16, 64, false) break;
+        default: TSMM_CASE_NT_BF16(segment_bf16, 128, false) break;
         }
     }
 }
 
-// The workgroup walks its range of work tiles as segments, one per
-// instance it meets: B of the instance into LDS, then the rows of the
-// segment with a software-pipelined row loop specialised for the instance.
+// Dynamic schedule: the work is a sequence of chunks (kBatchChunk rows of
+// one instance; instances of one kernel variant next to each other).  A
+// workgroup takes the next chunk from a counter, loads that instance's
+// packed B into LDS when the instance changes (the per-core resident block
+// of B of the paper's Sec. IV-A.2), and streams the chunk's rows with the
+// software-pipelined row steps of the single-instance kernels, specialised
+// for the instance.  Each chunk is computed by exactly one workgroup with
+// the same code, so results do not depend on the schedule.  The last
+// workgroup to finish puts both counters back to zero, so every launch
+// (and every graph replay) starts from a clean state without a memset.
 template <bool BF16>
-__global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_batched(const BatchDesc *__restrict__ desc,
-                                                              const int64_t *__restrict__ inst_start,
-                                                              const int64_t *__restrict__ wg_begin,
-                                                              const int32_t *__restrict__ wg_inst) {
+__global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_batched(
+    const BatchDesc *__restrict__ desc, const int64_t *__restrict__ chunk_start, int64_t nchunks,
+    int32_t *__restrict__ ctr) {
     extern __shared__ u16x8 sB[];  // the current instance's packed B
-    const int64_t begin = wg_begin[blockIdx.x], end = wg_begin[blockIdx.x + 1];
-    int inst = wg_inst[blockIdx.x];
+    __shared__ int32_t s_chunk;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t g = begin; g < end;) {
-        while (g >= inst_start[inst + 1]) ++inst;  // the sequence is sorted: inst only grows
-        const int64_t g_end = end < inst_start[inst + 1] ? end : inst_start[inst + 1];
+    int inst = 0, loaded = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_chunk = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();  // (also: every wavefront is done with the previous chunk and its B)
+        const int64_t c = s_chunk;
+        if (c >= nchunks) break;
+        while (c >= chunk_start[inst + 1]) ++inst;  // a workgroup's chunks only grow
         const BatchDesc d = desc[inst];
-        __syncthreads();  // every wavefront is done with the previous B
-        const int vecs = BF16 ? (d.KC / 32) * d.NT * 64 : (d.KC / 4) * d.NT * 64 / 4;
-        const u16x8 *src = static_cast<const u16x8 *>(d.Bfrag);
-        for (int i = threadIdx.x; i < vecs; i += blockDim.x) sB[i] = src[i];
-        __syncthreads();
-        const int64_t row_a = (g - inst_start[inst]) * kBatchRows;
-        int64_t row_b = (g_end - inst_start[inst]) * kBatchRows;
-        row_b = row_b < d.m ? row_b : d.m;
+        if (inst != loaded) {
+            const int vecs = BF16 ? (d.KC / 32) * d.NT * 64 : (d.KC / 4) * d.NT * 64 / 4;
+            const u16x8 *src = static_cast<const u16x8 *>(d.Bfrag);
+            for (int i = threadIdx.x; i < vecs; i += blockDim.x) sB[i] = src[i];
+            loaded = inst;
+        }
+        __syncthreads();  // B in LDS; every lane has read s_chunk
+        const int64_t row_a = (c - chunk_start[inst]) * kBatchChunk;
+        const int64_t row_b = row_a + kBatchChunk < d.m ? row_a + kBatchChunk : d.m;
         if constexpr (BF16) run_segment_bf16(d, row_a, row_b, sB, wave);
         else run_segment_f32(d, row_a, row_b, reinterpret_cast<const float *>(sB), wave);
-        g = g_end;
+    }
+    // the last workgroup out resets the counters for the next launch
+    if (threadIdx.x == 0 &&
+        __hip_atomic_fetch_add(ctr + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (int32_t)gridDim.x - 1) {
+        __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(ctr + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -171,16 +195,15 @@ hipError_t prepare_batched(tsmm_dtype dt, size_t lds_bytes) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *inst_start,
-                          const int64_t *wg_begin, const int32_t *wg_inst, int64_t grid, int block,
-                          size_t lds_bytes, hipStream_t s) {
-    if (block != 64 * kBatchWaves) return hipErrorInvalidValue;
+hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *chunk_start, int64_t nchunks,
+                          int32_t *ctr, int64_t grid, int block, size_t lds_bytes, hipStream_t s) {
+    if (block != 64 * kBatchWaves || nchunks < 0 || nchunks >= (int64_t)1 << 31) return hipErrorInvalidValue;
     if (dt == TSMM_BF16)
-        hipLaunchKernelGGL(k_batched<true>, dim3((unsigned)grid), dim3(block), lds_bytes, s, desc, inst_start,
-                           wg_begin, wg_inst);
+        hipLaunchKernelGGL(k_batched<true>, dim3((unsigned)grid), dim3(block), lds_bytes, s, desc, chunk_start,
+                           nchunks, ctr);
     else
-        hipLaunchKernelGGL(k_batched<false>, dim3((unsigned)grid), dim3(block), lds_bytes, s, desc, inst_start,
-                           wg_begin, wg_inst);
+        hipLaunchKernelGGL(k_batched<false>, dim3((unsigned)grid), dim3(block), lds_bytes, s, desc, chunk_start,
+                           nchunks, ctr);
     return hipGetLastError();
 }
 

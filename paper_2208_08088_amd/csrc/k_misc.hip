@@ -6,8 +6,8 @@
 
 namespace tsmm {
 
-StreamFn find_stream_f64(int KC, int NT, int RT, bool vec);
-StreamFn find_stream_f32(int KC, int NT, int RT, bool vec);
+StreamFn find_stream_f64(int KC, int NT, int RT, bool vec, bool il);
+StreamFn find_stream_f32(int KC, int NT, int RT, bool vec, bool il);
 
 static inline unsigned blocks_for(int64_t count, int block) {
     return (unsigned)((count + block - 1) / block);
@@ -19,7 +19,7 @@ static inline unsigned blocks_for(int64_t count, int block) {
 
 template <typename T>
 __global__ void k_pack_frag4(const T *__restrict__ B, T *__restrict__ frag, int64_t k, int64_t n,
-                             int KC, int NT, int vec, int64_t total) {
+                             int KC, int NT, int vec, int pg, int64_t total) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int lane = (int)(idx & 63);
@@ -28,21 +28,21 @@ __global__ void k_pack_frag4(const T *__restrict__ B, T *__restrict__ frag, int6
     const int q = lane >> 4, j = lane & 15;
     constexpr int VW = 16 / (int)sizeof(T);
     const int64_t col = vec ? (int64_t)(s / VW) * 4 * VW + q * VW + (s % VW) : 4 * (int64_t)s + q;
-    const int64_t nc = 16 * (int64_t)t + j;
+    const int64_t nc = 16 * pg * (int64_t)(t / pg) + pg * j + t % pg;  // colp(t, j)
     frag[idx] = (col < k && nc < n) ? B[col * n + nc] : T(0);
 }
 
 hipError_t launch_pack_frag4(tsmm_dtype dt, const void *B, void *frag, int64_t k, int64_t n,
-                             int KC, int NT, bool vec, hipStream_t s) {
+                             int KC, int NT, bool vec, int pg, hipStream_t s) {
     const int64_t total = (int64_t)(KC / 4) * NT * 64;
     if (dt == TSMM_F64)
         hipLaunchKernelGGL(k_pack_frag4<double>, dim3(blocks_for(total, 256)), dim3(256), 0, s,
                            static_cast<const double *>(B), static_cast<double *>(frag), k, n, KC, NT,
-                           (int)vec, total);
+                           (int)vec, pg, total);
     else if (dt == TSMM_F32)
         hipLaunchKernelGGL(k_pack_frag4<float>, dim3(blocks_for(total, 256)), dim3(256), 0, s,
                            static_cast<const float *>(B), static_cast<float *>(frag), k, n, KC, NT,
-                           (int)vec, total);
+                           (int)vec, pg, total);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -139,20 +139,20 @@ hipError_t launch_simple_t(tsmm_dtype dt, const void *A, const void *B, void *C,
 
 // ------------------------------------------------------- stream dispatch
 
-static StreamFn find_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec) {
-    if (dt == TSMM_F64) return find_stream_f64(KC, NT, RT, vec);
-    if (dt == TSMM_F32) return find_stream_f32(KC, NT, RT, vec);
+static StreamFn find_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il) {
+    if (dt == TSMM_F64) return find_stream_f64(KC, NT, RT, vec, il);
+    if (dt == TSMM_F32) return find_stream_f32(KC, NT, RT, vec, il);
     return nullptr;
 }
 
-bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec) {
-    return find_stream(dt, KC, NT, RT, vec) != nullptr;
+bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il) {
+    return find_stream(dt, KC, NT, RT, vec, il) != nullptr;
 }
 
-hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, const void *A,
+hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il, const void *A,
                          const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, double alpha,
                          double beta, int64_t grid, int block, int nt_total, int nsplit, hipStream_t s) {
-    StreamFn fn = find_stream(dt, KC, NT, RT, vec);
+    StreamFn fn = find_stream(dt, KC, NT, RT, vec, il);
     if (!fn || nsplit < 1 || NT * nsplit != nt_total) return hipErrorInvalidValue;
     return fn(A, Bfrag, C, m, n, k, alpha, beta, grid, block, nt_total, nsplit, s);
 }

@@ -93,7 +93,7 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 // into a_load.  C rows are read through a resource that is empty when
 // beta == 0 (no traffic, no branch), before the prefetch is issued, so the
 // epilogue's wait for them does not include the prefetch.
-template <typename T, int KC, int NT, int RT, bool VEC, bool CPRE = true>
+template <typename T, int KC, int NT, int RT, bool VEC, bool IL, bool CPRE = true>
 __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__restrict__ Bsrc, int bstride,
                                             T *__restrict__ C, int64_t m, int n, int k, bool kfull, double alpha,
                                             double beta, int col0, int64_t t, int64_t tnext, int voff0, int q,
@@ -112,19 +112,44 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
         rc[rt] = make_rsrc(C + row0 * n + col0, bytes);
         rl[rt] = make_rsrc(C + row0 * n + col0, beta != 0.0 ? bytes : 0);
     }
+    // With interleaved columns (IL; tsmm_internal.h) tile tt of lane j is
+    // column colp(tt) of the column group, a lane holds PG adjacent columns
+    // of each row in the tiles of one group, and C moves in 16-byte vectors
+    // (n is then a multiple of PG); otherwise element by element.
+    constexpr int PG = IL ? Mfma4<T>::VW : 1;
+    static_assert(!IL || NT % PG == 0, "interleave groups must be whole");
+    constexpr bool cvec = IL;
+    auto colp = [=](int tt) { return 16 * PG * (tt / PG) + PG * j + tt % PG; };
     // byte offset of accumulator element (tt, r): row M::row(q, r), column
-    // col0 + 16*tt + j of the tile; kOOB for columns beyond n
+    // colp(tt); kOOB for columns beyond n
     auto coff = [=](int tt, int r) {
-        return (col0 + 16 * tt + j < n) ? (M::row(q, r) * n + 16 * tt + j) * SZ : kOOB;
+        return (col0 + colp(tt) < n) ? (M::row(q, r) * n + colp(tt)) * SZ : kOOB;
+    };
+    // byte offset of the vector of group g (columns colp(PG*g) ..): whole
+    // vectors lie inside or outside n when n % PG == 0
+    auto voff = [=](int g, int r) {
+        return (col0 + colp(PG * g) < n) ? (M::row(q, r) * n + colp(PG * g)) * SZ : kOOB;
     };
     T cv[RT][NT][4];
     if constexpr (CPRE) {
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RT; ++rt) {
+            if constexpr (cvec) {
 #pragma unroll
-            for (int tt = 0; tt < NT; ++tt)
+                for (int g = 0; g < NT / PG; ++g)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<T>::load1(rl[rt], coff(tt, r));
+                    for (int r = 0; r < 4; ++r) {
+                        const typename M::vec v = BufIO<T>::load_vec(rl[rt], voff(g, r));
+#pragma unroll
+                        for (int i = 0; i < PG; ++i) cv[rt][PG * g + i][r] = v[i];
+                    }
+            } else {
+#pragma unroll
+                for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<T>::load1(rl[rt], coff(tt, r));
+            }
+        }
     }
 
     // past the last tile the resource holds no rows: the loads return 0
@@ -158,25 +183,45 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
     // the epilogue (and its wait for C) follows the products
     __builtin_amdgcn_sched_barrier(0);
 
-    // epilogue: lane (q, j) holds rows M::row(q, r) of column 16*tt + j.
+    // epilogue: lane (q, j) holds rows M::row(q, r) of columns colp(tt).
     // Without the C prefetch (CPRE false: variants whose registers are
     // spoken for), C is read here, and only when beta != 0.
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt) {
+        if constexpr (cvec) {
 #pragma unroll
-        for (int tt = 0; tt < NT; ++tt)
+            for (int g = 0; g < NT / PG; ++g)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if constexpr (!CPRE) cv[rt][tt][r] = beta != 0.0 ? BufIO<T>::load1(rl[rt], coff(tt, r)) : (T)0;
-                BufIO<T>::store1((T)epilogue(alpha, (double)acc[rt][tt][r], beta, (double)cv[rt][tt][r]), rc[rt],
-                                 coff(tt, r));
-            }
+                for (int r = 0; r < 4; ++r) {
+                    if constexpr (!CPRE) {
+                        const typename M::vec v = beta != 0.0 ? BufIO<T>::load_vec(rl[rt], voff(g, r))
+                                                              : typename M::vec{};
+#pragma unroll
+                        for (int i = 0; i < PG; ++i) cv[rt][PG * g + i][r] = v[i];
+                    }
+                    typename M::vec v;
+#pragma unroll
+                    for (int i = 0; i < PG; ++i)
+                        v[i] = (T)epilogue(alpha, (double)acc[rt][PG * g + i][r], beta, (double)cv[rt][PG * g + i][r]);
+                    BufIO<T>::store_vec(v, rc[rt], voff(g, r));
+                }
+        } else {
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if constexpr (!CPRE) cv[rt][tt][r] = beta != 0.0 ? BufIO<T>::load1(rl[rt], coff(tt, r)) : (T)0;
+                    BufIO<T>::store1((T)epilogue(alpha, (double)acc[rt][tt][r], beta, (double)cv[rt][tt][r]), rc[rt],
+                                     coff(tt, r));
+                }
+        }
+    }
 }
 
 // KC: packed k class; NT: 16-column tiles per workgroup (all of n, or one
 // column group of it); RT: 16-row tiles per wavefront step; VEC: vector
 // k-slot mapping.  nt_total is the number of column tiles of the packed B.
-template <typename T, int KC, int NT, int RT, bool VEC>
+template <typename T, int KC, int NT, int RT, bool VEC, bool IL>
 __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A,
                                                           const T *__restrict__ Bf,
                                                           T *__restrict__ C, int64_t m, int n,
@@ -236,18 +281,18 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A
     // compiler sink the prefetch past it); a pair's second step may lie past
     // the last tile, where its loads return 0 and its stores are dropped.
     for (; t < ntile; t += 2 * tstride) {
-        stream_step<T, KC, NT, RT, VEC>(A, Bsrc, bstride, C, m, n, k, kfull, alpha, beta, col0, t, t + tstride,
-                                        voff0, q, lane, j, a0, a1);
-        stream_step<T, KC, NT, RT, VEC>(A, Bsrc, bstride, C, m, n, k, kfull, alpha, beta, col0, t + tstride,
-                                        t + 2 * tstride, voff0, q, lane, j, a1, a0);
+        stream_step<T, KC, NT, RT, VEC, IL>(A, Bsrc, bstride, C, m, n, k, kfull, alpha, beta, col0, t,
+                                            t + tstride, voff0, q, lane, j, a0, a1);
+        stream_step<T, KC, NT, RT, VEC, IL>(A, Bsrc, bstride, C, m, n, k, kfull, alpha, beta, col0, t + tstride,
+                                            t + 2 * tstride, voff0, q, lane, j, a1, a0);
     }
 }
 
-template <typename T, int KC, int NT, int RT, bool VEC>
+template <typename T, int KC, int NT, int RT, bool VEC, bool IL>
 hipError_t run_stream(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k,
                       double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
                       hipStream_t s) {
-    hipLaunchKernelGGL((k_stream<T, KC, NT, RT, VEC>), dim3((unsigned)grid), dim3(block), 0, s,
+    hipLaunchKernelGGL((k_stream<T, KC, NT, RT, VEC, IL>), dim3((unsigned)grid), dim3(block), 0, s,
                        static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C),
                        m, (int)n, (int)k, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
@@ -256,15 +301,20 @@ hipError_t run_stream(const void *A, const void *Bf, void *C, int64_t m, int64_t
 typedef hipError_t (*StreamFn)(const void *, const void *, void *, int64_t, int64_t, int64_t,
                                double, double, int64_t, int, int, int, hipStream_t);
 struct StreamEntry {
-    int KC, NT, RT, vec;
+    int KC, NT, RT, vec, il;
     StreamFn fn;
 };
 
 }  // namespace tsmm
 
 // Instantiation lists: every NT for RT = 1, NT <= 8 for RT = 2, NT <= 4 for
-// RT = 4 (accumulators stay within 128 registers).
-#define TSMM_SE(T, KC, NT, RT, V) {KC, NT, RT, V, &tsmm::run_stream<T, KC, NT, RT, V>},
+// RT = 4 (accumulators stay within 128 registers), NT <= 2 for RT = 8.
+// TSMM_SE_* instantiate the plain column order; TSMM_SI, TSMM_SIS (scalar
+// mapping) and TSMM_SEI*_* the interleaved order, where it applies
+// (NT >= VW).
+#define TSMM_SE(T, KC, NT, RT, V) {KC, NT, RT, V, 0, &tsmm::run_stream<T, KC, NT, RT, V, false>},
+#define TSMM_SI(T, KC, NT, RT) {KC, NT, RT, 1, 1, &tsmm::run_stream<T, KC, NT, RT, true, true>},
+#define TSMM_SIS(T, KC, NT, RT) {KC, NT, RT, 0, 1, &tsmm::run_stream<T, KC, NT, RT, false, true>},
 #define TSMM_SE_RT1(T, KC, V) \
     TSMM_SE(T, KC, 1, 1, V) TSMM_SE(T, KC, 2, 1, V) TSMM_SE(T, KC, 4, 1, V) TSMM_SE(T, KC, 8, 1, V) TSMM_SE(T, KC, 16, 1, V)
 #define TSMM_SE_RT2(T, KC, V) \
@@ -272,3 +322,16 @@ struct StreamEntry {
 #define TSMM_SE_RT4(T, KC, V) TSMM_SE(T, KC, 1, 4, V) TSMM_SE(T, KC, 2, 4, V) TSMM_SE(T, KC, 4, 4, V)
 #define TSMM_SE_RT8(T, KC, V) TSMM_SE(T, KC, 1, 8, V) TSMM_SE(T, KC, 2, 8, V)
 #define TSMM_SE_ALL(T, KC, V) TSMM_SE_RT1(T, KC, V) TSMM_SE_RT2(T, KC, V) TSMM_SE_RT4(T, KC, V)
+// interleaved: binary64 pairs (NT >= 2), binary32 quads (NT >= 4)
+#define TSMM_SEI64_RT1(KC) TSMM_SI(double, KC, 2, 1) TSMM_SI(double, KC, 4, 1) TSMM_SI(double, KC, 8, 1) \
+    TSMM_SI(double, KC, 16, 1)
+#define TSMM_SEI64_RT2(KC) TSMM_SI(double, KC, 2, 2) TSMM_SI(double, KC, 4, 2) TSMM_SI(double, KC, 8, 2)
+#define TSMM_SEI64_RT4(KC) TSMM_SI(double, KC, 2, 4) TSMM_SI(double, KC, 4, 4)
+#define TSMM_SEI64_ALL(KC) TSMM_SEI64_RT1(KC) TSMM_SEI64_RT2(KC) TSMM_SEI64_RT4(KC)
+#define TSMM_SEI32_RT1(KC) TSMM_SI(float, KC, 4, 1) TSMM_SI(float, KC, 8, 1) TSMM_SI(float, KC, 16, 1)
+#define TSMM_SEI32_RT2(KC) TSMM_SI(float, KC, 4, 2) TSMM_SI(float, KC, 8, 2)
+#define TSMM_SEI32_RT4(KC) TSMM_SI(float, KC, 4, 4)
+#define TSMM_SEI32_ALL(KC) TSMM_SEI32_RT1(KC) TSMM_SEI32_RT2(KC) TSMM_SEI32_RT4(KC)
+#define TSMM_SIS64_RT1(KC) TSMM_SIS(double, KC, 2, 1) TSMM_SIS(double, KC, 4, 1) TSMM_SIS(double, KC, 8, 1) \
+    TSMM_SIS(double, KC, 16, 1)
+#define TSMM_SIS32_RT1(KC) TSMM_SIS(float, KC, 4, 1) TSMM_SIS(float, KC, 8, 1) TSMM_SIS(float, KC, 16, 1)

@@ -14,11 +14,18 @@ static const StreamEntry kF64[] = {
     TSMM_SE_RT8(double, 16, true) TSMM_SE_ALL(double, 32, true)
     TSMM_SE_ALL(double, 64, true) TSMM_SE_RT1(double, 128, true) TSMM_SE_RT2(double, 128, true)
     TSMM_SE_RT1(double, 256, true) TSMM_SE_RT2(double, 256, true)
+    // interleaved columns (n even): scalar mapping
+    TSMM_SIS64_RT1(4) TSMM_SIS64_RT1(8) TSMM_SIS64_RT1(16) TSMM_SIS64_RT1(32) TSMM_SIS64_RT1(64)
+    TSMM_SIS64_RT1(128) TSMM_SIS64_RT1(256) TSMM_SIS(double, 4, 2, 2) TSMM_SIS(double, 4, 4, 2)
+    TSMM_SIS(double, 4, 2, 4)
+    // vector mapping with interleaved columns (n even)
+    TSMM_SEI64_ALL(8) TSMM_SEI64_ALL(16) TSMM_SI(double, 8, 2, 8) TSMM_SI(double, 16, 2, 8) TSMM_SEI64_ALL(32)
+    TSMM_SEI64_ALL(64) TSMM_SEI64_RT1(128) TSMM_SEI64_RT2(128) TSMM_SEI64_RT1(256) TSMM_SEI64_RT2(256)
 };
 
-StreamFn find_stream_f64(int KC, int NT, int RT, bool vec) {
+StreamFn find_stream_f64(int KC, int NT, int RT, bool vec, bool il) {
     for (const StreamEntry &e : kF64)
-        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec) return e.fn;
+        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec && e.il == (int)il) return e.fn;
     return nullptr;
 }
 

@@ -271,11 +271,12 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
         const bool vec = vec_mapping(p.dtype, p.k, KC);
         // column groups: the smallest split whose B slice fits the LDS budget
         t.nsplit = 1;
-        while ((size_t)(KC / 4) * (NT / t.nsplit) * 64 * elem_bytes(p.dtype) > kLdsBudget && t.nsplit < NT)
+        const int pg = frag4_pg(p.dtype, NT, p.n);  // column groups keep whole interleave groups
+        while ((size_t)(KC / 4) * (NT / t.nsplit) * 64 * elem_bytes(p.dtype) > kLdsBudget && t.nsplit < NT / pg)
             t.nsplit *= 2;
         const int NTs = NT / t.nsplit;
         t.rows_per_wave = w <= 64 ? 4 : (w <= 256 ? 2 : 1);
-        while (t.rows_per_wave > 1 && !stream_variant_exists(p.dtype, KC, NTs, t.rows_per_wave, vec))
+        while (t.rows_per_wave > 1 && !stream_variant_exists(p.dtype, KC, NTs, t.rows_per_wave, vec, pg > 1))
             t.rows_per_wave /= 2;
         t.wg_per_cu = 8;
         break;
@@ -359,7 +360,11 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         p.vec = vec_mapping(p.dtype, p.k, p.KC);
         if (t.nsplit > p.NT) return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d > %d column tiles", t.nsplit, p.NT);
         const int NTs = p.NT / t.nsplit;
-        if (!stream_variant_exists(p.dtype, p.KC, NTs, t.rows_per_wave, p.vec))
+        const int pg = frag4_pg(p.dtype, p.NT, p.n);
+        if (NTs % pg != 0)
+            return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d splits the %d-tile column interleave groups", t.nsplit,
+                        pg);
+        if (!stream_variant_exists(p.dtype, p.KC, NTs, t.rows_per_wave, p.vec, pg > 1))
             return fail(TSMM_ERROR_NOT_SUPPORTED, "no stream kernel for KC=%d NT=%d RT=%d vec=%d", p.KC, NTs,
                         t.rows_per_wave, (int)p.vec);
         // Eq. (2) analogue: the workgroup's slice of packed B must fit the LDS
@@ -591,6 +596,7 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
         L.NT = ntclass(n);
         if (L.KC && L.NT) {
             L.vec = vec_mapping(dtype, k, L.KC);
+            L.pg = frag4_pg(dtype, L.NT, n);
             L.off_frag = off;
             off = align(off + (size_t)L.KC * L.NT * 16 * eb);
         }
@@ -619,7 +625,7 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
                                  mode != TSMM_MODE_NATIVE ? reinterpret_cast<int32_t *>(base + L.off_exps) : nullptr,
                                  k, n, L.KC, L.NT, terms, s);
         else
-            e = launch_pack_frag4(dtype, B, base + L.off_frag, k, n, L.KC, L.NT, L.vec, s);
+            e = launch_pack_frag4(dtype, B, base + L.off_frag, k, n, L.KC, L.NT, L.vec, L.pg, s);
     }
     if (e == hipSuccess && L.wide_KC)  // after the split planes it reads
         e = launch_pack_wide(B, terms > 0 ? base + L.off_planes : nullptr, base + L.off_wide, k, n, L.wide_KC,
@@ -814,8 +820,7 @@ void tsmm_plan_destroy(tsmm_plan_t p) {
     if (p->owns_workspace && p->workspace) (void)hipFree(p->workspace);
     if (p->d_desc) (void)hipFree(p->d_desc);
     if (p->d_inst_start) (void)hipFree(p->d_inst_start);
-    if (p->d_wg_begin) (void)hipFree(p->d_wg_begin);
-    if (p->d_wg_inst) (void)hipFree(p->d_wg_inst);
+    if (p->d_ctr) (void)hipFree(p->d_ctr);
     if (p->h_desc) (void)hipHostFree(p->h_desc);
     delete p;
 }
@@ -847,11 +852,13 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
     const char *base = static_cast<const char *>(packed->dev);
     const void *Brow = p->layout == TSMM_OP_N ? base + packed->L.off_rowmajor : nullptr;
     int kernel = p->tile.kernel;
-    if (kernel == TSMM_KERNEL_STREAM && p->vec && (reinterpret_cast<uintptr_t>(A) & 15))
-        kernel = TSMM_KERNEL_SIMPLE;  // vector loads need 16-byte aligned rows
+    if (kernel == TSMM_KERNEL_STREAM && ((p->vec && (reinterpret_cast<uintptr_t>(A) & 15)) ||
+                                         (frag4_pg(p->dtype, p->NT, p->n) > 1 && (reinterpret_cast<uintptr_t>(C) & 15))))
+        kernel = TSMM_KERNEL_SIMPLE;  // vector accesses need 16-byte aligned rows
     switch (kernel) {
     case TSMM_KERNEL_STREAM:
-        e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec, A,
+        e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec,
+                          frag4_pg(p->dtype, p->NT, p->n) > 1, A,
                           base + packed->L.off_frag, C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, p->NT,
                           p->tile.nsplit, s);
         break;
@@ -955,24 +962,34 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
     }
     p->order.resize(count);
     for (int64_t b = 0; b < count; ++b) p->order[b] = b;
-    std::stable_sort(p->order.begin(), p->order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+    // instances of one kernel variant (k class, n class, k-slot mapping) next
+    // to each other, longest first within a variant: the workgroups that
+    // share an XCD then mostly run the same code on the same B classes
+    auto variant = [&](int64_t b) {
+        const int KC = dtype == TSMM_BF16 ? kclass32(k[b]) : kclass4(k[b]);
+        const bool vec = dtype == TSMM_BF16 ? (k[b] % 8 == 0) : vec_mapping(dtype, k[b], KC);
+        return std::make_tuple(KC, ntclass(n[b]), vec);
+    };
+    std::stable_sort(p->order.begin(), p->order.end(), [&](int64_t x, int64_t y) {
+        const auto vx = variant(x), vy = variant(y);
+        return vx != vy ? vx < vy : cost[x] > cost[y];
+    });
 
-    // work-tile prefix counts in execution order
+    // chunk prefix counts in execution order
     std::vector<int64_t> inst_start(count + 1, 0);
-    std::vector<double> tile_cost(count);
     for (int64_t e = 0; e < count; ++e) {
         const BatchedInstance &I = p->inst[p->order[e]];
-        const int64_t tiles = (I.m + kBatchRows - 1) / kBatchRows;
-        inst_start[e + 1] = inst_start[e] + tiles;
-        tile_cost[e] = (double)kBatchRows * (double)(I.k * sa + I.n * 4) + 2048.0;
+        inst_start[e + 1] = inst_start[e] + (I.m + kBatchChunk - 1) / kBatchChunk;
     }
     p->n_work = inst_start[count];
+    if (p->n_work >= (int64_t)1 << 31) return fail(TSMM_ERROR_NOT_SUPPORTED, "batch too large (2^31 chunks)");
     for (const BatchedInstance &I : p->inst) {
         const int KC = dtype == TSMM_BF16 ? kclass32(I.k) : kclass4(I.k);
         p->batch_lds = std::max(p->batch_lds, batched_lds_bytes(dtype, KC, ntclass(I.n)));
     }
     // the batched kernel's fixed workgroup (kBatchWaves wavefronts), one per
-    // compute unit (two wavefronts per SIMD)
+    // compute unit (two wavefronts per SIMD); chunks are handed out at run
+    // time, so the grid only needs to fill the device
     const int waves = kBatchWaves;
     p->tile = tsmm_tile{TSMM_KERNEL_STREAM, 0, waves, 1, 1, 1};
     p->block = 64 * waves;
@@ -980,43 +997,11 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
                                                                 p->n_work));
     p->grid = grid;
 
-    // contiguous cost-balanced partition of the work-tile sequence: workgroup
-    // w starts at the first tile whose preceding cost reaches w/grid of the
-    // total (tiles of one instance all cost the same)
-    double total = 0.0;
-    for (int64_t e = 0; e < count; ++e) total += tile_cost[e] * (double)(inst_start[e + 1] - inst_start[e]);
-    std::vector<int64_t> wg_begin(grid + 1, p->n_work);
-    std::vector<int32_t> wg_inst(grid, (int32_t)(count - 1));
-    {
-        wg_begin[0] = 0;
-        int64_t w = 1;
-        double cum = 0.0;
-        for (int64_t e = 0; e < count && w < grid; ++e) {
-            const int64_t nt = inst_start[e + 1] - inst_start[e];
-            const double c = tile_cost[e];
-            while (w < grid && cum + (double)nt * c >= total * (double)w / (double)grid) {
-                const double need = total * (double)w / (double)grid - cum;
-                int64_t step = (int64_t)std::ceil(need / c);
-                step = std::max<int64_t>(0, std::min<int64_t>(nt, step));
-                wg_begin[w] = std::max(wg_begin[w - 1], inst_start[e] + step);
-                ++w;
-            }
-            cum += (double)nt * c;
-        }
-        wg_begin[grid] = p->n_work;
-        int64_t inst = 0;
-        for (int64_t w2 = 0; w2 < grid; ++w2) {
-            while (inst + 1 < count && wg_begin[w2] >= inst_start[inst + 1]) ++inst;
-            wg_inst[w2] = (int32_t)inst;
-        }
-    }
-
     hipError_t e1 = hipMalloc(&p->d_desc, sizeof(BatchDesc) * count);
     hipError_t e2 = hipMalloc(&p->d_inst_start, sizeof(int64_t) * (count + 1));
-    hipError_t e3 = hipMalloc(&p->d_wg_begin, sizeof(int64_t) * (grid + 1));
-    hipError_t e4 = hipMalloc(&p->d_wg_inst, sizeof(int32_t) * grid);
+    hipError_t e3 = hipMalloc(&p->d_ctr, sizeof(int32_t) * 2);
     hipError_t e5 = hipHostMalloc(&p->h_desc, sizeof(BatchDesc) * count, hipHostMallocDefault);
-    if (e1 || e2 || e3 || e4 || e5) {
+    if (e1 || e2 || e3 || e5) {
         tsmm_plan_destroy(p.release());
         return fail(TSMM_ERROR_OUT_OF_MEMORY, "batched plan allocation failed");
     }
@@ -1026,8 +1011,9 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
         return hip_fail(e, "batched kernel attributes");
     }
     e = hipMemcpy(p->d_inst_start, inst_start.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_wg_begin, wg_begin.data(), sizeof(int64_t) * (grid + 1), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_wg_inst, wg_inst.data(), sizeof(int32_t) * grid, hipMemcpyHostToDevice);
+    // the counters start at zero once; every launch leaves them at zero
+    if (e == hipSuccess) e = hipMemset(p->d_ctr, 0, sizeof(int32_t) * 2);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         tsmm_plan_destroy(p.release());
         return hip_fail(e, "batched plan upload");
@@ -1035,7 +1021,7 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
     p->m = 0;
     for (const BatchedInstance &I : p->inst) p->m += I.m;
     if (log_level() >= 1)
-        fprintf(stderr, "[tsmm] batched plan: %" PRId64 " instances, %" PRId64 " work tiles, grid %" PRId64 "\n",
+        fprintf(stderr, "[tsmm] batched plan: %" PRId64 " instances, %" PRId64 " chunks, grid %" PRId64 "\n",
                 count, p->n_work, grid);
     *out = p.release();
     return TSMM_SUCCESS;
@@ -1060,6 +1046,9 @@ tsmm_status tsmm_batched_bind(tsmm_plan_t p, const void *const *A, const tsmm_pa
         const bool vec = p->dtype == TSMM_BF16 ? (I.k % 8 == 0) : P->L.vec;
         if (vec && (reinterpret_cast<uintptr_t>(A[b]) & 15))
             return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": A must be 16-byte aligned", b);
+        const bool il = p->dtype == TSMM_F32 && P->L.pg > 1;
+        if (il && (reinterpret_cast<uintptr_t>(C[b]) & 15))
+            return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": C must be 16-byte aligned", b);
         BatchDesc &d = desc[e];
         memset(&d, 0, sizeof d);
         d.A = A[b];
@@ -1073,6 +1062,7 @@ tsmm_status tsmm_batched_bind(tsmm_plan_t p, const void *const *A, const tsmm_pa
         d.KC = P->L.KC;
         d.NT = P->L.NT;
         d.vec = vec ? 1 : 0;
+        d.il = il ? 1 : 0;
         if (d.alpha == 0.0 && I.m > 0)
             return fail(TSMM_ERROR_NOT_SUPPORTED, "instance %" PRId64 ": alpha == 0 in a batched plan", b);
     }
@@ -1102,10 +1092,8 @@ tsmm_status tsmm_execute_batched(tsmm_plan_t p, const void *const *A, const tsmm
     if (!p->bound) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan has no bound operands");
     if (p->n_work == 0) return TSMM_SUCCESS;
     hipError_t e = launch_batched(p->dtype, static_cast<const BatchDesc *>(p->d_desc),
-                                  static_cast<const int64_t *>(p->d_inst_start),
-                                  static_cast<const int64_t *>(p->d_wg_begin),
-                                  static_cast<const int32_t *>(p->d_wg_inst), p->grid, p->block, p->batch_lds,
-                                  p->stream);
+                                  static_cast<const int64_t *>(p->d_inst_start), p->n_work,
+                                  static_cast<int32_t *>(p->d_ctr), p->grid, p->block, p->batch_lds, p->stream);
     return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "batched launch");
 }
 
@@ -1124,10 +1112,8 @@ tsmm_status tsmm_graph_create_batched(tsmm_plan_t p, tsmm_graph_t *out) {
     if (e == hipSuccess && g) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = launch_batched(p->dtype, static_cast<const BatchDesc *>(p->d_desc),
-                                       static_cast<const int64_t *>(p->d_inst_start),
-                                       static_cast<const int64_t *>(p->d_wg_begin),
-                                       static_cast<const int32_t *>(p->d_wg_inst), p->grid, p->block, p->batch_lds,
-                                       cs);
+                                       static_cast<const int64_t *>(p->d_inst_start), p->n_work,
+                                       static_cast<int32_t *>(p->d_ctr), p->grid, p->block, p->batch_lds, cs);
         e = hipStreamEndCapture(cs, &g->graph);
         if (le != hipSuccess) e = le;
     }

@@ -33,8 +33,16 @@ namespace tsmm {
 //     col(s, q) = 4*s + q                                   (scalar mapping)
 // The vector mapping is used when k % VW == 0 and KC % (4*VW) == 0 (rows
 // stay 16-byte aligned and a vector never straddles the end of a row).
-// Packed B holds, for k-step s < KC/4, column tile t < NT and lane l,
-//     frag[(s*NT + t)*64 + l] = B[col(s, q)][16*t + j]   (0 outside k x n).
+// When NT >= VW and n % VW == 0 the columns of B are interleaved in groups of PG = VW column tiles (otherwise PG = 1): tile t,
+// lane column j holds
+// column
+//     colp(t, j) = 16*PG*(t / PG) + PG*j + t % PG,
+// so that a lane's accumulators of the PG tiles of a group are PG adjacent
+// columns of C (one 16-byte vector).  Packed B holds, for k-step s < KC/4,
+// column tile t < NT and lane l,
+//     frag[(s*NT + t)*64 + l] = B[col(s, q)][colp(t, j)]   (0 outside k x n).
+// A plan that splits the tiles into column groups keeps whole interleave
+// groups in each (NT / nsplit a multiple of PG).
 //
 // The split-bfloat16 kernels use V_MFMA_F32_16X16X32_BF16: lane 16*q + j
 // supplies 8 consecutive k-slots 8q..8q+7 of a 32-wide k-chunk.  Packed B
@@ -58,6 +66,12 @@ constexpr int kMaxKC = 256;  // largest packed k class of the fragment kernels
 constexpr int kMaxNT = 16;   // largest number of 16-column tiles (n <= 256)
 
 inline int elem_bytes(tsmm_dtype d) { return d == TSMM_F64 ? 8 : (d == TSMM_F32 ? 4 : 2); }
+
+// Column interleave group of the 16x16x4 fragments (see above).
+inline int frag4_pg(tsmm_dtype d, int NT, int64_t n) {
+    const int vw = 16 / elem_bytes(d);
+    return (NT % vw == 0 && n % vw == 0) ? vw : 1;
+}
 
 // Smallest k class >= k for the 16x16x4 kernels (0 if k > kMaxKC).
 inline int kclass4(int64_t k) {
@@ -87,6 +101,7 @@ inline bool vec_mapping(tsmm_dtype d, int64_t k, int KC) {
 struct PackedLayout {
     int KC = 0, NT = 0;         // fragment class (0: no fragment copy)
     bool vec = false;           // vector k-slot mapping (16x16x4 kernels)
+    int pg = 1;                 // column interleave group (16x16x4 kernels)
     int terms = 0;              // split planes (0: not a split mode)
     size_t off_rowmajor = 0;    // k*n elements of the input type
     size_t off_frag = 0;        // 16x16x4 fragments, or bf16 fragments
@@ -127,12 +142,12 @@ struct alignas(16) BatchDesc {
     int64_t m;
     int32_t k, n;
     int32_t KC, NT;
-    int32_t vec, pad;
+    int32_t vec, il;  // vector k-slot mapping; interleaved columns (binary32)
 };
 
-// Rows of one batched work tile (the unit of the host's schedule) and
+// Rows of one batched chunk (the unit of the dynamic schedule) and
 // wavefronts per workgroup of the batched kernel.
-constexpr int kBatchRows = 128;
+constexpr int kBatchChunk = 4096;
 constexpr int kBatchWaves = 8;
 
 }  // namespace tsmm
@@ -161,12 +176,11 @@ struct tsmm_plan_s {
     bool batched = false;
     std::vector<tsmm::BatchedInstance> inst;  // caller order
     std::vector<int64_t> order;               // execution position -> caller index
-    int64_t n_work = 0;                       // work tiles over all instances
+    int64_t n_work = 0;                       // chunks over all instances
     void *d_desc = nullptr;                   // device BatchDesc[count] (execution order)
     void *h_desc = nullptr;                   // pinned staging BatchDesc[count]
-    void *d_inst_start = nullptr;             // device int64[count + 1]: first work tile
-    void *d_wg_begin = nullptr;               // device int64[grid + 1]: work-tile range
-    void *d_wg_inst = nullptr;                // device int32[grid]: instance of wg_begin
+    void *d_inst_start = nullptr;             // device int64[count + 1]: first chunk
+    void *d_ctr = nullptr;                    // device int32[2]: work counter, finished workgroups
     size_t batch_lds = 0;                     // dynamic LDS of the batched launch
     bool bound = false;
     std::vector<tsmm::BatchDesc> bound_desc;
@@ -184,7 +198,7 @@ namespace tsmm {
 
 // Pack B (k x n row-major) into the 16x16x4 fragment order.
 hipError_t launch_pack_frag4(tsmm_dtype dt, const void *B, void *frag, int64_t k, int64_t n,
-                             int KC, int NT, bool vec, hipStream_t s);
+                             int KC, int NT, bool vec, int pg, hipStream_t s);
 // Split-bf16 pack: column exponents, row-major planes and fragments.
 // For TSMM_BF16 inputs (terms == 1) B is bf16 and no scaling is applied.
 hipError_t launch_pack_bf16(tsmm_dtype dt, const void *B, void *frag, void *planes, int32_t *exps,
@@ -217,10 +231,11 @@ hipError_t launch_simple_t(tsmm_dtype dt, const void *A, const void *B, void *C,
 // op N streaming, binary64 / binary32 16x16x4 fragments.
 // NT: column tiles per workgroup; nt_total = NT * nsplit column tiles of
 // the packed B.  With nsplit > 1, grid must be a multiple of 8 * nsplit.
-hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, const void *A,
+// il: the fragments interleave columns (pg > 1).
+hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il, const void *A,
                          const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, double alpha,
                          double beta, int64_t grid, int block, int nt_total, int nsplit, hipStream_t s);
-bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec);
+bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il);
 
 // op N, split-bf16 (terms 2 or 3 of binary32 A and B; products 3 or 6) or
 // plain bf16 inputs (terms == 1).
@@ -251,8 +266,10 @@ bool splitk_variant_exists(int MT, int NT, int RG);
 // with at least that size.  block must be 256.
 size_t batched_lds_bytes(tsmm_dtype dt, int KC, int NT);
 hipError_t prepare_batched(tsmm_dtype dt, size_t lds_bytes);
-hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *inst_start,
-                          const int64_t *wg_begin, const int32_t *wg_inst, int64_t grid, int block,
-                          size_t lds_bytes, hipStream_t s);
+// chunk_start: device int64[count + 1], first chunk of each instance (in
+// descriptor order); ctr: device int32[2], zero before the first launch
+// (every launch leaves it zero again).
+hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *chunk_start, int64_t nchunks,
+                          int32_t *ctr, int64_t grid, int block, size_t lds_bytes, hipStream_t s);
 
 }  // namespace tsmm

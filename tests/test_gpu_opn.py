@@ -91,6 +91,28 @@ def test_f32_native(m, k, n):
     assert np.array_equal(C2, oracle.gemm_n(Ai, Bi, Ci, 1.5, 0.5))
 
 
+@pytest.mark.parametrize("dtype,m,k,n", [(torch.float64, 777, 32, 34), (torch.float64, 1000, 64, 100),
+                                         (torch.float64, 515, 16, 126), (torch.float64, 300, 8, 66),
+                                         (torch.float32, 777, 32, 64), (torch.float32, 1000, 64, 96),
+                                         (torch.float32, 515, 16, 124), (torch.float32, 300, 128, 68),
+                                         (torch.float32, 301, 40, 66)])
+def test_interleaved_columns(dtype, m, k, n):
+    # n a multiple of the 16-byte vector width and at least that many column
+    # tiles: the fragments interleave columns and C moves in vectors, also
+    # for a ragged last group (n = 66 binary32: plain order)
+    seed = 4000 + m + k + n
+    f32 = dtype == torch.float32
+    A = I.host_ints((m, k), seed, 1, -4, 4, dtype=np.float32 if f32 else np.float64)
+    B = I.host_ints((k, n), seed, 2, -4, 4, dtype=np.float32 if f32 else np.float64)
+    C0 = I.host_ints((m, n), seed, 3, -4, 4, dtype=np.float32 if f32 else np.float64)
+    C, p = run(A, B, C0, 1.5, 0.5, dtype=dtype, tile=dict(kernel=T.KERNEL_STREAM))
+    assert np.array_equal(C, oracle.gemm_n(A, B, C0, 1.5, 0.5))
+    A = I.host_uniform((m, k), seed, 4, dtype=np.float32 if f32 else np.float64)
+    B = I.host_uniform((k, n), seed, 5, dtype=np.float32 if f32 else np.float64)
+    C, _ = run(A, B, None, -0.75, 0.0, dtype=dtype, tile=dict(kernel=T.KERNEL_STREAM))
+    assert_normwise(C, oracle.gemm_n(A, B, None, -0.75, 0.0), 1e-6 if f32 else 1e-12)
+
+
 @pytest.mark.parametrize("k,n", [(8, 8), (32, 32), (128, 128)])
 def test_every_tile_gives_the_same_bits(k, n):
     m = 2000
