@@ -56,7 +56,7 @@ __device__ __forceinline__ void segment_f32(const BatchDesc &d, int64_t row_a, i
 }
 
 // The same for a bfloat16 instance (k_bf16.h row steps, one product).
-template <int KC, int NT, bool VEC>
+template <int KC, int NT, bool VEC, bool IL>
 __device__ __forceinline__ void segment_bf16(const BatchDesc &d, int64_t row_a, int64_t row_b,
                                              const u16x8 *__restrict__ sB, int wave) {
     constexpr int RT = batch_rt_bf16<KC, NT>();
@@ -72,15 +72,15 @@ __device__ __forceinline__ void segment_bf16(const BatchDesc &d, int64_t row_a, 
     RawA<false, RT, KC / 32> x0, x1;
     bf16_load_step<uint16_t, KC, RT, 1, VEC>(A, row_b, k, t, j, q, x0);
     for (; t < tend; t += 2 * tstride) {
-        bf16_step<uint16_t, KC, NT, RT, 1, VEC, CPRE>(A, sB, NT, nullptr, C, row_b, n, k, d.alpha, d.beta, 0, t,
-                                                      t + tstride, j, q, lane, x0, x1);
-        bf16_step<uint16_t, KC, NT, RT, 1, VEC, CPRE>(A, sB, NT, nullptr, C, row_b, n, k, d.alpha, d.beta, 0,
-                                                      t + tstride, t + 2 * tstride, j, q, lane, x1, x0);
+        bf16_step<uint16_t, KC, NT, RT, 1, VEC, IL, CPRE>(A, sB, NT, nullptr, C, row_b, n, k, d.alpha, d.beta, 0,
+                                                          t, t + tstride, j, q, lane, x0, x1);
+        bf16_step<uint16_t, KC, NT, RT, 1, VEC, IL, CPRE>(A, sB, NT, nullptr, C, row_b, n, k, d.alpha, d.beta, 0,
+                                                          t + tstride, t + 2 * tstride, j, q, lane, x1, x0);
     }
 }
 
-// binary32 with n % 4 == 0 and at least 4 column tiles uses the
-// interleaved column order (16-byte C vectors)
+// n % 4 == 0 and at least 4 column tiles: interleaved column order
+// (16-byte C vectors)
 #define TSMM_CASE_NT(BODY, KC, V)                                                                  \
     switch (d.NT) {                                                                                \
     case 1: BODY<KC, 1, V, false>(d, row_a, row_b, sB, wave); break;                               \
@@ -93,14 +93,6 @@ __device__ __forceinline__ void segment_bf16(const BatchDesc &d, int64_t row_a, 
         if (d.il) BODY<KC, 8, V, true>(d, row_a, row_b, sB, wave);                                 \
         else BODY<KC, 8, V, false>(d, row_a, row_b, sB, wave);                                     \
         break;                                                                                     \
-    }
-
-#define TSMM_CASE_NT_BF16(BODY, KC, V)                          \
-    switch (d.NT) {                                             \
-    case 1: BODY<KC, 1, V>(d, row_a, row_b, sB, wave); break;   \
-    case 2: BODY<KC, 2, V>(d, row_a, row_b, sB, wave); break;   \
-    case 4: BODY<KC, 4, V>(d, row_a, row_b, sB, wave); break;   \
-    default: BODY<KC, 8, V>(d, row_a, row_b, sB, wave); break;  \
     }
 
 __device__ __forceinline__ void run_segment_f32(const BatchDesc &d, int64_t row_a, int64_t row_b, const float *sB,
@@ -128,15 +120,15 @@ __device__ __forceinline__ void run_segment_bf16(const BatchDesc &d, int64_t row
                                                  int wave) {
     if (d.vec) {
         switch (d.KC) {
-        case 32: TSMM_CASE_NT_BF16(segment_bf16, 32, true) break;
-        case 64: TSMM_CASE_NT_BF16(segment_bf16, 64, true) break;
-        default: TSMM_CASE_NT_BF16(segment_bf16, 128, true) break;
+        case 32: TSMM_CASE_NT(segment_bf16, 32, true) break;
+        case 64: TSMM_CASE_NT(segment_bf16, 64, true) break;
+        default: TSMM_CASE_NT(segment_bf16, 128, true) break;
         }
     } else {
         switch (d.KC) {
-        case 32: TSMM_CASE_NT_BF16(segment_bf16, 32, false) break;
-        case 64: TSMM_CASE_NT_BF16(segment_bf16, 64, false) break;
-        default: TSMM_CASE_NT_BF16(segment_bf16, 128, false) break;
+        case 32: TSMM_CASE_NT(segment_bf16, 32, false) break;
+        case 64: TSMM_CASE_NT(segment_bf16, 64, false) break;
+        default: TSMM_CASE_NT(segment_bf16, 128, false) break;
         }
     }
 }

@@ -137,7 +137,7 @@ __device__ __forceinline__ void bf16_load_step(const TA *__restrict__ A, int64_t
 
 // One row step: products of tiles t.. from x_use while tiles tnext.. load
 // into x_load; C is read through a resource that is empty when beta == 0.
-template <typename TA, int KC, int NT, int RT, int PROD, bool VEC, bool CPRE = true>
+template <typename TA, int KC, int NT, int RT, int PROD, bool VEC, bool IL = false, bool CPRE = true>
 __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 *__restrict__ Bsrc, int bstride,
                                           const int32_t *__restrict__ exps, float *__restrict__ C, int64_t m, int n,
                                           int k, double alpha, double beta, int col0, int64_t t, int64_t tnext,
@@ -156,15 +156,37 @@ __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 
         rc[rt] = make_rsrc(C + row0 * n + col0, bytes);
         rl[rt] = make_rsrc(C + row0 * n + col0, beta != 0.0 ? bytes : 0);
     }
-    auto coff = [=](int tt, int r) { return (col0 + 16 * tt + j < n) ? ((4 * q + r) * n + 16 * tt + j) * 4 : kOOB; };
+    // Interleaved columns (IL, bfloat16 inputs with n % 4 == 0; the
+    // fragment order of tsmm_internal.h): tile tt of lane j is column
+    // colp(tt) of the group, a lane holds 4 adjacent columns in the 4 tiles
+    // of a group, and C moves in 16-byte vectors.
+    constexpr int PG = IL ? 4 : 1;
+    static_assert(!IL || (PROD == 1 && NT % 4 == 0), "interleave: bfloat16 inputs, whole groups");
+    auto colp = [=](int tt) { return 16 * PG * (tt / PG) + PG * j + tt % PG; };
+    auto coff = [=](int tt, int r) { return (col0 + colp(tt) < n) ? ((4 * q + r) * n + colp(tt)) * 4 : kOOB; };
+    auto voff = [=](int g, int r) {
+        return (col0 + colp(PG * g) < n) ? ((4 * q + r) * n + colp(PG * g)) * 4 : kOOB;
+    };
     float cv[RT][NT][4];
     if constexpr (CPRE) {
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RT; ++rt) {
+            if constexpr (IL) {
 #pragma unroll
-            for (int tt = 0; tt < NT; ++tt)
+                for (int g = 0; g < NT / PG; ++g)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<float>::load1(rl[rt], coff(tt, r));
+                    for (int r = 0; r < 4; ++r) {
+                        const f4v v = BufIO<float>::load_vec(rl[rt], voff(g, r));
+#pragma unroll
+                        for (int i = 0; i < PG; ++i) cv[rt][PG * g + i][r] = v[i];
+                    }
+            } else {
+#pragma unroll
+                for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) cv[rt][tt][r] = BufIO<float>::load1(rl[rt], coff(tt, r));
+            }
+        }
     }
     bf16_load_step<TA, KC, RT, PROD, VEC>(A, m, k, tnext, j, q, x_load);
     __builtin_amdgcn_sched_barrier(0);
@@ -213,28 +235,50 @@ __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 
     }
     __builtin_amdgcn_sched_barrier(0);
 
-#pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-        const int col = col0 + 16 * tt + j;
-        const int e = (PROD > 1 && col < n) ? exps[col] : 0;
+    if constexpr (IL) {
+        // bfloat16 inputs: one accumulator, no column scale
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                // without the C prefetch, C is read here (beta != 0 only)
-                if constexpr (!CPRE) cv[rt][tt][r] = beta != 0.0 ? BufIO<float>::load1(rl[rt], coff(tt, r)) : 0.0f;
-                double sacc = (double)acc[rt][tt][r];
-                if constexpr (TWO_ACC) sacc = sacc + (double)acc2[rt][tt][r];
-                if constexpr (PROD > 1) sacc = __builtin_ldexp(sacc, e);
-                BufIO<float>::store1((float)epilogue(alpha, sacc, beta, (double)cv[rt][tt][r]), rc[rt], coff(tt, r));
-            }
+            for (int g = 0; g < NT / PG; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if constexpr (!CPRE) {
+                        const f4v v = beta != 0.0 ? BufIO<float>::load_vec(rl[rt], voff(g, r)) : f4v{};
+#pragma unroll
+                        for (int i = 0; i < PG; ++i) cv[rt][PG * g + i][r] = v[i];
+                    }
+                    f4v o;
+#pragma unroll
+                    for (int i = 0; i < PG; ++i)
+                        o[i] = (float)epilogue(alpha, (double)acc[rt][PG * g + i][r], beta, (double)cv[rt][PG * g + i][r]);
+                    BufIO<float>::store_vec(o, rc[rt], voff(g, r));
+                }
+    } else {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+            const int col = col0 + 16 * tt + j;
+            const int e = (PROD > 1 && col < n) ? exps[col] : 0;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    // without the C prefetch, C is read here (beta != 0 only)
+                    if constexpr (!CPRE) cv[rt][tt][r] = beta != 0.0 ? BufIO<float>::load1(rl[rt], coff(tt, r)) : 0.0f;
+                    double sacc = (double)acc[rt][tt][r];
+                    if constexpr (TWO_ACC) sacc = sacc + (double)acc2[rt][tt][r];
+                    if constexpr (PROD > 1) sacc = __builtin_ldexp(sacc, e);
+                    BufIO<float>::store1((float)epilogue(alpha, sacc, beta, (double)cv[rt][tt][r]), rc[rt],
+                                         coff(tt, r));
+                }
+        }
     }
 }
 
 // PROD: 1 (plain bf16), 3 (two terms) or 6 (three terms).  NT: column tiles
 // per workgroup (one column group of the nt_total tiles when nsplit > 1,
 // with the workgroup -> (row block, group) map of k_stream.h).
-template <typename TA, int KC, int NT, int RT, int PROD, bool VEC>
+template <typename TA, int KC, int NT, int RT, int PROD, bool VEC, bool IL>
 __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__ A,
                                                           const uint16_t *__restrict__ Bf,
                                                           const int32_t *__restrict__ exps,
@@ -285,18 +329,18 @@ __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__
     if (t >= ntile) return;
     bf16_load_step<TA, KC, RT, PROD, VEC>(A, m, k, t, j, q, x0);
     for (; t < ntile; t += 2 * tstride) {
-        bf16_step<TA, KC, NT, RT, PROD, VEC>(A, Bsrc, bstride, exps, C, m, n, k, alpha, beta, col0, t, t + tstride,
-                                             j, q, lane, x0, x1);
-        bf16_step<TA, KC, NT, RT, PROD, VEC>(A, Bsrc, bstride, exps, C, m, n, k, alpha, beta, col0, t + tstride,
-                                             t + 2 * tstride, j, q, lane, x1, x0);
+        bf16_step<TA, KC, NT, RT, PROD, VEC, IL>(A, Bsrc, bstride, exps, C, m, n, k, alpha, beta, col0, t,
+                                                 t + tstride, j, q, lane, x0, x1);
+        bf16_step<TA, KC, NT, RT, PROD, VEC, IL>(A, Bsrc, bstride, exps, C, m, n, k, alpha, beta, col0,
+                                                 t + tstride, t + 2 * tstride, j, q, lane, x1, x0);
     }
 }
 
-template <typename TA, int KC, int NT, int RT, int PROD, bool VEC>
+template <typename TA, int KC, int NT, int RT, int PROD, bool VEC, bool IL>
 hipError_t run_splitbf16(const void *A, const void *Bf, const int32_t *exps, void *C, int64_t m, int64_t n,
                          int64_t k, double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
                          hipStream_t s) {
-    hipLaunchKernelGGL((k_splitbf16<TA, KC, NT, RT, PROD, VEC>), dim3((unsigned)grid), dim3(block), 0, s,
+    hipLaunchKernelGGL((k_splitbf16<TA, KC, NT, RT, PROD, VEC, IL>), dim3((unsigned)grid), dim3(block), 0, s,
                        static_cast<const TA *>(A), static_cast<const uint16_t *>(Bf), exps, static_cast<float *>(C),
                        m, (int)n, (int)k, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
@@ -305,15 +349,19 @@ hipError_t run_splitbf16(const void *A, const void *Bf, const int32_t *exps, voi
 typedef hipError_t (*Bf16Fn)(const void *, const void *, const int32_t *, void *, int64_t, int64_t, int64_t,
                              double, double, int64_t, int, int, int, hipStream_t);
 struct Bf16Entry {
-    int KC, NT, RT, prod, vec;
+    int KC, NT, RT, prod, vec, il;
     Bf16Fn fn;
 };
 
 }  // namespace tsmm
 
-#define TSMM_BE(TA, KC, NT, RT, P, V) {KC, NT, RT, P, V, &tsmm::run_splitbf16<TA, KC, NT, RT, P, V>},
+#define TSMM_BE(TA, KC, NT, RT, P, V) {KC, NT, RT, P, V, 0, &tsmm::run_splitbf16<TA, KC, NT, RT, P, V, false>},
 #define TSMM_BE_NT(TA, KC, RT, P, V) \
     TSMM_BE(TA, KC, 1, RT, P, V) TSMM_BE(TA, KC, 2, RT, P, V) TSMM_BE(TA, KC, 4, RT, P, V) TSMM_BE(TA, KC, 8, RT, P, V) \
     TSMM_BE(TA, KC, 16, RT, P, V)
 #define TSMM_BE_KC(TA, RT, P, V) \
     TSMM_BE_NT(TA, 32, RT, P, V) TSMM_BE_NT(TA, 64, RT, P, V) TSMM_BE_NT(TA, 128, RT, P, V) TSMM_BE_NT(TA, 256, RT, P, V)
+// interleaved columns (bfloat16 inputs, NT >= 4)
+#define TSMM_BEI(KC, NT, RT, V) {KC, NT, RT, 1, V, 1, &tsmm::run_splitbf16<uint16_t, KC, NT, RT, 1, V, true>},
+#define TSMM_BEI_NT(KC, RT, V) TSMM_BEI(KC, 4, RT, V) TSMM_BEI(KC, 8, RT, V) TSMM_BEI(KC, 16, RT, V)
+#define TSMM_BEI_KC(RT, V) TSMM_BEI_NT(32, RT, V) TSMM_BEI_NT(64, RT, V) TSMM_BEI_NT(128, RT, V) TSMM_BEI_NT(256, RT, V)

@@ -10,9 +10,9 @@
 
 namespace tsmm {
 
-Bf16Fn find_bf16_x1(int KC, int NT, int RT, bool vec);
-Bf16Fn find_bf16_x3(int KC, int NT, int RT, bool vec);
-Bf16Fn find_bf16_x6(int KC, int NT, int RT, bool vec);
+Bf16Fn find_bf16_x1(int KC, int NT, int RT, bool vec, bool il);
+Bf16Fn find_bf16_x3(int KC, int NT, int RT, bool vec, bool il);
+Bf16Fn find_bf16_x6(int KC, int NT, int RT, bool vec, bool il);
 
 __global__ void k_col_exps(const float *__restrict__ B, int32_t *__restrict__ exps, int64_t k, int64_t n) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -37,12 +37,13 @@ __global__ void k_col_exps(const float *__restrict__ B, int32_t *__restrict__ ex
 template <bool SPLIT>
 __global__ void k_pack_bf16(const void *__restrict__ Bv, const int32_t *__restrict__ exps,
                             uint16_t *__restrict__ frag, uint16_t *__restrict__ planes, int64_t k, int64_t n,
-                            int NT, int terms) {
+                            int NT, int terms, int pg) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= k * n) return;
     const int64_t i = idx / n, jn = idx % n;
     const int c = (int)(i / 32), kk = (int)(i % 32), q = kk / 8, u = kk % 8;
-    const int t = (int)(jn / 16), jj = (int)(jn % 16);
+    // column jn sits in tile t, lane column jj (interleave group pg)
+    const int t = (int)(pg * (jn / (16 * pg)) + jn % pg), jj = (int)((jn % (16 * pg)) / pg);
     const int lane = 16 * q + jj;
     if constexpr (SPLIT) {
         float r = ldexpf(static_cast<const float *>(Bv)[idx], -exps[jn]);
@@ -67,7 +68,7 @@ __global__ void k_unpack_split(const uint16_t *__restrict__ planes, const int32_
 }
 
 hipError_t launch_pack_bf16(tsmm_dtype dt, const void *B, void *frag, void *planes, int32_t *exps, int64_t k,
-                            int64_t n, int KC, int NT, int terms, hipStream_t s) {
+                            int64_t n, int KC, int NT, int terms, int pg, hipStream_t s) {
     const size_t frag_bytes = (size_t)KC * NT * 16 * terms * 2;
     hipError_t e = hipMemsetAsync(frag, 0, frag_bytes, s);  // zero padding
     if (e != hipSuccess) return e;
@@ -79,10 +80,10 @@ hipError_t launch_pack_bf16(tsmm_dtype dt, const void *B, void *frag, void *plan
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pack_bf16<true>, dim3(blocks), dim3(256), 0, s, B, (const int32_t *)exps,
-                           static_cast<uint16_t *>(frag), static_cast<uint16_t *>(planes), k, n, NT, terms);
+                           static_cast<uint16_t *>(frag), static_cast<uint16_t *>(planes), k, n, NT, terms, 1);
     } else {
         hipLaunchKernelGGL(k_pack_bf16<false>, dim3(blocks), dim3(256), 0, s, B, (const int32_t *)nullptr,
-                           static_cast<uint16_t *>(frag), (uint16_t *)nullptr, k, n, NT, 1);
+                           static_cast<uint16_t *>(frag), (uint16_t *)nullptr, k, n, NT, 1, pg);
     }
     return hipGetLastError();
 }
@@ -95,23 +96,25 @@ hipError_t launch_unpack_split(const void *planes, const int32_t *exps, void *B_
     return hipGetLastError();
 }
 
-static Bf16Fn find_bf16(tsmm_dtype dt, int KC, int NT, int RT, int products, bool vec) {
-    if (dt == TSMM_BF16 && products == 1) return find_bf16_x1(KC, NT, RT, vec);
-    if (dt == TSMM_F32 && products == 3) return find_bf16_x3(KC, NT, RT, vec);
-    if (dt == TSMM_F32 && products == 6) return find_bf16_x6(KC, NT, RT, vec);
+static Bf16Fn find_bf16(tsmm_dtype dt, int KC, int NT, int RT, int products, bool vec, bool il) {
+    if (dt == TSMM_BF16 && products == 1) return find_bf16_x1(KC, NT, RT, vec, il);
+    if (dt == TSMM_F32 && products == 3) return find_bf16_x3(KC, NT, RT, vec, il);
+    if (dt == TSMM_F32 && products == 6) return find_bf16_x6(KC, NT, RT, vec, il);
     return nullptr;
 }
 
-bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int products) {
-    return find_bf16(dt, KC, NT, RT, products, true) != nullptr && find_bf16(dt, KC, NT, 1, products, false) != nullptr;
+bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int products, bool il) {
+    return find_bf16(dt, KC, NT, RT, products, true, il) != nullptr &&
+           find_bf16(dt, KC, NT, 1, products, false, il) != nullptr;
 }
 
-hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products, const void *A, const void *Bfrag,
-                            const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k, double alpha, double beta,
-                            int64_t grid, int block, int nt_total, int nsplit, hipStream_t s) {
+hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products, bool il, const void *A,
+                            const void *Bfrag, const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k,
+                            double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
+                            hipStream_t s) {
     const int vw = dt == TSMM_BF16 ? 8 : 4;  // elements per 16-byte vector
     const bool vec = (k % vw) == 0;
-    Bf16Fn fn = find_bf16(dt, KC, NT, vec ? RT : 1, products, vec);
+    Bf16Fn fn = find_bf16(dt, KC, NT, vec ? RT : 1, products, vec, il);
     if (!fn || nsplit < 1 || NT * nsplit != nt_total) return hipErrorInvalidValue;
     return fn(A, Bfrag, exps, C, m, n, k, alpha, beta, grid, block, nt_total, nsplit, s);
 }

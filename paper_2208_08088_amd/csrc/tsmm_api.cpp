@@ -283,12 +283,14 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
     }
     case TSMM_KERNEL_SPLITBF16: {
         const int KC = kclass32(p.k), NT = ntclass(p.n), terms = std::max(1, split_terms(p.dtype, p.mode));
+        const int pg = bfrag_pg(p.dtype, NT, p.n);
         t.nsplit = 1;
-        while ((size_t)(KC / 32) * (NT / t.nsplit) * terms * 64 * 16 > kLdsBudget && t.nsplit < NT) t.nsplit *= 2;
+        while ((size_t)(KC / 32) * (NT / t.nsplit) * terms * 64 * 16 > kLdsBudget && t.nsplit < NT / pg)
+            t.nsplit *= 2;
         const int NTs = NT / t.nsplit;
         t.rows_per_wave = KC * NTs <= 1024 ? 2 : 1;
         while (t.rows_per_wave > 1 &&
-               !splitbf16_variant_exists(p.dtype, KC, NTs, t.rows_per_wave, split_products(p.dtype, p.mode)))
+               !splitbf16_variant_exists(p.dtype, KC, NTs, t.rows_per_wave, split_products(p.dtype, p.mode), pg > 1))
             t.rows_per_wave /= 2;
         t.wg_per_cu = 4;
         break;
@@ -380,7 +382,11 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         p.vec = false;
         if (t.nsplit > p.NT) return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d > %d column tiles", t.nsplit, p.NT);
         const int NTs = p.NT / t.nsplit;
-        if (!splitbf16_variant_exists(p.dtype, p.KC, NTs, t.rows_per_wave, split_products(p.dtype, p.mode)))
+        const int pg = bfrag_pg(p.dtype, p.NT, p.n);
+        if (NTs % pg != 0)
+            return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d splits the %d-tile column interleave groups", t.nsplit,
+                        pg);
+        if (!splitbf16_variant_exists(p.dtype, p.KC, NTs, t.rows_per_wave, split_products(p.dtype, p.mode), pg > 1))
             return fail(TSMM_ERROR_NOT_SUPPORTED, "no split-bf16 kernel for KC=%d NT=%d RT=%d", p.KC, NTs,
                         t.rows_per_wave);
         p.grid = row_grid(p, t, cus);
@@ -581,6 +587,7 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
         L.KC = kclass32(k);
         L.NT = ntclass(n);
         L.terms = terms;
+        L.pg = bfrag_pg(dtype, L.NT, n);
         if (L.KC && L.NT) {
             L.off_frag = off;
             off = align(off + (size_t)L.KC * L.NT * 16 * terms * 2);
@@ -623,7 +630,7 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
             e = launch_pack_bf16(dtype, B, base + L.off_frag,
                                  mode != TSMM_MODE_NATIVE ? base + L.off_planes : nullptr,
                                  mode != TSMM_MODE_NATIVE ? reinterpret_cast<int32_t *>(base + L.off_exps) : nullptr,
-                                 k, n, L.KC, L.NT, terms, s);
+                                 k, n, L.KC, L.NT, terms, L.pg, s);
         else
             e = launch_pack_frag4(dtype, B, base + L.off_frag, k, n, L.KC, L.NT, L.vec, L.pg, s);
     }
@@ -870,19 +877,21 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
         e = launch_valu64(p->tile.rows_per_wave, static_cast<const double *>(A), static_cast<const double *>(Brow),
                           static_cast<double *>(C), p->m, p->n, p->k, alpha, beta, p->grid, s);
         break;
-    case TSMM_KERNEL_SPLITBF16:
-        if (reinterpret_cast<uintptr_t>(A) & 15) {
+    case TSMM_KERNEL_SPLITBF16: {
+        const bool il = bfrag_pg(p->dtype, p->NT, p->n) > 1;  // bfloat16 inputs only (NATIVE mode)
+        if ((reinterpret_cast<uintptr_t>(A) & 15) || (il && (reinterpret_cast<uintptr_t>(C) & 15))) {
             if (p->mode != TSMM_MODE_NATIVE)
                 return fail(TSMM_ERROR_INVALID_VALUE, "split-bf16 modes need a 16-byte aligned A");
             e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
             break;
         }
         e = launch_splitbf16(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave,
-                             split_products(p->dtype, p->mode), A, base + packed->L.off_frag,
+                             split_products(p->dtype, p->mode), il, A, base + packed->L.off_frag,
                              p->mode != TSMM_MODE_NATIVE ? reinterpret_cast<const int32_t *>(base + packed->L.off_exps)
                                                          : nullptr,
                              C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, p->NT, p->tile.nsplit, s);
         break;
+    }
     case TSMM_KERNEL_WIDE:
         if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(C)) & 15) {
             if (p->mode != TSMM_MODE_NATIVE)
@@ -1046,7 +1055,7 @@ tsmm_status tsmm_batched_bind(tsmm_plan_t p, const void *const *A, const tsmm_pa
         const bool vec = p->dtype == TSMM_BF16 ? (I.k % 8 == 0) : P->L.vec;
         if (vec && (reinterpret_cast<uintptr_t>(A[b]) & 15))
             return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": A must be 16-byte aligned", b);
-        const bool il = p->dtype == TSMM_F32 && P->L.pg > 1;
+        const bool il = P->L.pg > 1;
         if (il && (reinterpret_cast<uintptr_t>(C[b]) & 15))
             return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": C must be 16-byte aligned", b);
         BatchDesc &d = desc[e];

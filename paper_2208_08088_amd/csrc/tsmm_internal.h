@@ -50,7 +50,10 @@ namespace tsmm {
 //     bfrag[(((c*NT + t)*P + p)*64 + l)*8 + u] = plane p of
 //         B[32c + 8q + u][16t + j] * 2^-e_(16t+j)
 // where e_j is the column's power-of-two exponent (1 <= max|B[:,j]|*2^-e_j
-// < 2) and planes are the residual split hi, mid, lo.
+// < 2) and planes are the residual split hi, mid, lo.  For bfloat16 inputs
+// with NT >= 4 and n % 4 == 0 the columns are interleaved in groups of 4
+// tiles as above (16t + j -> colp(t, j) with PG = 4), so that binary32 C
+// moves in 16-byte vectors; the split planes keep the plain order.
 //
 // The wide kernels (k_wide.hip; binary32 B with n = 128 or 256, k <= 256,
 // k % 8 == 0) use the 32x32 products.  Their image holds, per 32-row chunk
@@ -72,6 +75,8 @@ inline int frag4_pg(tsmm_dtype d, int NT, int64_t n) {
     const int vw = 16 / elem_bytes(d);
     return (NT % vw == 0 && n % vw == 0) ? vw : 1;
 }
+// Column interleave group of the bfloat16 fragments: bfloat16 inputs only.
+inline int bfrag_pg(tsmm_dtype d, int NT, int64_t n) { return (d == TSMM_BF16 && NT % 4 == 0 && n % 4 == 0) ? 4 : 1; }
 
 // Smallest k class >= k for the 16x16x4 kernels (0 if k > kMaxKC).
 inline int kclass4(int64_t k) {
@@ -201,8 +206,9 @@ hipError_t launch_pack_frag4(tsmm_dtype dt, const void *B, void *frag, int64_t k
                              int KC, int NT, bool vec, int pg, hipStream_t s);
 // Split-bf16 pack: column exponents, row-major planes and fragments.
 // For TSMM_BF16 inputs (terms == 1) B is bf16 and no scaling is applied.
+// pg: column interleave group of the fragments (4 or 1; bfloat16 inputs).
 hipError_t launch_pack_bf16(tsmm_dtype dt, const void *B, void *frag, void *planes, int32_t *exps,
-                            int64_t k, int64_t n, int KC, int NT, int terms, hipStream_t s);
+                            int64_t k, int64_t n, int KC, int NT, int terms, int pg, hipStream_t s);
 // Unpack a split handle: B_out[i][j] = (sum of planes) * 2^e_j (binary32).
 hipError_t launch_unpack_split(const void *planes, const int32_t *exps, void *B_out, int64_t k,
                                int64_t n, int terms, hipStream_t s);
@@ -239,11 +245,11 @@ bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool
 
 // op N, split-bf16 (terms 2 or 3 of binary32 A and B; products 3 or 6) or
 // plain bf16 inputs (terms == 1).
-hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products, const void *A,
+hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products, bool il, const void *A,
                             const void *Bfrag, const int32_t *exps, void *C, int64_t m, int64_t n,
                             int64_t k, double alpha, double beta, int64_t grid, int block, int nt_total,
                             int nsplit, hipStream_t s);
-bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int products);
+bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int products, bool il);
 
 // op N binary64 on the vector ALU: NB columns per wavefront (16, 32),
 // B row-major; requires n % NB == 0 and k % 8 == 0.  grid = 64-row tiles

@@ -121,6 +121,31 @@ def test_bf16_inputs(m, k, n):
     assert np.array_equal(host(C), oracle.gemm_n(Ai, Bi))
 
 
+@pytest.mark.parametrize("m,k,n", [(777, 64, 64), (300, 40, 100), (515, 16, 68), (301, 32, 66), (129, 128, 128)])
+def test_bf16_inputs_interleaved_columns(m, k, n):
+    # bfloat16 fragments interleave columns in groups of four tiles when
+    # n % 4 == 0 (binary32 C moves in 16-byte vectors); n = 66 keeps the
+    # plain order.  Small integers: every result is exact.
+    seed = 90 + m + k + n
+    Ai = I.f32_to_bf16_bits(I.host_ints((m, k), seed, 1, -8, 8, dtype=np.float32))
+    Bi = I.f32_to_bf16_bits(I.host_ints((k, n), seed, 2, -8, 8, dtype=np.float32))
+    C0 = I.host_ints((m, n), seed, 3, -8, 8, dtype=np.float32)
+    want = oracle.gemm_n(Ai, Bi, C0, 1.5, 0.5)
+    announce("bf16 interleave", m, n, k)
+    p = T.plan(m, n, k, "N", torch.bfloat16)
+    p.set_tile(kernel=T.KERNEL_SPLITBF16)
+    pk = T.pack(dev_bf16_bits(Bi))
+    C = dev(C0, torch.float32)
+    T.execute(p, dev_bf16_bits(Ai), pk, C, 1.5, 0.5)
+    assert np.array_equal(host(C), want)
+    # C at an address that is not 16-byte aligned (the kernel falls back)
+    buf = torch.zeros(m * n + 1, dtype=torch.float32, device="cuda")
+    Cu = buf[1:].view(m, n)
+    Cu.copy_(dev(C0, torch.float32))
+    T.execute(p, dev_bf16_bits(Ai), pk, Cu, 1.5, 0.5)
+    assert np.array_equal(host(Cu), want)
+
+
 def test_large_precision_sampled():
     # 2^20 rows of the precision workload (k = n = 256), sampled rows
     m, k, n = 1 << 20, 256, 256
