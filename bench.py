@@ -352,7 +352,9 @@ def main():
         ach, peak, unit = c["bytes"] / ms / 1e6, HBM_PEAK_GBS, "GB/s"
     else:
         ach, peak, unit = c["flops"] / ms / 1e9, PEAK_TFLOPS["f64"], "TFLOP/s"
-    roofline = dict(kernel="k_stream<double,%d,%d> (%s)" % (c["k"], c["n"] // 16, c["tag"]), bound=bnd,
+    pd = dict(f.split("=", 1) for f in c["p"].describe().split() if "=" in f)
+    roofline = dict(kernel="%s f64 kc=%s nt=%s rt=%s nsplit=%s (%s)" % (pd["kernel"], pd["kc"], pd["nt"], pd["rt"],
+                                                                   pd["nsplit"], c["tag"]), bound=bnd,
                     achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=measured_traffic(c["tag"]),
                     per_launch_bytes=c["bytes"], per_launch_flops=c["flops"], avg_launch_us=ms * 1e3)
     print("[bench] headline done: %.1f GB/s" % value, file=sys.stderr, flush=True)

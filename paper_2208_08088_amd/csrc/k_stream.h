@@ -228,7 +228,6 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A
                                                           int k, double alpha, double beta,
                                                           int nt_total, int nsplit) {
     typedef Mfma4<T> M;
-    typedef typename M::acc acc_t;
     typedef typename M::vec vec_t;
     constexpr int VW = M::VW;
     constexpr int S = KC / 4;  // k-steps
