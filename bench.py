@@ -40,7 +40,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}
 M_ROWS = 1 << 23
-CPU_SAMPLE_ROWS = 7 << 20  # sampled rows of each sub-case: about 10 s of oracle time
+CPU_SAMPLE_ROWS = 5 << 20  # sampled rows of each sub-case: about 7 s of oracle time on 16 cores
+CPU_ONE_THREAD_DIV = 32    # the one-thread leg runs 1/32 of that sample
 KS = (8, 32, 128)
 BETAS = (0.0, 1.0)
 
@@ -139,15 +140,26 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(case):
+TILE_FIELDS = ("kernel", "kc", "nt", "vec", "rt", "waves", "wg_per_cu", "nsplit")
+
+
+def plan_tile(describe):
+    """The fields of a plan description that fix the launched kernel."""
+    d = dict(f.split("=", 1) for f in describe.split() if "=" in f)
+    return " ".join("%s=%s" % (f, d[f]) for f in TILE_FIELDS)
+
+
+def measured_traffic(case, describe):
     """HBM bytes per launch of `case` from the committed rocprofv3 counter
-    summary, or None when there is none or the kernel changed since."""
+    summary, or None when there is none, or the kernel sources or the
+    plan's tile changed since."""
     path = os.path.join(ROOT, "profiles", "k_stream_f64_%s_pmc.txt" % {
         "k128b1": "k128_n128_beta1_m2p23"}.get(case, case))
     if not os.path.exists(path):
         return None
     kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
-    if kv.get("case") != case or kv.get("source_hash") != kernel_source_hash():
+    if (kv.get("case") != case or kv.get("source_hash") != kernel_source_hash()
+            or kv.get("plan_tile") != plan_tile(describe)):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -203,6 +215,35 @@ def extras_opt(torch, T, I, steps, warmup):
                 roofline_frac=bound_of(byt, fl, "f64")[1] / (ms * 1e-3)), (A, B, C)
 
 
+def extras_small(torch, T, I, calls=200):
+    """The 4096 x 16 x 16 binary64 case (alpha 1.5, beta 0.5): a latency
+    case, reported as microseconds per call over `calls` back-to-back calls."""
+    m, k, n = 4096, 16, 16
+    A = I.device_uniform((m, k), I.BASE_SEED, 11, torch.float64)
+    B = I.device_uniform((k, n), I.BASE_SEED, 12, torch.float64)
+    C0 = I.device_uniform((m, n), I.BASE_SEED, 13, torch.float64)
+    p = T.plan(m, n, k, "N", torch.float64)
+    pk = T.pack(B)
+    C = C0.clone()
+    T.execute(p, A, pk, C, 1.5, 0.5)
+    first = C.clone()
+    for _ in range(10):
+        T.execute(p, A, pk, C, 1.5, 0.5)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(calls):
+        T.execute(p, A, pk, C, 1.5, 0.5)
+    e1.record()
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / calls
+    byt = opn_bytes(m, n, k, 0.5)
+    keep = dict(A=A.cpu().numpy(), B=B.cpu().numpy(), C0=C0.cpu().numpy(), C=first.cpu().numpy())
+    return dict(shape="f64 4096x16 times 16x16, alpha 1.5, beta 0.5", plan=p.describe(), calls=calls,
+                us_per_call=us, GB_s=byt / us / 1e3), keep
+
+
 def extras_precision(torch, T, I, steps, warmup):
     m, k, n = 1 << 24, 256, 256
     A32 = I.device_col_scaled_uniform(m, k, I.BASE_SEED, 41, torch.float32)
@@ -253,13 +294,16 @@ def extras_batched(torch, T, I, steps, warmup):
         As, packs, Cs = [], [], []
         byt = 0
         fl = 0.0
+        t_roof = 0.0  # sum over instances of max(bytes / HBM peak, flops / matrix peak)
         for b in range(count):
             m, n, k = int(ms_[b]), int(ns_[b]), int(ks_[b])
             As.append(I.device_uniform((m, k), I.BASE_SEED, 1000 + b, dt))
             packs.append(T.pack(I.device_uniform((k, n), I.BASE_SEED, 3000 + b, dt)))
             Cs.append(torch.empty((m, n), dtype=torch.float32, device="cuda"))
-            byt += m * (k * As[-1].element_size() + n * 4)
+            bi = m * (k * As[-1].element_size() + n * 4)
+            byt += bi
             fl += 2.0 * m * n * k
+            t_roof += bound_of(bi, 2.0 * m * n * k, "f32" if dt == torch.float32 else "bf16")[1]
         bp = T.plan_batched(ms_, ns_, ks_, dt)
         bp.bind(As, packs, Cs)
         g = bp.graph()
@@ -271,15 +315,27 @@ def extras_batched(torch, T, I, steps, warmup):
             g.launch()
             timer.stop(dname, e0)
         ms = float(np.median(timer.per_key_ms()[dname]))
-        out[dname] = dict(instances=count, us=ms * 1e3, GB_s=byt / ms / 1e6, hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS,
-                          TFLOP_s=fl / ms / 1e9, bytes=byt)
+        out[dname] = dict(instances=count, plan=bp.describe(), us=ms * 1e3, GB_s=byt / ms / 1e6,
+                          hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, TFLOP_s=fl / ms / 1e9, bytes=byt,
+                          roofline_us=t_roof * 1e6, roofline_frac=t_roof / (ms * 1e-3))
         keep[dname] = (As, packs, Cs, bp, g)
     return out, keep
 
 
-def cpu_baseline(torch, I, cases, target_s=15.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(torch, I, cases, small=None):
     """The FP64 oracle on a row sample of the headline workload, on this
-    host's cores; also the sampled error of the GPU results."""
+    host's cores (and on one core, on a smaller sample); also the sampled
+    error of the GPU results, and the 4096 x 16 case checked in full."""
     import oracle
     oracle.build()
     cores = len(os.sched_getaffinity(0))
@@ -300,10 +356,27 @@ def cpu_baseline(torch, I, cases, target_s=15.0):
             err = oracle.normwise_rel_err(c["Cs"], ref)
             worst = max(worst, err)
             per.append(dict(case=c["tag"], sample_err=err))
-    return dict(value=tot_bytes / tot_s / 1e9, unit="GB/s", cores=cores, kind="oracle",
-                sample="%d sampled rows of each of the %d sub-cases (m=2^23 rows each), oracle time %.2f s"
-                       % (len(rows), len(cases), tot_s),
-                seconds=tot_s, sample_err_max=worst, per_case=per)
+    # one thread, on the first rows of the same sample
+    rows1 = rows[: len(rows) // CPU_ONE_THREAD_DIV]
+    one_bytes, one_s = 0, 0.0
+    for c in cases:
+        A = c["As"][0][idx[: len(rows1)]].cpu().numpy()
+        B = c["B"].cpu().numpy()
+        C0 = c["C0s"][: len(rows1)] if "C0s" in c else None
+        t0 = time.perf_counter()
+        oracle.gemm_n(A, B, C0, 1.0, c["beta"], threads=1)
+        one_s += time.perf_counter() - t0
+        one_bytes += opn_bytes(len(rows1), c["n"], c["k"], c["beta"])
+    out = dict(value=tot_bytes / tot_s / 1e9, unit="GB/s", cores=cores, kind="oracle",
+               sample="%d sampled rows of each of the %d sub-cases (m=2^23 rows each), oracle time %.2f s"
+                      % (len(rows), len(cases), tot_s),
+               seconds=tot_s, cpu_model=cpu_model(), one_thread_GB_s=one_bytes / one_s / 1e9,
+               one_thread_sample="%d rows of each sub-case, %.2f s" % (len(rows1), one_s),
+               sample_err_max=worst, per_case=per)
+    if small is not None:
+        ref = oracle.gemm_n(small["A"], small["B"], small["C0"], 1.5, 0.5, threads=cores)
+        out["small_4096x16_err"] = oracle.normwise_rel_err(small["C"], ref)
+    return out
 
 
 def main():
@@ -339,11 +412,13 @@ def main():
     for c in cases:
         msl = per[c["tag"]]
         ms = float(np.mean(msl))
+        q = np.percentile(msl, [50, 90])
         bnd, t_ideal = bound_of(c["bytes"], c["flops"], "f64")
         row = dict(case=c["tag"], m=M_ROWS, k=c["k"], n=c["n"], beta=c["beta"], us=ms * 1e3,
                    GB_s=c["bytes"] / ms / 1e6, hbm_frac=c["bytes"] / ms / 1e6 / HBM_PEAK_GBS,
                    TFLOP_s=c["flops"] / ms / 1e9, bound=bnd, roofline_frac=t_ideal / (ms * 1e-3),
-                   plan=c["p"].describe())
+                   us_median=float(q[0]) * 1e3, us_min=float(np.min(msl)) * 1e3, us_p90=float(q[1]) * 1e3,
+                   copy_frac=c["bytes"] / ms / 1e6 / ceiling["GB_s"], plan=c["p"].describe())
         breakdown.append(row)
         if dom is None or ms > dom[1]:
             dom = (c, ms, bnd)
@@ -355,7 +430,7 @@ def main():
     pd = dict(f.split("=", 1) for f in c["p"].describe().split() if "=" in f)
     roofline = dict(kernel="%s f64 kc=%s nt=%s rt=%s nsplit=%s (%s)" % (pd["kernel"], pd["kc"], pd["nt"], pd["rt"],
                                                                    pd["nsplit"], c["tag"]), bound=bnd,
-                    achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=measured_traffic(c["tag"]),
+                    achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=measured_traffic(c["tag"], c["p"].describe()),
                     per_launch_bytes=c["bytes"], per_launch_flops=c["flops"], avg_launch_us=ms * 1e3)
     print("[bench] headline done: %.1f GB/s" % value, file=sys.stderr, flush=True)
 
@@ -369,7 +444,10 @@ def main():
                   hbm_frac=value / HBM_PEAK_GBS, roofline=roofline, breakdown=breakdown,
                   copy_ceiling=ceiling)
 
+    keep_s = None
     if not args.no_extras and not args.only:
+        small, keep_s = extras_small(torch, T, I)
+        print("[bench] small case done", file=sys.stderr, flush=True)
         opt, keep_t = extras_opt(torch, T, I, args.steps, args.warmup)
         print("[bench] op T done", file=sys.stderr, flush=True)
         prec, keep_p = extras_precision(torch, T, I, args.steps, args.warmup)
@@ -378,10 +456,11 @@ def main():
         bat, keep_b = extras_batched(torch, T, I, args.steps, args.warmup)
         print("[bench] batched done", file=sys.stderr, flush=True)
         del keep_b, keep_t
-        result["extras"] = dict(op_t_splitk=opt, precision_m2p24_k256=prec, batched_512=bat)
+        result["extras"] = dict(small_4096x16=small, op_t_splitk=opt, precision_m2p24_k256=prec,
+                                batched_512=bat)
 
     if not args.no_cpu_baseline and not args.only:
-        result["cpu_baseline"] = cpu_baseline(torch, I, cases)
+        result["cpu_baseline"] = cpu_baseline(torch, I, cases, keep_s)
         if "extras" in result:
             # sampled errors of the precision variants against the oracle
             import oracle

@@ -104,12 +104,14 @@ typedef enum tsmm_kernel {
     TSMM_KERNEL_VALU64 = 5,    /* op N binary64 on the vector ALU: one row per
                                   lane, k % 8 == 0, n a multiple of the
                                   column block                               */
-    TSMM_KERNEL_WIDE = 6       /* op N TSMM_F32 (native, BF16X3, BF16X6) with
+    TSMM_KERNEL_WIDE = 6,      /* op N TSMM_F32 (native, BF16X3, BF16X6) with
                                   n = 128 or 256, k <= 256, k % 8 == 0: a
                                   wavefront owns whole rows of C in 32x32
                                   matrix-core accumulators, packed B streams
                                   through LDS in 32-row slabs; A and C 16-byte
                                   aligned                                    */
+    TSMM_KERNEL_BATCHED = 7    /* batched plans only: the persistent launch
+                                  over chunks of instance rows               */
 } tsmm_kernel;
 
 /* One entry of the tile table: the register/LDS blocking and launch shape
@@ -127,6 +129,9 @@ typedef struct tsmm_tile {
                               CUs * wg_per_cu, capped by the work): 1..32   */
     int32_t splitk;        /* op T: number of partial sums P (1..65536)     */
     int32_t nsplit;        /* op N: column groups sharing one row block     */
+    int32_t chunk_rows;    /* batched plans: rows of one instance that a
+                              workgroup takes per work item, a power of two
+                              in 256..65536 (0 = default); 0 elsewhere      */
 } tsmm_tile;
 
 /* Device properties the planner uses; tsmm_plan reads them from the current
@@ -225,7 +230,11 @@ tsmm_status tsmm_plan_set_mode(tsmm_plan_t plan, tsmm_mode mode);
 
 /* Replace the tile (autotuner and tests).  The tile is validated against
  * the shape and the device limits; INVALID_VALUE / NOT_SUPPORTED if it
- * cannot run. */
+ * cannot run.  A batched plan takes kernel TSMM_KERNEL_BATCHED (or AUTO)
+ * and only chunk_rows may differ from its defaults; the chunk list is
+ * rebuilt on the device (synchronously), so the plan must be idle, and a
+ * plan from which a graph was made refuses it (INVALID_VALUE) while the
+ * graph exists. */
 tsmm_status tsmm_plan_set_tile(tsmm_plan_t plan, const tsmm_tile *tile);
 tsmm_status tsmm_plan_get_tile(tsmm_plan_t plan, tsmm_tile *tile);
 
@@ -272,7 +281,8 @@ tsmm_status tsmm_execute(tsmm_plan_t plan, const void *A, tsmm_packed_t packed,
 
 /* Plan `count` independent op N multiplies that run in ONE persistent
  * launch: instance b is m[b] x k[b] times k[b] x n[b].  Host arrays.  The
- * plan cuts the instances into chunks of rows (instances of one kernel
+ * plan cuts the instances into chunks of rows (chunk_rows from the tile
+ * table's batched entry for the dtype, else 4096; instances of one kernel
  * variant together, longest first) that the launch's workgroups take from
  * a device counter; the plan owns that counter, which every launch leaves
  * at zero, so the launches (or graph replays) of one plan must not overlap
@@ -289,9 +299,8 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
  * device on the plan's stream from pinned staging memory, so a bind can be
  * captured in a graph.  Every packed[b] must match (k[b], n[b], dtype).
  * A[b] must be 16-byte aligned when k[b] allows vector loads (binary32: k
- * a multiple of 4; bfloat16: of 8) and C[b] when binary32 C is stored in
- * vectors (vector loads, n a multiple of 4, n > 48); INVALID_VALUE
- * otherwise. */
+ * a multiple of 4; bfloat16: of 8) and C[b] when C is stored in 16-byte
+ * vectors (n a multiple of 4 and n > 32); INVALID_VALUE otherwise. */
 tsmm_status tsmm_batched_bind(tsmm_plan_t plan, const void *const *A,
                               const tsmm_packed_t *packed, void *const *C,
                               const double *alpha, const double *beta);

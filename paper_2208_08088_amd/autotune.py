@@ -34,7 +34,8 @@ DEFAULT_TABLE = os.path.join(HERE, "tile_table.txt")
 
 _DT_NAME = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}
 _KERNEL_NAME = {T.KERNEL_SIMPLE: "simple", T.KERNEL_STREAM: "stream", T.KERNEL_SPLITK: "splitk",
-                T.KERNEL_SPLITBF16: "splitbf16", T.KERNEL_VALU64: "valu64", T.KERNEL_WIDE: "wide"}
+                T.KERNEL_SPLITBF16: "splitbf16", T.KERNEL_VALU64: "valu64", T.KERNEL_WIDE: "wide",
+                T.KERNEL_BATCHED: "batched"}
 
 
 def mclass_of(m):
@@ -53,7 +54,12 @@ CLASSES = {
     "n_f32x6_k256": ("N", torch.float32, "bf16x6", 1 << 24, 256, 256),
     "n_f32x3_k256": ("N", torch.float32, "bf16x3", 1 << 24, 256, 256),
     "t_f64_64x64": ("T", torch.float64, "native", 64, 64, 1 << 22),
+    # batched: the 512-instance workload (m uniform in [1024, 262144], k and
+    # n from {4, ..., 128}); the tile is the chunk of rows a workgroup takes
+    "b_f32_512": ("B", torch.float32, "native", 512, 0, 0),
+    "b_bf16_512": ("B", torch.bfloat16, "native", 512, 0, 0),
 }
+BATCH_CHUNKS = (512, 1024, 2048, 4096, 8192, 16384, 32768)
 HEADLINE = ["n_f64_k8", "n_f64_k32", "n_f64_k128", "t_f64_64x64"]
 
 
@@ -68,6 +74,8 @@ def _pow2_class(x, lo, hi):
 
 def table_key(layout, dt, mode, m, n, k):
     """(kc, nt, mclass) of the table entry tsmm_plan looks up for a shape."""
+    if layout == "B":
+        return 0, 0, 0
     if layout == "T":
         tiles = lambda d: 1 if (d + 15) // 16 <= 1 else (2 if (d + 15) // 16 <= 2 else 4)
         return tiles(m), tiles(n), mclass_of(k)
@@ -85,6 +93,7 @@ def natural_kernel(p):
 def candidates(p):
     """Candidate tiles for plan p (the plan's current tile first)."""
     base = p.get_tile()
+    base.pop("chunk_rows", None)  # batched plans only
     out = [dict(base)]
     # the natural family's default tile, whatever the plan picked
     nat = dict(base)
@@ -92,6 +101,7 @@ def candidates(p):
         try:
             p.set_tile(kernel=natural_kernel(p))
             nat = p.get_tile()
+            nat.pop("chunk_rows", None)
             out.append(dict(nat))
         except T.TsmmError:
             nat = None
@@ -145,8 +155,48 @@ def time_plan(p, As, pk, C, beta, reps):
     return float(np.median(times))
 
 
+def tune_batched(name, spec, reps, log):
+    """Chunk size of the persistent batched launch for one dtype."""
+    _, dt, _, count, _, _ = spec
+    ms, ns, ks = I.batched_shapes(count, I.BASE_SEED)
+    As, packs, Cs = [], [], []
+    for b in range(count):
+        m, n, k = int(ms[b]), int(ns[b]), int(ks[b])
+        As.append(I.device_uniform((m, k), I.BASE_SEED, 1000 + b, dt))
+        packs.append(T.pack(I.device_uniform((k, n), I.BASE_SEED, 3000 + b, dt)))
+        Cs.append(torch.empty((m, n), dtype=torch.float32, device="cuda"))
+    bp = T.plan_batched(ms, ns, ks, dt)
+    bp.bind(As, packs, Cs)
+    best = None
+    for chunk in BATCH_CHUNKS:
+        bp.set_chunk_rows(chunk)
+        bp.execute()  # warm-up
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            bp.execute()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms_ = float(np.median(times))
+        log("  %-14s chunk_rows=%d  %.3f ms" % (name, chunk, ms_))
+        if best is None or ms_ < best[0]:
+            best = (ms_, bp.get_tile())
+    t = best[1]
+    entry = "B %s native 0 0 0 : batched %d %d %d %d %d %d" % (
+        _DT_NAME[dt], t["rows_per_wave"], t["waves_per_wg"], t["wg_per_cu"], t["splitk"], t["nsplit"],
+        t["chunk_rows"])
+    del As, packs, Cs, bp
+    torch.cuda.empty_cache()
+    return entry, best[0]
+
+
 def tune_class(name, spec, reps, log):
     layout, dt, mode, m, n, k = spec
+    if layout == "B":
+        return tune_batched(name, spec, reps, log)
     if layout == "N":
         if mode == "native":
             As = [I.device_uniform((m, k), I.BASE_SEED, 900 + r, dt) for r in range(2)]
@@ -227,14 +277,15 @@ def main(argv=None):
     log = lambda s: print(s, flush=True)
     for name in names:
         spec = CLASSES[name]
-        log("[autotune] class %s" % name)
-        entry, ms = tune_class(name, spec, a.reps, log)
-        key = " ".join(entry.split(":")[0].split())
+        key = "%s %s %s %d %d %d" % ((spec[0], _DT_NAME[spec[1]], spec[2]) + table_key(*spec))
         if key in entries and not a.retune:
             log("[autotune] %s already in the table; kept (use --retune)" % key)
             continue
-        entries[key] = entry + "  # %.3f ms at %s%s" % (ms, "x".join(str(v) for v in spec[3:]),
-                                                       " (beta 0 + beta 1)" if spec[0] == "N" else "")
+        log("[autotune] class %s" % name)
+        entry, ms = tune_class(name, spec, a.reps, log)
+        assert " ".join(entry.split(":")[0].split()) == key, (entry, key)
+        where = ("%d batched instances" % spec[3]) if spec[0] == "B" else "x".join(str(v) for v in spec[3:])
+        entries[key] = entry + "  # %.3f ms at %s%s" % (ms, where, " (beta 0 + beta 1)" if spec[0] == "N" else "")
         write_table(a.out, entries, header)
         log("[autotune] %s -> %s (%.3f ms)" % (name, entry, ms))
     return 0

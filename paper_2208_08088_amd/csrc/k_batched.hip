@@ -1,7 +1,7 @@
 // Batched op N: many independent tall-and-skinny multiplies, each with its
 // own packed B, in ONE persistent launch.
 //
-// The host cuts every instance into chunks of kBatchChunk rows and orders
+// The host cuts every instance into chunks of chunk_rows rows and orders
 // the instances by kernel variant; workgroups take chunks from a counter
 // (dynamic schedule, see k_batched).  Binary32 inputs use the 16x16x4 f32
 // product and fragments of k_stream.h, bfloat16 inputs the 16x16x32 bf16
@@ -133,7 +133,7 @@ __device__ __forceinline__ void run_segment_bf16(const BatchDesc &d, int64_t row
     }
 }
 
-// Dynamic schedule: the work is a sequence of chunks (kBatchChunk rows of
+// Dynamic schedule: the work is a sequence of chunks (chunk_rows rows of
 // one instance; instances of one kernel variant next to each other).  A
 // workgroup takes the next chunk from a counter, loads that instance's
 // packed B into LDS when the instance changes (the per-core resident block
@@ -145,7 +145,7 @@ __device__ __forceinline__ void run_segment_bf16(const BatchDesc &d, int64_t row
 // (and every graph replay) starts from a clean state without a memset.
 template <bool BF16>
 __global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_batched(
-    const BatchDesc *__restrict__ desc, const int64_t *__restrict__ chunk_start, int64_t nchunks,
+    const BatchDesc *__restrict__ desc, const int64_t *__restrict__ chunk_start, int64_t nchunks, int chunk_rows,
     int32_t *__restrict__ ctr) {
     extern __shared__ u16x8 sB[];  // the current instance's packed B
     __shared__ int32_t s_chunk;
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_e
             loaded = inst;
         }
         __syncthreads();  // B in LDS; every lane has read s_chunk
-        const int64_t row_a = (c - chunk_start[inst]) * kBatchChunk;
-        const int64_t row_b = row_a + kBatchChunk < d.m ? row_a + kBatchChunk : d.m;
+        const int64_t row_a = (c - chunk_start[inst]) * chunk_rows;
+        const int64_t row_b = row_a + chunk_rows < d.m ? row_a + chunk_rows : d.m;
         if constexpr (BF16) run_segment_bf16(d, row_a, row_b, sB, wave);
         else run_segment_f32(d, row_a, row_b, reinterpret_cast<const float *>(sB), wave);
     }
@@ -188,14 +188,17 @@ hipError_t prepare_batched(tsmm_dtype dt, size_t lds_bytes) {
 }
 
 hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *chunk_start, int64_t nchunks,
-                          int32_t *ctr, int64_t grid, int block, size_t lds_bytes, hipStream_t s) {
-    if (block != 64 * kBatchWaves || nchunks < 0 || nchunks >= (int64_t)1 << 31) return hipErrorInvalidValue;
+                          int chunk_rows, int32_t *ctr, int64_t grid, int block, size_t lds_bytes,
+                          hipStream_t s) {
+    if (block != 64 * kBatchWaves || nchunks < 0 || nchunks >= (int64_t)1 << 31 || chunk_rows < kBatchChunkMin ||
+        chunk_rows > kBatchChunkMax || chunk_rows % 16 != 0)
+        return hipErrorInvalidValue;
     if (dt == TSMM_BF16)
         hipLaunchKernelGGL(k_batched<true>, dim3((unsigned)grid), dim3(block), lds_bytes, s, desc, chunk_start,
-                           nchunks, ctr);
+                           nchunks, chunk_rows, ctr);
     else
         hipLaunchKernelGGL(k_batched<false>, dim3((unsigned)grid), dim3(block), lds_bytes, s, desc, chunk_start,
-                           nchunks, ctr);
+                           nchunks, chunk_rows, ctr);
     return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ const char *kernel_name(int k) {
     case TSMM_KERNEL_SPLITBF16: return "splitbf16";
     case TSMM_KERNEL_VALU64: return "valu64";
     case TSMM_KERNEL_WIDE: return "wide";
+    case TSMM_KERNEL_BATCHED: return "batched";
     default: return "auto";
     }
 }
@@ -126,6 +127,10 @@ tsmm_status query_caps(tsmm_device_caps *caps, int *device) {
 //       mclass = class of the shared dimension.
 // '#' starts a comment.
 
+// Tile-table layout "B": the entry of batched plans of one dtype (key
+// fields kc, nt, mclass are 0).
+constexpr int kLayoutBatched = 2;
+
 struct TableKey {
     int layout, dtype, mode, kc, nt, mclass;
     bool operator<(const TableKey &o) const {
@@ -158,6 +163,7 @@ int parse_kernel(const std::string &s) {
     if (s == "splitbf16") return TSMM_KERNEL_SPLITBF16;
     if (s == "valu64") return TSMM_KERNEL_VALU64;
     if (s == "wide") return TSMM_KERNEL_WIDE;
+    if (s == "batched") return TSMM_KERNEL_BATCHED;
     return -1;
 }
 
@@ -166,7 +172,7 @@ bool parse_table_line(const std::string &line, TableKey *key, tsmm_tile *tile) {
     std::string lay, dt, md, colon, kern;
     if (!(is >> lay >> dt >> md >> key->kc >> key->nt >> key->mclass >> colon >> kern)) return false;
     if (colon != ":") return false;
-    key->layout = lay == "N" ? TSMM_OP_N : lay == "T" ? TSMM_OP_T : -1;
+    key->layout = lay == "N" ? TSMM_OP_N : lay == "T" ? TSMM_OP_T : lay == "B" ? kLayoutBatched : -1;
     key->dtype = dt == "f64" ? TSMM_F64 : dt == "f32" ? TSMM_F32 : dt == "bf16" ? TSMM_BF16 : -1;
     key->mode = md == "native" ? TSMM_MODE_NATIVE : md == "bf16x3" ? TSMM_MODE_BF16X3 : md == "bf16x6" ? TSMM_MODE_BF16X6 : -1;
     if (key->layout < 0 || key->dtype < 0 || key->mode < 0) return false;
@@ -174,6 +180,9 @@ bool parse_table_line(const std::string &line, TableKey *key, tsmm_tile *tile) {
     t.kernel = parse_kernel(kern);
     if (t.kernel < 0) return false;
     if (!(is >> t.rows_per_wave >> t.waves_per_wg >> t.wg_per_cu >> t.splitk >> t.nsplit)) return false;
+    // batched entries carry the chunk size as a sixth field
+    if (key->layout == kLayoutBatched && !(is >> t.chunk_rows)) return false;
+    if ((key->layout == kLayoutBatched) != (t.kernel == TSMM_KERNEL_BATCHED)) return false;
     *tile = t;
     return true;
 }
@@ -441,6 +450,68 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         break;
     }
     p.tile = t;
+    return TSMM_SUCCESS;
+}
+
+// ------------------------------------------------------ batched tiles
+
+bool valid_chunk_rows(int c) { return c >= kBatchChunkMin && c <= kBatchChunkMax && is_pow2(c); }
+
+// Chunk size of batched plans of `dtype`: the table's batched entry, else
+// the default.
+int batched_table_chunk(tsmm_dtype dtype, bool *from_table) {
+    *from_table = false;
+    Table &tab = table();
+    if (tab.loaded) {
+        auto it = tab.entries.find(TableKey{kLayoutBatched, dtype, TSMM_MODE_NATIVE, 0, 0, 0});
+        if (it != tab.entries.end() && valid_chunk_rows(it->second.chunk_rows)) {
+            *from_table = true;
+            return it->second.chunk_rows;
+        }
+    }
+    return kBatchChunkDefault;
+}
+
+// Cut the instances (in execution order) into chunks of chunk_rows rows:
+// the prefix of chunk counts goes to the device (synchronously) and the
+// grid follows the work.
+tsmm_status batched_chunks(tsmm_plan_s &p, int chunk_rows) {
+    const size_t count = p.inst.size();
+    std::vector<int64_t> inst_start(count + 1, 0);
+    for (size_t e = 0; e < count; ++e) {
+        const BatchedInstance &I = p.inst[p.order[e]];
+        inst_start[e + 1] = inst_start[e] + (I.m + chunk_rows - 1) / chunk_rows;
+    }
+    if (inst_start[count] >= (int64_t)1 << 31) return fail(TSMM_ERROR_NOT_SUPPORTED, "batch too large (2^31 chunks)");
+    hipError_t e = hipMemcpy(p.d_inst_start, inst_start.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batched chunk list upload");
+    p.n_work = inst_start[count];
+    p.tile.chunk_rows = chunk_rows;
+    p.grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)p.caps.compute_units * p.tile.wg_per_cu, p.n_work));
+    return TSMM_SUCCESS;
+}
+
+// tsmm_plan_set_tile on a batched plan: only the chunk size is free.
+tsmm_status set_batched_tile(tsmm_plan_s &p, const tsmm_tile &t) {
+    if (t.kernel != TSMM_KERNEL_AUTO && t.kernel != TSMM_KERNEL_BATCHED)
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans run the batched kernel");
+    if ((t.rows_per_wave != 0) || (t.waves_per_wg != 0 && t.waves_per_wg != kBatchWaves) ||
+        (t.wg_per_cu != 0 && t.wg_per_cu != 1) || (t.splitk != 0 && t.splitk != 1) ||
+        (t.nsplit != 0 && t.nsplit != 1))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take only chunk_rows (%d waves, 1 workgroup per CU)",
+                    kBatchWaves);
+    bool from_table = false;
+    const int chunk = t.chunk_rows ? t.chunk_rows : batched_table_chunk(p.dtype, &from_table);
+    if (!valid_chunk_rows(chunk))
+        return fail(TSMM_ERROR_INVALID_VALUE, "chunk_rows %d: a power of two in %d..%d", chunk, kBatchChunkMin,
+                    kBatchChunkMax);
+    if (p.graphs > 0) return fail(TSMM_ERROR_INVALID_VALUE, "a graph captured from this plan still exists");
+    hipError_t e = hipSetDevice(p.device);
+    if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+    if (e != hipSuccess) return hip_fail(e, "batched plan re-tile");
+    tsmm_status st = batched_chunks(p, chunk);
+    if (st != TSMM_SUCCESS) return st;
+    p.tile_from_table = from_table;
     return TSMM_SUCCESS;
 }
 
@@ -748,9 +819,10 @@ tsmm_status tsmm_plan_set_mode(tsmm_plan_t p, tsmm_mode mode) {
 tsmm_status tsmm_plan_set_tile(tsmm_plan_t p, const tsmm_tile *tile) {
     g_err.clear();
     if (!p || !tile) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
-    if (p->batched) return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take tiles at planning time");
+    if (p->batched) return set_batched_tile(*p, *tile);
     if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_WIDE)
         return fail(TSMM_ERROR_INVALID_VALUE, "bad kernel id %d", tile->kernel);
+    if (tile->chunk_rows != 0) return fail(TSMM_ERROR_INVALID_VALUE, "chunk_rows is for batched plans");
     tsmm_plan_s trial = *p;
     trial.workspace = nullptr;
     trial.owns_workspace = false;
@@ -984,14 +1056,6 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
         return vx != vy ? vx < vy : cost[x] > cost[y];
     });
 
-    // chunk prefix counts in execution order
-    std::vector<int64_t> inst_start(count + 1, 0);
-    for (int64_t e = 0; e < count; ++e) {
-        const BatchedInstance &I = p->inst[p->order[e]];
-        inst_start[e + 1] = inst_start[e] + (I.m + kBatchChunk - 1) / kBatchChunk;
-    }
-    p->n_work = inst_start[count];
-    if (p->n_work >= (int64_t)1 << 31) return fail(TSMM_ERROR_NOT_SUPPORTED, "batch too large (2^31 chunks)");
     for (const BatchedInstance &I : p->inst) {
         const int KC = dtype == TSMM_BF16 ? kclass32(I.k) : kclass4(I.k);
         p->batch_lds = std::max(p->batch_lds, batched_lds_bytes(dtype, KC, ntclass(I.n)));
@@ -999,12 +1063,11 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
     // the batched kernel's fixed workgroup (kBatchWaves wavefronts), one per
     // compute unit (two wavefronts per SIMD); chunks are handed out at run
     // time, so the grid only needs to fill the device
-    const int waves = kBatchWaves;
-    p->tile = tsmm_tile{TSMM_KERNEL_STREAM, 0, waves, 1, 1, 1};
-    p->block = 64 * waves;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)caps.compute_units * p->tile.wg_per_cu,
-                                                                p->n_work));
-    p->grid = grid;
+    bool from_table = false;
+    const int chunk = batched_table_chunk(dtype, &from_table);
+    p->tile = tsmm_tile{TSMM_KERNEL_BATCHED, 0, kBatchWaves, 1, 1, 1, chunk};
+    p->tile_from_table = from_table;
+    p->block = 64 * kBatchWaves;
 
     hipError_t e1 = hipMalloc(&p->d_desc, sizeof(BatchDesc) * count);
     hipError_t e2 = hipMalloc(&p->d_inst_start, sizeof(int64_t) * (count + 1));
@@ -1019,9 +1082,13 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
         tsmm_plan_destroy(p.release());
         return hip_fail(e, "batched kernel attributes");
     }
-    e = hipMemcpy(p->d_inst_start, inst_start.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
+    st = batched_chunks(*p, chunk);
+    if (st != TSMM_SUCCESS) {
+        tsmm_plan_destroy(p.release());
+        return st;
+    }
     // the counters start at zero once; every launch leaves them at zero
-    if (e == hipSuccess) e = hipMemset(p->d_ctr, 0, sizeof(int32_t) * 2);
+    e = hipMemset(p->d_ctr, 0, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         tsmm_plan_destroy(p.release());
@@ -1030,8 +1097,8 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
     p->m = 0;
     for (const BatchedInstance &I : p->inst) p->m += I.m;
     if (log_level() >= 1)
-        fprintf(stderr, "[tsmm] batched plan: %" PRId64 " instances, %" PRId64 " chunks, grid %" PRId64 "\n",
-                count, p->n_work, grid);
+        fprintf(stderr, "[tsmm] batched plan: %" PRId64 " instances, %" PRId64 " chunks of %d rows, grid %" PRId64 "\n",
+                count, p->n_work, chunk, p->grid);
     *out = p.release();
     return TSMM_SUCCESS;
 }
@@ -1102,7 +1169,7 @@ tsmm_status tsmm_execute_batched(tsmm_plan_t p, const void *const *A, const tsmm
     if (p->n_work == 0) return TSMM_SUCCESS;
     hipError_t e = launch_batched(p->dtype, static_cast<const BatchDesc *>(p->d_desc),
                                   static_cast<const int64_t *>(p->d_inst_start), p->n_work,
-                                  static_cast<int32_t *>(p->d_ctr), p->grid, p->block, p->batch_lds, p->stream);
+                                  p->tile.chunk_rows, static_cast<int32_t *>(p->d_ctr), p->grid, p->block, p->batch_lds, p->stream);
     return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "batched launch");
 }
 
@@ -1122,7 +1189,7 @@ tsmm_status tsmm_graph_create_batched(tsmm_plan_t p, tsmm_graph_t *out) {
     if (e == hipSuccess) {
         hipError_t le = launch_batched(p->dtype, static_cast<const BatchDesc *>(p->d_desc),
                                        static_cast<const int64_t *>(p->d_inst_start), p->n_work,
-                                       static_cast<int32_t *>(p->d_ctr), p->grid, p->block, p->batch_lds, cs);
+                                       p->tile.chunk_rows, static_cast<int32_t *>(p->d_ctr), p->grid, p->block, p->batch_lds, cs);
         e = hipStreamEndCapture(cs, &g->graph);
         if (le != hipSuccess) e = le;
     }
@@ -1132,6 +1199,8 @@ tsmm_status tsmm_graph_create_batched(tsmm_plan_t p, tsmm_graph_t *out) {
         if (g && g->graph) (void)hipGraphDestroy(g->graph);
         return g ? hip_fail(e, "graph capture") : fail(TSMM_ERROR_OUT_OF_MEMORY, "host allocation failed");
     }
+    g->plan = p;
+    ++p->graphs;
     *out = g.release();
     return TSMM_SUCCESS;
 }
@@ -1145,6 +1214,7 @@ tsmm_status tsmm_graph_launch(tsmm_graph_t g, void *stream) {
 
 void tsmm_graph_destroy(tsmm_graph_t g) {
     if (!g) return;
+    if (g->plan) --g->plan->graphs;
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;

@@ -147,12 +147,15 @@ struct alignas(16) BatchDesc {
     int64_t m;
     int32_t k, n;
     int32_t KC, NT;
-    int32_t vec, il;  // vector k-slot mapping; interleaved columns (binary32)
+    int32_t vec, il;  // vector k-slot mapping; interleaved columns (16-byte C vectors)
 };
 
-// Rows of one batched chunk (the unit of the dynamic schedule) and
-// wavefronts per workgroup of the batched kernel.
-constexpr int kBatchChunk = 4096;
+// Rows of one batched chunk (the unit of the dynamic schedule) when the
+// tile table has no batched entry, the allowed range (powers of two; a
+// multiple of the 16-row tile), and wavefronts per workgroup of the
+// batched kernel.
+constexpr int kBatchChunkDefault = 4096;
+constexpr int kBatchChunkMin = 256, kBatchChunkMax = 65536;
 constexpr int kBatchWaves = 8;
 
 }  // namespace tsmm
@@ -187,6 +190,7 @@ struct tsmm_plan_s {
     void *d_inst_start = nullptr;             // device int64[count + 1]: first chunk
     void *d_ctr = nullptr;                    // device int32[2]: work counter, finished workgroups
     size_t batch_lds = 0;                     // dynamic LDS of the batched launch
+    int graphs = 0;                           // live graphs captured from this plan
     bool bound = false;
     std::vector<tsmm::BatchDesc> bound_desc;
 };
@@ -194,6 +198,7 @@ struct tsmm_plan_s {
 struct tsmm_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    tsmm_plan_s *plan = nullptr;  // the batched plan it was captured from
 };
 
 namespace tsmm {
@@ -273,9 +278,11 @@ bool splitk_variant_exists(int MT, int NT, int RG);
 size_t batched_lds_bytes(tsmm_dtype dt, int KC, int NT);
 hipError_t prepare_batched(tsmm_dtype dt, size_t lds_bytes);
 // chunk_start: device int64[count + 1], first chunk of each instance (in
-// descriptor order); ctr: device int32[2], zero before the first launch
-// (every launch leaves it zero again).
+// descriptor order); chunk_rows: rows per chunk (a multiple of 16); ctr:
+// device int32[2], zero before the first launch (every launch leaves it
+// zero again).
 hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *chunk_start, int64_t nchunks,
-                          int32_t *ctr, int64_t grid, int block, size_t lds_bytes, hipStream_t s);
+                          int chunk_rows, int32_t *ctr, int64_t grid, int block, size_t lds_bytes,
+                          hipStream_t s);
 
 }  // namespace tsmm

@@ -24,7 +24,8 @@ SUCCESS, INVALID_VALUE, SHAPE_MISMATCH, NOT_SUPPORTED, TABLE, OUT_OF_MEMORY, NO_
 F64, F32, BF16 = 0, 1, 2
 OP_N, OP_T = 0, 1
 MODE_NATIVE, MODE_BF16X3, MODE_BF16X6 = 0, 1, 2
-KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_STREAM, KERNEL_SPLITK, KERNEL_SPLITBF16, KERNEL_VALU64, KERNEL_WIDE = range(7)
+(KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_STREAM, KERNEL_SPLITK, KERNEL_SPLITBF16, KERNEL_VALU64, KERNEL_WIDE,
+ KERNEL_BATCHED) = range(8)
 
 _MODES = {"native": MODE_NATIVE, "bf16x3": MODE_BF16X3, "bf16x6": MODE_BF16X6}
 _LAYOUTS = {"N": OP_N, "T": OP_T}
@@ -41,7 +42,24 @@ class TsmmError(RuntimeError):
 
 class _Tile(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in
-                ("kernel", "rows_per_wave", "waves_per_wg", "wg_per_cu", "splitk", "nsplit")]
+                ("kernel", "rows_per_wave", "waves_per_wg", "wg_per_cu", "splitk", "nsplit", "chunk_rows")]
+
+
+def _set_tile(h, **fields):
+    t = _Tile(**fields)
+    _check(_lib().tsmm_plan_set_tile(h, ctypes.byref(t)), "tsmm_plan_set_tile")
+
+
+def _get_tile(h) -> dict:
+    t = _Tile()
+    _check(_lib().tsmm_plan_get_tile(h, ctypes.byref(t)), "tsmm_plan_get_tile")
+    return {f: getattr(t, f) for f, _ in _Tile._fields_}
+
+
+def _describe(h) -> str:
+    buf = ctypes.create_string_buffer(512)
+    _check(_lib().tsmm_plan_describe(h, buf, 512), "tsmm_plan_describe")
+    return buf.value.decode()
 
 
 class _Caps(ctypes.Structure):
@@ -210,16 +228,14 @@ class Plan:
         self._ws = None
         return self
 
-    def set_tile(self, kernel=0, rows_per_wave=0, waves_per_wg=0, wg_per_cu=0, splitk=0, nsplit=0):
-        t = _Tile(kernel, rows_per_wave, waves_per_wg, wg_per_cu, splitk, nsplit)
-        _check(_lib().tsmm_plan_set_tile(self._h, ctypes.byref(t)), "tsmm_plan_set_tile")
+    def set_tile(self, kernel=0, rows_per_wave=0, waves_per_wg=0, wg_per_cu=0, splitk=0, nsplit=0, chunk_rows=0):
+        _set_tile(self._h, kernel=kernel, rows_per_wave=rows_per_wave, waves_per_wg=waves_per_wg,
+                  wg_per_cu=wg_per_cu, splitk=splitk, nsplit=nsplit, chunk_rows=chunk_rows)
         self._ws = None
         return self
 
     def get_tile(self) -> dict:
-        t = _Tile()
-        _check(_lib().tsmm_plan_get_tile(self._h, ctypes.byref(t)), "tsmm_plan_get_tile")
-        return {f: getattr(t, f) for f, _ in _Tile._fields_}
+        return _get_tile(self._h)
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t(0)
@@ -227,9 +243,7 @@ class Plan:
         return b.value
 
     def describe(self) -> str:
-        buf = ctypes.create_string_buffer(512)
-        _check(_lib().tsmm_plan_describe(self._h, buf, 512), "tsmm_plan_describe")
-        return buf.value.decode()
+        return _describe(self._h)
 
     def info(self) -> dict:
         out = {}
@@ -299,6 +313,18 @@ class BatchedPlan:
     @property
     def handle(self):
         return self._h
+
+    def set_chunk_rows(self, chunk_rows: int = 0):
+        """Rows per work item of the persistent launch (0: the tile table's
+        or the default); the plan must be idle and have no live graph."""
+        _set_tile(self._h, kernel=KERNEL_BATCHED, chunk_rows=chunk_rows)
+        return self
+
+    def get_tile(self) -> dict:
+        return _get_tile(self._h)
+
+    def describe(self) -> str:
+        return _describe(self._h)
 
     def _arrays(self, As, packeds, Cs, alphas, betas):
         cnt = len(self.ms)

@@ -160,7 +160,8 @@ def test_tile_table_parsing(tmp_path):
     import subprocess
     import sys
     tab = tmp_path / "t.txt"
-    tab.write_text("# comment\nN f64 native 8 1 2 : stream 2 4 6 1 1\nT f64 native 4 4 2 : splitk 4 4 2 300 1\n")
+    tab.write_text("# comment\nN f64 native 8 1 2 : stream 2 4 6 1 1\nT f64 native 4 4 2 : splitk 4 4 2 300 1\n"
+                   "B f32 native 0 0 0 : batched 0 8 1 1 1 2048\n")
     code = (
         "from paper_2208_08088_amd import tsmm as T\n"
         "p = T.plan_with_caps(1 << 23, 8, 8, 'N'); i = p.info(); t = p.get_tile()\n"
@@ -183,6 +184,14 @@ def test_tile_table_parsing(tmp_path):
                          env=dict(os.environ, TSMM_TILE_TABLE=str(bad), TSMM_STRICT_TABLE="1"),
                          capture_output=True, text=True)
     assert out.returncode != 0 and "tile table" in out.stderr
+    # a batched entry needs the chunk field and the batched kernel, and only
+    # the batched layout takes that kernel
+    for line in ("B f32 native 0 0 0 : batched 0 8 1 1 1\n", "B f32 native 0 0 0 : stream 0 8 1 1 1 2048\n",
+                 "N f64 native 8 1 2 : batched 2 4 6 1 1\n"):
+        bad.write_text("N f64 native 8 1 2 : stream 2 4 6 1 1\n" + line)
+        out = subprocess.run([sys.executable, "-c", code2], cwd=ROOT, env=dict(os.environ, TSMM_TILE_TABLE=str(bad)),
+                             capture_output=True, text=True)
+        assert out.returncode == 0 and "ok" in out.stdout, (line, out.stderr)
 
 
 def test_valu64_tile_rules(T):

@@ -99,6 +99,49 @@ def test_graph_replays_match_eager(dtype):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_chunk_size_does_not_change_results(dtype):
+    # the chunk size only changes which workgroup computes which rows; each
+    # row runs the same code, so the results are bitwise the same
+    count = 24
+    ms, ns, ks, As, Bs, Ah, Bh = make_case(count, 72, dtype, m_hi=9000)
+    packs = [T.pack(b) for b in Bs]
+    Cs = [torch.zeros((int(ms[b]), int(ns[b])), dtype=torch.float32, device="cuda") for b in range(count)]
+    bp = T.plan_batched(ms, ns, ks, dtype)
+    t = bp.get_tile()
+    assert t["kernel"] == T.KERNEL_BATCHED and t["chunk_rows"] >= 256
+    assert "kernel=batched" in bp.describe()
+    announce("chunk default", dtype, t["chunk_rows"])
+    bp.execute(As, packs, Cs)
+    ref = [c.clone() for c in Cs]
+    for chunk in (256, 1024, 65536):
+        announce("chunk", dtype, chunk)
+        bp.set_chunk_rows(chunk)
+        assert bp.get_tile()["chunk_rows"] == chunk
+        for c in Cs:
+            c.zero_()
+        bp.execute()
+        for b in range(count):
+            assert torch.equal(Cs[b], ref[b]), (chunk, b)
+    for b in range(count):
+        if ms[b]:
+            assert_normwise(host(Cs[b]), oracle.gemm_n(Ah[b], Bh[b]), 1e-6 if dtype == torch.float32 else 1e-5)
+    # a graph fixes the chunk list it captured
+    g = bp.graph()
+    with pytest.raises(T.TsmmError) as e:
+        bp.set_chunk_rows(2048)
+    assert e.value.status == T.INVALID_VALUE
+    del g
+    bp.set_chunk_rows(2048)
+    for bad in (300, 128, 1 << 17):
+        with pytest.raises(T.TsmmError) as e:
+            bp.set_chunk_rows(bad)
+        assert e.value.status == T.INVALID_VALUE
+    with pytest.raises(T.TsmmError) as e:
+        T._set_tile(bp.handle, kernel=T.KERNEL_STREAM)
+    assert e.value.status == T.NOT_SUPPORTED
+
+
 def test_batched_validation():
     bp = T.plan_batched([100, 200], [8, 16], [8, 16], torch.float32)
     A = [torch.zeros((100, 8), device="cuda"), torch.zeros((200, 16), device="cuda")]
