@@ -285,9 +285,28 @@ def extras_precision(torch, T, I, steps, warmup):
     return out, keep
 
 
+def loop_ms(torch, T, plans, As, packs, Cs, steps, warmup):
+    """Median milliseconds of one pass of single executes over every instance."""
+    def one():
+        for p, A, pk, C in zip(plans, As, packs, Cs):
+            T.execute(p, A, pk, C, 1.0, 0.0)
+    for _ in range(warmup):
+        one()
+    timer = Timer(torch)
+    for _ in range(steps):
+        e0 = timer.start()
+        one()
+        timer.stop("loop", e0)
+    return float(np.median(timer.per_key_ms()["loop"]))
+
+
 def extras_batched(torch, T, I, steps, warmup):
+    """The 512-instance batched launch (graph replay), binary32 and bfloat16
+    inputs; beside it, the same instances as 512 single executes in plain
+    binary32 and in binary64 (on binary64 copies)."""
     count = 512
     ms_, ns_, ks_ = I.batched_shapes(count, I.BASE_SEED)
+    sample = list(range(0, count, 64))  # instances whose first rows the CPU leg checks
     out = {}
     keep = {}
     for dname, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
@@ -315,10 +334,35 @@ def extras_batched(torch, T, I, steps, warmup):
             g.launch()
             timer.stop(dname, e0)
         ms = float(np.median(timer.per_key_ms()[dname]))
-        out[dname] = dict(instances=count, plan=bp.describe(), us=ms * 1e3, GB_s=byt / ms / 1e6,
-                          hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, TFLOP_s=fl / ms / 1e9, bytes=byt,
-                          roofline_us=t_roof * 1e6, roofline_frac=t_roof / (ms * 1e-3))
-        keep[dname] = (As, packs, Cs, bp, g)
+        row = dict(instances=count, plan=bp.describe(), us=ms * 1e3, GB_s=byt / ms / 1e6,
+                   hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, TFLOP_s=fl / ms / 1e9, bytes=byt,
+                   roofline_us=t_roof * 1e6, roofline_frac=t_roof / (ms * 1e-3))
+        torch.cuda.synchronize()
+        keep[dname] = [(As[b][:1024].cpu().float().numpy(), T.unpack(packs[b]).cpu().float().numpy(),
+                        Cs[b][:1024].cpu().numpy()) for b in sample]
+        if dt == torch.float32:
+            # the same instances one execute at a time: plain binary32 ...
+            plans = [T.plan(int(ms_[b]), int(ns_[b]), int(ks_[b]), "N", dt) for b in range(count)]
+            l32 = loop_ms(torch, T, plans, As, packs, Cs, steps, warmup)
+            # ... and binary64 on binary64 copies of the same values
+            del g, bp
+            A64 = [a.double() for a in As]
+            del As
+            B64 = [T.pack(T.unpack(pk).double()) for pk in packs]
+            del packs, Cs
+            C64 = [torch.empty((int(ms_[b]), int(ns_[b])), dtype=torch.float64, device="cuda") for b in range(count)]
+            plans64 = [T.plan(int(ms_[b]), int(ns_[b]), int(ks_[b]), "N", torch.float64) for b in range(count)]
+            l64 = loop_ms(torch, T, plans64, A64, B64, C64, steps, warmup)
+            del A64, B64, C64
+            torch.cuda.empty_cache()
+            row.update(loop_f32_us=l32 * 1e3, loop_f64_us=l64 * 1e3, speedup_vs_loop_f32=l32 / ms,
+                       speedup_vs_loop_f64=l64 / ms)
+            loops = (l32, l64)
+        else:
+            row.update(speedup_vs_loop_f32=loops[0] / ms, speedup_vs_loop_f64=loops[1] / ms)
+            del g, bp, As, packs, Cs
+            torch.cuda.empty_cache()
+        out[dname] = row
     return out, keep
 
 
@@ -455,7 +499,7 @@ def main():
         torch.cuda.empty_cache()
         bat, keep_b = extras_batched(torch, T, I, args.steps, args.warmup)
         print("[bench] batched done", file=sys.stderr, flush=True)
-        del keep_b, keep_t
+        del keep_t
         result["extras"] = dict(small_4096x16=small, op_t_splitk=opt, precision_m2p24_k256=prec,
                                 batched_512=bat)
 
@@ -467,6 +511,9 @@ def main():
             ref = oracle.gemm_n(keep_p["A_rows"], keep_p["B"], threads=len(os.sched_getaffinity(0)))
             for name, row in result["extras"]["precision_m2p24_k256"].items():
                 row["sample_err"] = oracle.normwise_rel_err(keep_p[name], ref)
+            # batched: the first rows of every 64th instance
+            for name, row in result["extras"]["batched_512"].items():
+                row["sample_err"] = max(oracle.normwise_rel_err(C, oracle.gemm_n(A, B)) for A, B, C in keep_b[name])
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(result), flush=True)
 
