@@ -110,8 +110,15 @@ typedef enum tsmm_kernel {
                                   matrix-core accumulators, packed B streams
                                   through LDS in 32-row slabs; A and C 16-byte
                                   aligned                                    */
-    TSMM_KERNEL_BATCHED = 7    /* batched plans only: the persistent launch
+    TSMM_KERNEL_BATCHED = 7,   /* batched plans only: the persistent launch
                                   over chunks of instance rows               */
+    TSMM_KERNEL_SLAB = 8       /* op N TSMM_F64 / TSMM_F32 (native) with a long
+                                  k (beyond 256, up to 2^20; also any k class
+                                  of 32 and more), n <= 256: a wavefront keeps
+                                  its rows' accumulators for all n columns,
+                                  packed B streams through LDS in 32-k slabs;
+                                  splitk cuts the k range (binary64 partials,
+                                  ordered second pass)                       */
 } tsmm_kernel;
 
 /* One entry of the tile table: the register/LDS blocking and launch shape
@@ -127,7 +134,8 @@ typedef struct tsmm_tile {
     int32_t waves_per_wg;  /* wavefronts per workgroup: 1..16               */
     int32_t wg_per_cu;     /* resident workgroups per compute unit (grid =
                               CUs * wg_per_cu, capped by the work): 1..32   */
-    int32_t splitk;        /* op T: number of partial sums P (1..65536)     */
+    int32_t splitk;        /* op T: number of partial sums P (1..65536);
+                              TSMM_KERNEL_SLAB: parts of the k range        */
     int32_t nsplit;        /* op N: column groups sharing one row block     */
     int32_t chunk_rows;    /* batched plans: rows of one instance that a
                               workgroup takes per work item, a power of two

@@ -71,6 +71,7 @@ const char *kernel_name(int k) {
     case TSMM_KERNEL_VALU64: return "valu64";
     case TSMM_KERNEL_WIDE: return "wide";
     case TSMM_KERNEL_BATCHED: return "batched";
+    case TSMM_KERNEL_SLAB: return "slab";
     default: return "auto";
     }
 }
@@ -164,6 +165,7 @@ int parse_kernel(const std::string &s) {
     if (s == "valu64") return TSMM_KERNEL_VALU64;
     if (s == "wide") return TSMM_KERNEL_WIDE;
     if (s == "batched") return TSMM_KERNEL_BATCHED;
+    if (s == "slab") return TSMM_KERNEL_SLAB;
     return -1;
 }
 
@@ -235,12 +237,29 @@ bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 constexpr size_t kLdsBudget = 128 * 1024;  // packed-B bytes a workgroup may keep in LDS
 
+// Packed depth of the 16x16x4 fragment image: the k class, or for k past
+// the classes a multiple of the slab depth (0: no image).
+int64_t frag4_depth(int64_t k) {
+    if (kclass4(k)) return kclass4(k);
+    return k <= kSlabMaxK ? (k + kSlabK - 1) / kSlabK * kSlabK : 0;
+}
+
+// Shapes the k-slab kernel serves: op N binary64 / binary32 native, n <= 256
+// (binary32: n > 16, the smallest slab it moves), a fragment image whose
+// depth is a multiple of the slab.
+bool slab_ok(const tsmm_plan_s &p) {
+    const int NT = ntclass(p.n);
+    return p.layout == TSMM_OP_N && p.mode == TSMM_MODE_NATIVE && (p.dtype == TSMM_F64 || p.dtype == TSMM_F32) &&
+           NT > 0 && (p.dtype == TSMM_F64 || NT >= 2) && frag4_depth(p.k) % kSlabK == 0 && frag4_depth(p.k) > 0;
+}
+
 // Which kernel family serves (layout, dtype, mode, shape)?
 int natural_kernel(const tsmm_plan_s &p) {
     if (p.layout == TSMM_OP_T) return p.dtype == TSMM_F64 ? TSMM_KERNEL_SPLITK : TSMM_KERNEL_SIMPLE;
     if (p.dtype == TSMM_BF16 || p.mode != TSMM_MODE_NATIVE)
         return (kclass32(p.k) && ntclass(p.n)) ? TSMM_KERNEL_SPLITBF16 : TSMM_KERNEL_SIMPLE;
-    return (kclass4(p.k) && ntclass(p.n)) ? TSMM_KERNEL_STREAM : TSMM_KERNEL_SIMPLE;
+    if (kclass4(p.k) && ntclass(p.n)) return TSMM_KERNEL_STREAM;
+    return slab_ok(p) ? TSMM_KERNEL_SLAB : TSMM_KERNEL_SIMPLE;
 }
 
 bool wide_ok(const tsmm_plan_s &p) { return wide_shape(p.layout, p.dtype, p.k, p.n); }
@@ -258,8 +277,32 @@ bool eligible(const tsmm_plan_s &p, int kernel) {
     case TSMM_KERNEL_SIMPLE: return p.mode == TSMM_MODE_NATIVE;
     case TSMM_KERNEL_VALU64: return valu64_ok(p);
     case TSMM_KERNEL_WIDE: return wide_ok(p);
+    case TSMM_KERNEL_SLAB: return slab_ok(p);
     default: return kernel == natural_kernel(p);
     }
+}
+
+// Parts of the k range for the k-slab kernel: the row blocks alone fill
+// the device in whole waves of workgroups when there are many of them;
+// otherwise the smallest split (at most 16, at most one part per slab)
+// whose items fill the last wave to 90%, else the best filled.
+int slab_splitk(const tsmm_plan_s &p, int RT) {
+    const int64_t cus = std::max(1, p.caps.compute_units);
+    const int64_t nrb = (p.m + slab_rows(RT) - 1) / slab_rows(RT);
+    const int64_t nsl = std::max<int64_t>(1, frag4_depth(p.k) / kSlabK);
+    if (nrb >= 8 * cus) return 1;
+    int best = 1;
+    double best_fill = 0.0;
+    for (int s = 1; s <= 16 && s <= nsl; ++s) {
+        const int64_t items = nrb * s;
+        const double fill = (double)items / (double)(((items + cus - 1) / cus) * cus);
+        if (fill >= 0.9) return s;
+        if (fill > best_fill + 1e-9) {
+            best_fill = fill;
+            best = s;
+        }
+    }
+    return best;
 }
 
 int pow2_tiles(int64_t d) {  // 16-wide tiles of a small dimension, as 1, 2 or 4
@@ -313,6 +356,17 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
         t.rows_per_wave = (p.n == 128 && p.mode == TSMM_MODE_NATIVE) ? 4 : 2;
         t.wg_per_cu = 1;
         break;
+    case TSMM_KERNEL_SLAB: {
+        // row tiles per wavefront: accumulators (RT * NT tiles of 8 or 4
+        // registers) and two A register sets (2 * RT * 8 values) within
+        // about 200 registers, at most 4
+        const int NT = ntclass(p.n), regs = p.dtype == TSMM_F64 ? 8 : 4;
+        t.rows_per_wave = 4;
+        while (t.rows_per_wave > 1 && t.rows_per_wave * (NT * regs + 2 * 2 * regs) > 200) t.rows_per_wave /= 2;
+        t.wg_per_cu = 1;
+        t.splitk = slab_splitk(p, t.rows_per_wave);
+        break;
+    }
     case TSMM_KERNEL_SPLITK:
         t.rows_per_wave = 2;  // RG: 4-row groups per wavefront iteration
         t.wg_per_cu = 2;
@@ -429,6 +483,31 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
                         "the wide kernel runs one workgroup of 4 wavefronts per compute unit, no column split");
         const int64_t tiles = (p.m + wide_rows_per_wg(t.rows_per_wave) - 1) / wide_rows_per_wg(t.rows_per_wave);
         p.grid = std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
+        break;
+    }
+    case TSMM_KERNEL_SLAB: {
+        const int64_t depth = frag4_depth(p.k);
+        p.KC = (int)depth;
+        p.NT = ntclass(p.n);
+        p.vec = vec_mapping(p.dtype, p.k, p.KC);
+        const bool il = frag4_pg(p.dtype, p.NT, p.n) > 1;
+        if (!slab_variant_exists(p.dtype, p.NT, t.rows_per_wave, p.vec, il))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no k-slab kernel for NT=%d RT=%d", p.NT, t.rows_per_wave);
+        if (t.waves_per_wg != 4 || t.wg_per_cu != 1 || t.nsplit != 1)
+            return fail(TSMM_ERROR_INVALID_VALUE,
+                        "the k-slab kernel runs one workgroup of 4 wavefronts per compute unit, no column split");
+        const int64_t nsl = depth / kSlabK;
+        if (t.splitk > nsl || t.splitk > 64)
+            return fail(TSMM_ERROR_INVALID_VALUE, "splitk %d: at most 64 and at most one part per 32-k slab (%" PRId64
+                                                  ")", t.splitk, nsl);
+        // the slab double buffer, the Eq. (2) analogue
+        const size_t lds = 2 * (size_t)(kSlabK / 4) * p.NT * 64 * elem_bytes(p.dtype);
+        if ((int64_t)lds > p.caps.lds_bytes_per_cu)
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "two slabs of packed B (%zu bytes) exceed LDS", lds);
+        const int64_t nrb = (p.m + slab_rows(t.rows_per_wave) - 1) / slab_rows(t.rows_per_wave);
+        p.grid = std::max<int64_t>(1, std::min<int64_t>(nrb * t.splitk, cus));
+        if (t.splitk > 1)
+            p.workspace_bytes = (size_t)t.splitk * (size_t)((p.m + 15) / 16) * p.NT * 64 * 4 * sizeof(double);
         break;
     }
     case TSMM_KERNEL_SPLITK: {
@@ -670,7 +749,7 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
             off = align(off + (size_t)n * 4);
         }
     } else {
-        L.KC = kclass4(k);
+        L.KC = (int)frag4_depth(k);
         L.NT = ntclass(n);
         if (L.KC && L.NT) {
             L.vec = vec_mapping(dtype, k, L.KC);
@@ -820,7 +899,7 @@ tsmm_status tsmm_plan_set_tile(tsmm_plan_t p, const tsmm_tile *tile) {
     g_err.clear();
     if (!p || !tile) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
     if (p->batched) return set_batched_tile(*p, *tile);
-    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_WIDE)
+    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_SLAB || tile->kernel == TSMM_KERNEL_BATCHED)
         return fail(TSMM_ERROR_INVALID_VALUE, "bad kernel id %d", tile->kernel);
     if (tile->chunk_rows != 0) return fail(TSMM_ERROR_INVALID_VALUE, "chunk_rows is for batched plans");
     tsmm_plan_s trial = *p;
@@ -906,6 +985,29 @@ void tsmm_plan_destroy(tsmm_plan_t p) {
 
 // --------------------------------------------------------------- execute
 
+}  // extern "C"
+
+namespace {
+// The plan's device scratch: the caller's (tsmm_plan_set_workspace), else
+// allocated on first use and owned by the plan.
+tsmm_status ensure_workspace(tsmm_plan_s &p) {
+    if (p.workspace_bytes == 0 || (p.workspace && p.workspace_size >= p.workspace_bytes)) return TSMM_SUCCESS;
+    if (p.owns_workspace && p.workspace) (void)hipFree(p.workspace);
+    p.workspace = nullptr;
+    p.owns_workspace = false;
+    void *ws = nullptr;
+    hipError_t e = hipMalloc(&ws, p.workspace_bytes);
+    if (e != hipSuccess)
+        return fail(TSMM_ERROR_OUT_OF_MEMORY, "workspace (%zu bytes): %s", p.workspace_bytes, hipGetErrorString(e));
+    p.workspace = ws;
+    p.workspace_size = p.workspace_bytes;
+    p.owns_workspace = true;
+    return TSMM_SUCCESS;
+}
+}  // namespace
+
+extern "C" {
+
 tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, void *C, double alpha,
                          double beta) {
     g_err.clear();
@@ -978,17 +1080,24 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
                                                     : nullptr,
                         C, p->m, p->n, p->k, alpha, beta, p->grid, s);
         break;
-    case TSMM_KERNEL_SPLITK: {
-        if (!p->workspace) {
-            void *ws = nullptr;
-            e = hipMalloc(&ws, p->workspace_bytes);
-            if (e != hipSuccess)
-                return fail(TSMM_ERROR_OUT_OF_MEMORY, "split-k workspace (%zu bytes): %s", p->workspace_bytes,
-                            hipGetErrorString(e));
-            p->workspace = ws;
-            p->workspace_size = p->workspace_bytes;
-            p->owns_workspace = true;
+    case TSMM_KERNEL_SLAB: {
+        const bool il = frag4_pg(p->dtype, p->NT, p->n) > 1;
+        if ((p->vec && (reinterpret_cast<uintptr_t>(A) & 15)) || (il && (reinterpret_cast<uintptr_t>(C) & 15))) {
+            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
+            break;
         }
+        if (packed->L.KC != p->KC || packed->L.NT != p->NT)
+            return fail(TSMM_ERROR_SHAPE_MISMATCH, "packed operand has no image for the k-slab kernel");
+        tsmm_status st = ensure_workspace(*p);
+        if (st != TSMM_SUCCESS) return st;
+        e = launch_slab(p->dtype, p->NT, p->tile.rows_per_wave, p->vec, il, A, base + packed->L.off_frag, C,
+                        static_cast<double *>(p->workspace), p->m, p->n, p->k, p->KC, alpha, beta, p->tile.splitk,
+                        p->grid, s);
+        break;
+    }
+    case TSMM_KERNEL_SPLITK: {
+        tsmm_status st = ensure_workspace(*p);
+        if (st != TSMM_SUCCESS) return st;
         e = launch_splitk(p->KC, p->NT, p->tile.rows_per_wave, static_cast<const double *>(A),
                           static_cast<const double *>(packed->ref), static_cast<double *>(p->workspace),
                           static_cast<double *>(C), p->k, p->m, p->n, p->tile.splitk, alpha, beta, p->block, s);

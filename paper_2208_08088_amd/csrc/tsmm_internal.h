@@ -66,6 +66,10 @@ namespace tsmm {
 // 0 outside k x n.
 
 constexpr int kMaxKC = 256;  // largest packed k class of the fragment kernels
+// The k-slab kernel (long shared dimension): k per slab of packed B, and
+// the largest k it takes.
+constexpr int kSlabK = 32;
+constexpr int64_t kSlabMaxK = (int64_t)1 << 20;
 constexpr int kMaxNT = 16;   // largest number of 16-column tiles (n <= 256)
 
 inline int elem_bytes(tsmm_dtype d) { return d == TSMM_F64 ? 8 : (d == TSMM_F32 ? 4 : 2); }
@@ -269,6 +273,16 @@ hipError_t launch_splitk(int MT, int NT, int RG, const double *A, const double *
                          double *C, int64_t K, int64_t m, int64_t n, int P, double alpha,
                          double beta, int block, hipStream_t s);
 bool splitk_variant_exists(int MT, int NT, int RG);
+
+// op N, long k: packed B (16x16x4 fragment order over KCimg = a multiple of
+// kSlabK) streamed through LDS in k-slabs, splitk parts of the k range
+// (W: splitk * ceil(m/16) * NT * 64 * 4 binary64 partials when splitk > 1,
+// then an ordered second pass).
+hipError_t launch_slab(tsmm_dtype dt, int NT, int RT, bool vec, bool il, const void *A, const void *Bf, void *C,
+                       double *W, int64_t m, int64_t n, int64_t k, int KCimg, double alpha, double beta, int splitk,
+                       int64_t grid, hipStream_t s);
+bool slab_variant_exists(tsmm_dtype dt, int NT, int RT, bool vec, bool il);
+int slab_rows(int RT);  // rows of one work item (four wavefronts of RT 16-row tiles)
 
 // Batched persistent launch: workgroup w runs work tiles
 // [wg_begin[w], wg_begin[w+1]) of the instance sequence described by

@@ -25,7 +25,7 @@ F64, F32, BF16 = 0, 1, 2
 OP_N, OP_T = 0, 1
 MODE_NATIVE, MODE_BF16X3, MODE_BF16X6 = 0, 1, 2
 (KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_STREAM, KERNEL_SPLITK, KERNEL_SPLITBF16, KERNEL_VALU64, KERNEL_WIDE,
- KERNEL_BATCHED) = range(8)
+ KERNEL_BATCHED, KERNEL_SLAB) = range(9)
 
 _MODES = {"native": MODE_NATIVE, "bf16x3": MODE_BF16X3, "bf16x6": MODE_BF16X6}
 _LAYOUTS = {"N": OP_N, "T": OP_T}

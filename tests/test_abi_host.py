@@ -107,7 +107,8 @@ def test_plan_geometry_from_caps(T):
     assert int(T.plan_with_caps(16, 16, 16, "N").info()["grid"].split("x")[0]) == 1
     # beyond the fragment classes: the any-shape kernel
     assert T.plan_with_caps(100, 300, 16, "N").info()["kernel"] == "simple"
-    assert T.plan_with_caps(100, 16, 1000, "N").info()["kernel"] == "simple"
+    # k beyond the classes: the k-slab kernel
+    assert T.plan_with_caps(100, 16, 1000, "N").info()["kernel"] == "slab"
 
 
 def test_plan_splitk_workspace(T):
@@ -251,3 +252,46 @@ def test_wide_tile_rules(T):
     # op T never
     with pytest.raises(T.TsmmError):
         T.plan_with_caps(256, 256, 4096, "T", dtype=f32).set_tile(kernel=T.KERNEL_WIDE)
+
+
+def test_slab_tile_rules(T):
+    torch = __import__("torch")
+    # the paper's workload: square A (25600 x 25600) times B 25600 x 240.
+    # binary64: 1 row tile per wavefront (16 tiles x 8 accumulator
+    # registers), 64-row blocks -> 400 blocks; 3 parts of k fill 1200 of
+    # 1280 workgroup slots (the fewest parts that fill 90%)
+    p = T.plan_with_caps(25600, 240, 25600, "N")
+    t, info = p.get_tile(), p.info()
+    assert info["kernel"] == "slab" and t["rows_per_wave"] == 1 and t["splitk"] == 3
+    assert info["kc"] == "25600" and info["nt"] == "16" and info["grid"] == "256x1"
+    assert p.workspace_bytes() == 3 * 1600 * 16 * 64 * 4 * 8
+    # binary32: 2 row tiles (128-row blocks -> 200), 5 parts
+    q = T.plan_with_caps(25600, 240, 25600, "N", dtype=torch.float32)
+    assert q.info()["kernel"] == "slab" and q.get_tile()["rows_per_wave"] == 2 and q.get_tile()["splitk"] == 5
+    # enough row blocks: no split, no workspace
+    r = T.plan_with_caps(1 << 22, 64, 1000, "N")
+    assert r.info()["kernel"] == "slab" and r.get_tile()["splitk"] == 1 and r.workspace_bytes() == 0
+    assert r.info()["kc"] == "1024"  # 1000 rounded up to whole 32-k slabs
+    r.set_tile(kernel=T.KERNEL_SLAB, splitk=3)
+    assert r.workspace_bytes() == 3 * (1 << 18) * 4 * 64 * 4 * 8
+    # k within the streaming classes: streaming by default, slab on request
+    s = T.plan_with_caps(100000, 64, 128, "N")
+    assert s.info()["kernel"] == "stream"
+    s.set_tile(kernel=T.KERNEL_SLAB)
+    assert s.info()["kernel"] == "slab" and s.info()["kc"] == "128"
+    bad = [
+        (dict(m=1000, n=64, k=1000), dict(splitk=33)),          # more parts than 32-k slabs
+        (dict(m=1000, n=64, k=1000), dict(wg_per_cu=2)),
+        (dict(m=1000, n=64, k=1000), dict(nsplit=2)),
+        (dict(m=1000, n=256, k=1000), dict(rows_per_wave=4)),   # 512 accumulator registers: no instantiation
+        (dict(m=1000, n=64, k=16), {}),                         # k class 16: not whole slabs
+    ]
+    for shape, extra in bad:
+        with pytest.raises(T.TsmmError):
+            T.plan_with_caps(shape["m"], shape["n"], shape["k"], "N").set_tile(kernel=T.KERNEL_SLAB, **extra)
+    # binary32 with n <= 16 and k beyond the classes, and k past 2^20: the
+    # any-shape kernel
+    assert T.plan_with_caps(1000, 16, 1000, "N", dtype=torch.float32).info()["kernel"] == "simple"
+    assert T.plan_with_caps(100, 64, (1 << 20) + 32, "N").info()["kernel"] == "simple"
+    with pytest.raises(T.TsmmError):
+        T.plan_with_caps(1000, 64, 1000, "N", dtype=torch.bfloat16).set_tile(kernel=T.KERNEL_SLAB)
