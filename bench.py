@@ -12,11 +12,12 @@ algorithmic HBM bytes of a step (A once, C once, plus C once more when
 beta = 1; packing excluded, as the paper excludes it) over the wall time of
 the step: GB/s, whole job.
 
-Extras (same run, reported beside the headline): the op T split-k shape
-(C(64x64) = A^T B, A and B 2^22 x 64), the binary32 precision comparison
-(m = 2^24, k = n = 256: binary32 products, split-bf16 x3 / x6, binary64 on
-binary64 copies) and the batched persistent launch (512 uneven instances,
-replayed from a HIP graph).
+Extras (same run, reported beside the headline): the 4096 x 16 latency
+case, the op T split-k shape (C(64x64) = A^T B, A and B 2^22 x 64), the
+binary32 precision comparison (m = 2^24, k = n = 256: binary32 products,
+split-bf16 x3 / x6, binary64 on binary64 copies), the batched persistent
+launch (512 uneven instances, replayed from a HIP graph) and the paper's
+own shape (square A 25600 x 25600 times B 25600 x N, N in {16, 64, 240}).
 
 The `roofline` object is for the kernel that takes the most time in a step,
 timed with HIP events on the stream it runs on; `cpu_baseline` times the
@@ -285,6 +286,40 @@ def extras_precision(torch, T, I, steps, warmup):
     return out, keep
 
 
+def extras_square(torch, T, I, steps, warmup):
+    """The paper's own workload shape: square A (25600 x 25600) times a
+    tall-and-skinny B (25600 x N), binary64 and binary32, alpha 1, beta 0
+    (the k-slab kernel).  GFLOP/s is the paper's figure of merit."""
+    M = K = 25600
+    out, keep = {}, {}
+    rows = torch.from_numpy(I.sample_rows(M, 16, 23)).cuda()
+    for dname, dt, peak in (("f64", torch.float64, PEAK_TFLOPS["f64"]), ("f32", torch.float32, PEAK_TFLOPS["f32"])):
+        A = I.device_uniform((M, K), I.BASE_SEED, 61, dt)
+        for N in (16, 64, 240):
+            B = I.device_uniform((K, N), I.BASE_SEED, 62 + N, dt)
+            C = torch.empty((M, N), dtype=dt, device="cuda")
+            p = T.plan(M, N, K, "N", dt)
+            pk = T.pack(B)
+            for _ in range(warmup):
+                T.execute(p, A, pk, C, 1.0, 0.0)
+            timer = Timer(torch)
+            for _ in range(steps):
+                e0 = timer.start()
+                T.execute(p, A, pk, C, 1.0, 0.0)
+                timer.stop("sq", e0)
+            ms = float(np.median(timer.per_key_ms()["sq"]))
+            fl = 2.0 * M * N * K
+            byt = (M * K + K * N + M * N) * A.element_size()
+            name = "%s_n%d" % (dname, N)
+            out[name] = dict(plan=p.describe(), us=ms * 1e3, TFLOP_s=fl / ms / 1e9, mfma_frac=fl / ms / 1e9 / peak,
+                             GB_s=byt / ms / 1e6)
+            keep[name] = (A[rows].cpu().numpy(), B.cpu().numpy(), C[rows].cpu().numpy())
+            del B, C, pk
+        del A
+        torch.cuda.empty_cache()
+    return out, keep
+
+
 def loop_ms(torch, T, plans, As, packs, Cs, steps, warmup):
     """Median milliseconds of one pass of single executes over every instance."""
     def one():
@@ -499,9 +534,11 @@ def main():
         torch.cuda.empty_cache()
         bat, keep_b = extras_batched(torch, T, I, args.steps, args.warmup)
         print("[bench] batched done", file=sys.stderr, flush=True)
+        sq, keep_q = extras_square(torch, T, I, max(3, args.steps // 4), args.warmup)
+        print("[bench] square done", file=sys.stderr, flush=True)
         del keep_t
         result["extras"] = dict(small_4096x16=small, op_t_splitk=opt, precision_m2p24_k256=prec,
-                                batched_512=bat)
+                                batched_512=bat, square_25600=sq)
 
     if not args.no_cpu_baseline and not args.only:
         result["cpu_baseline"] = cpu_baseline(torch, I, cases, keep_s)
@@ -511,6 +548,10 @@ def main():
             ref = oracle.gemm_n(keep_p["A_rows"], keep_p["B"], threads=len(os.sched_getaffinity(0)))
             for name, row in result["extras"]["precision_m2p24_k256"].items():
                 row["sample_err"] = oracle.normwise_rel_err(keep_p[name], ref)
+            # square A: 16 sampled rows of each case
+            for name, row in result["extras"]["square_25600"].items():
+                A, B, C = keep_q[name]
+                row["sample_err"] = oracle.normwise_rel_err(C, oracle.gemm_n(A, B, threads=len(os.sched_getaffinity(0))))
             # batched: the first rows of every 64th instance
             for name, row in result["extras"]["batched_512"].items():
                 row["sample_err"] = max(oracle.normwise_rel_err(C, oracle.gemm_n(A, B)) for A, B, C in keep_b[name])

@@ -54,6 +54,9 @@ CLASSES = {
     "n_f32x6_k256": ("N", torch.float32, "bf16x6", 1 << 24, 256, 256),
     "n_f32x3_k256": ("N", torch.float32, "bf16x3", 1 << 24, 256, 256),
     "t_f64_64x64": ("T", torch.float64, "native", 64, 64, 1 << 22),
+    # the paper's own shape: square A (25600 x 25600) x B (25600 x 240)
+    "n_f64_sq25600": ("N", torch.float64, "native", 25600, 240, 25600),
+    "n_f32_sq25600": ("N", torch.float32, "native", 25600, 240, 25600),
     # batched: the 512-instance workload (m uniform in [1024, 262144], k and
     # n from {4, ..., 128}); the tile is the chunk of rows a workgroup takes
     "b_f32_512": ("B", torch.float32, "native", 512, 0, 0),
@@ -87,7 +90,9 @@ def table_key(layout, dt, mode, m, n, k):
 def natural_kernel(p):
     if p.layout == T.OP_T:
         return T.KERNEL_SPLITK
-    return T.KERNEL_SPLITBF16 if (p.dtype == T.BF16 or p.mode != T.MODE_NATIVE) else T.KERNEL_STREAM
+    if p.dtype == T.BF16 or p.mode != T.MODE_NATIVE:
+        return T.KERNEL_SPLITBF16
+    return T.KERNEL_SLAB if p.k > 256 else T.KERNEL_STREAM
 
 
 def candidates(p):
@@ -123,6 +128,12 @@ def candidates(p):
             for rt in (1, 2):
                 for wpc in (1, 2, 4, 8):
                     out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=wpc, splitk=1, nsplit=ns))
+    elif kern == T.KERNEL_SLAB:
+        # parts of the long k range; row tiles per wavefront where an
+        # instantiation exists
+        for rt in (1, 2, 4):
+            for sk in sorted({nat["splitk"], 1, 2, 3, 4, 5, 6, 8, 12, 16}):
+                out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=1, splitk=sk, nsplit=1))
     elif kern == T.KERNEL_SPLITK:
         for rg in (1, 2, 4):
             for P in (256, 512, 1024, 2048):

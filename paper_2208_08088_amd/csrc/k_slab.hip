@@ -30,12 +30,16 @@ constexpr int kSlabSteps = kSlabK / 4;  // 16x16x4 k-steps per slab (kSlabK: tsm
 
 // This wavefront's share of slab sl of the packed image (NT fragments of
 // 64 lanes per k-step, kSlabSteps k-steps) into LDS: 1 KiB per LDS-DMA
-// load (lane l's 16 bytes land at base + 16*l).
+// load (lane l's 16 bytes land at base + 16*l).  A slab of fewer than four
+// pieces is moved by the first wavefronts, one piece each.
 template <typename T, int NT>
 __device__ __forceinline__ void slab_dma(__amdgpu_buffer_rsrc_t rb, int64_t sl, int wave, int lane, u32x4 *dst) {
     constexpr int BYTES = kSlabSteps * NT * 64 * (int)sizeof(T);
-    constexpr int PER = BYTES / 1024 / kSlabWaves;
-    static_assert(PER * 1024 * kSlabWaves == BYTES, "slab must split into whole 1 KiB pieces per wavefront");
+    constexpr int PIECES = BYTES / 1024;
+    static_assert(PIECES * 1024 == BYTES && (PIECES % kSlabWaves == 0 || PIECES < kSlabWaves),
+                  "slab must split into whole 1 KiB pieces");
+    constexpr int PER = PIECES >= kSlabWaves ? PIECES / kSlabWaves : 1;
+    if (PIECES < kSlabWaves && wave >= PIECES) return;
     u32x4 *d = dst + wave * PER * 64;
     // the image offset of a slab stays below 2^32 bytes (checked on the host)
     const int f0 = (int)(sl * BYTES) + wave * PER * 1024;
@@ -83,18 +87,33 @@ __device__ __forceinline__ void slab_load_a(const T *__restrict__ A, int64_t m, 
 }
 
 // The products of one slab: NT fragments of B per k-step from LDS, RT*NT
-// matrix-core products.
+// matrix-core products.  The fragments of k-step s + 1 are read into the
+// second register set while the products of step s run, one read between
+// every RT products (with one wavefront per SIMD nothing else hides the
+// LDS latency).
 template <typename T, int NT, int RT>
 __device__ __forceinline__ void slab_products(const T *__restrict__ sb, const T (&a)[RT][kSlabSteps],
                                               typename Mfma4<T>::acc (&acc)[RT][NT], int lane) {
+    T b[2][NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) b[0][t] = sb[t * 64 + lane];
 #pragma unroll
     for (int s = 0; s < kSlabSteps; ++s) {
+        const int c = s & 1;
+        if (s + 1 < kSlabSteps) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[c ^ 1][t] = sb[((s + 1) * NT + t) * 64 + lane];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc[rt][t] = Mfma4<T>::op(a[rt][s], b[c][t], acc[rt][t]);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const T b = sb[(s * NT + t) * 64 + lane];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt][t] = Mfma4<T>::op(a[rt][s], b, acc[rt][t]);
+            if (s + 1 < kSlabSteps) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, RT, 0);                        // RT products
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -280,7 +299,7 @@ static const SlabEntry kSlabTable[] = {
     TSMM_SLAB(double, TSMM_F64, 16, 1) TSMM_SLAB(double, TSMM_F64, 8, 2) TSMM_SLAB(double, TSMM_F64, 4, 2)
     TSMM_SLAB(double, TSMM_F64, 2, 4) TSMM_SLAB_PLAIN(double, TSMM_F64, 1, 4)
     TSMM_SLAB(float, TSMM_F32, 16, 2) TSMM_SLAB(float, TSMM_F32, 8, 4) TSMM_SLAB(float, TSMM_F32, 4, 4)
-    TSMM_SLAB_PLAIN(float, TSMM_F32, 2, 4)
+    TSMM_SLAB_PLAIN(float, TSMM_F32, 2, 4) TSMM_SLAB_PLAIN(float, TSMM_F32, 1, 4)
 };
 #undef TSMM_SLAB
 #undef TSMM_SLAB_PLAIN

@@ -244,13 +244,11 @@ int64_t frag4_depth(int64_t k) {
     return k <= kSlabMaxK ? (k + kSlabK - 1) / kSlabK * kSlabK : 0;
 }
 
-// Shapes the k-slab kernel serves: op N binary64 / binary32 native, n <= 256
-// (binary32: n > 16, the smallest slab it moves), a fragment image whose
-// depth is a multiple of the slab.
+// Shapes the k-slab kernel serves: op N binary64 / binary32 native, n <= 256,
+// a fragment image whose depth is a multiple of the slab.
 bool slab_ok(const tsmm_plan_s &p) {
-    const int NT = ntclass(p.n);
     return p.layout == TSMM_OP_N && p.mode == TSMM_MODE_NATIVE && (p.dtype == TSMM_F64 || p.dtype == TSMM_F32) &&
-           NT > 0 && (p.dtype == TSMM_F64 || NT >= 2) && frag4_depth(p.k) % kSlabK == 0 && frag4_depth(p.k) > 0;
+           ntclass(p.n) > 0 && frag4_depth(p.k) % kSlabK == 0 && frag4_depth(p.k) > 0;
 }
 
 // Which kernel family serves (layout, dtype, mode, shape)?

@@ -289,9 +289,8 @@ def test_slab_tile_rules(T):
     for shape, extra in bad:
         with pytest.raises(T.TsmmError):
             T.plan_with_caps(shape["m"], shape["n"], shape["k"], "N").set_tile(kernel=T.KERNEL_SLAB, **extra)
-    # binary32 with n <= 16 and k beyond the classes, and k past 2^20: the
-    # any-shape kernel
-    assert T.plan_with_caps(1000, 16, 1000, "N", dtype=torch.float32).info()["kernel"] == "simple"
+    # k past 2^20: the any-shape kernel
+    assert T.plan_with_caps(1000, 16, 1000, "N", dtype=torch.float32).info()["kernel"] == "slab"
     assert T.plan_with_caps(100, 64, (1 << 20) + 32, "N").info()["kernel"] == "simple"
     with pytest.raises(T.TsmmError):
         T.plan_with_caps(1000, 64, 1000, "N", dtype=torch.bfloat16).set_tile(kernel=T.KERNEL_SLAB)
