@@ -261,12 +261,15 @@ def test_slab_tile_rules(T):
     # registers), 64-row blocks -> 400 blocks; 3 parts of k fill 1200 of
     # 1280 workgroup slots (the fewest parts that fill 90%)
     p = T.plan_with_caps(25600, 240, 25600, "N")
+    assert p.info()["kernel"] == "slab"
+    p.set_tile(kernel=T.KERNEL_SLAB)  # the built-in default, whatever the tile table holds
     t, info = p.get_tile(), p.info()
-    assert info["kernel"] == "slab" and t["rows_per_wave"] == 1 and t["splitk"] == 3
+    assert t["rows_per_wave"] == 1 and t["splitk"] == 3
     assert info["kc"] == "25600" and info["nt"] == "16" and info["grid"] == "256x1"
     assert p.workspace_bytes() == 3 * 1600 * 16 * 64 * 4 * 8
     # binary32: 2 row tiles (128-row blocks -> 200), 5 parts
     q = T.plan_with_caps(25600, 240, 25600, "N", dtype=torch.float32)
+    q.set_tile(kernel=T.KERNEL_SLAB)
     assert q.info()["kernel"] == "slab" and q.get_tile()["rows_per_wave"] == 2 and q.get_tile()["splitk"] == 5
     # enough row blocks: no split, no workspace
     r = T.plan_with_caps(1 << 22, 64, 1000, "N")
