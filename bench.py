@@ -16,8 +16,9 @@ Extras (same run, reported beside the headline): the 4096 x 16 latency
 case, the op T split-k shape (C(64x64) = A^T B, A and B 2^22 x 64), the
 binary32 precision comparison (m = 2^24, k = n = 256: binary32 products,
 split-bf16 x3 / x6, binary64 on binary64 copies), the batched persistent
-launch (512 uneven instances, replayed from a HIP graph) and the paper's
-own shape (square A 25600 x 25600 times B 25600 x N, N in {16, 64, 240}).
+launch (512 uneven instances, replayed from a HIP graph), the paper's own
+shape (square A 25600 x 25600 times B 25600 x N, N in {16, 64, 240}) and
+the runtime evaluator on a shape class the tile table does not hold.
 
 The `roofline` object is for the kernel that takes the most time in a step,
 timed with HIP events on the stream it runs on; `cpu_baseline` times the
@@ -320,6 +321,41 @@ def extras_square(torch, T, I, steps, warmup):
     return out, keep
 
 
+def extras_tune(torch, T, I, steps, warmup):
+    """The runtime evaluator on a shape class the tile table does not hold
+    (binary64, m = 2^22, k = 24, n = 48): the built-in default tile against
+    the tile tsmm_plan_tune keeps, and the wall time of the tuning call."""
+    m, k, n = 1 << 22, 24, 48
+    A = I.device_uniform((m, k), I.BASE_SEED, 71, torch.float64)
+    pk = T.pack(I.device_uniform((k, n), I.BASE_SEED, 72, torch.float64))
+    C = torch.empty((m, n), dtype=torch.float64, device="cuda")
+
+    def time_plan(p):
+        for _ in range(warmup):
+            T.execute(p, A, pk, C, 1.0, 0.0)
+        timer = Timer(torch)
+        for _ in range(steps):
+            e0 = timer.start()
+            T.execute(p, A, pk, C, 1.0, 0.0)
+            timer.stop("t", e0)
+        return float(np.median(timer.per_key_ms()["t"]))
+
+    T.tune_cache_clear()
+    p = T.plan(m, n, k, "N", torch.float64)
+    before = p.describe()
+    t_default = time_plan(p)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    p.tune(A, pk, C, reps=3)
+    tune_s = time.perf_counter() - w0
+    t_tuned = time_plan(p)
+    T.tune_cache_clear()
+    byt = opn_bytes(m, n, k, 0.0)
+    return dict(shape="f64 m=2^22 k=24 n=48 (no table entry)", default_plan=before, tuned_plan=p.describe(),
+                default_us=t_default * 1e3, tuned_us=t_tuned * 1e3, default_GB_s=byt / t_default / 1e6,
+                tuned_GB_s=byt / t_tuned / 1e6, tune_wall_s=tune_s)
+
+
 def loop_ms(torch, T, plans, As, packs, Cs, steps, warmup):
     """Median milliseconds of one pass of single executes over every instance."""
     def one():
@@ -536,9 +572,11 @@ def main():
         print("[bench] batched done", file=sys.stderr, flush=True)
         sq, keep_q = extras_square(torch, T, I, max(3, args.steps // 4), args.warmup)
         print("[bench] square done", file=sys.stderr, flush=True)
+        tune = extras_tune(torch, T, I, args.steps, args.warmup)
+        print("[bench] runtime evaluator done", file=sys.stderr, flush=True)
         del keep_t
         result["extras"] = dict(small_4096x16=small, op_t_splitk=opt, precision_m2p24_k256=prec,
-                                batched_512=bat, square_25600=sq)
+                                batched_512=bat, square_25600=sq, runtime_evaluator=tune)
 
     if not args.no_cpu_baseline and not args.only:
         result["cpu_baseline"] = cpu_baseline(torch, I, cases, keep_s)

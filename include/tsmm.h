@@ -260,9 +260,32 @@ tsmm_status tsmm_plan_workspace_bytes(tsmm_plan_t plan, size_t *bytes);
 tsmm_status tsmm_plan_set_workspace(tsmm_plan_t plan, void *workspace,
                                     size_t bytes);
 
-/* A one-line text description of the plan (kernel, tile, grid); writes at
+/* A one-line text description of the plan (kernel, tile, grid; table=0
+ * built-in or caller's tile, 1 tile table, 2 runtime evaluator); writes at
  * most len bytes including the terminating NUL. */
 tsmm_status tsmm_plan_describe(tsmm_plan_t plan, char *buf, size_t len);
+
+/* Runtime stage of the paper's performance evaluator (Sec. III: when the
+ * install-time stage has no answer for a shape, candidate strategies are
+ * timed at run time and the fastest is kept).  Times each candidate tile of
+ * the plan's kernel family (and the wide kernels where they apply) on the
+ * caller's operands: one warm-up and `reps` (1..1000) executes with
+ * alpha = 1, beta = 0, HIP events on the plan's stream, median.  The
+ * fastest tile is set in the plan and remembered for the plan's shape
+ * class (the tile-table key) in this process: later tsmm_plan calls of the
+ * class start from it (describe: table=2).  C is overwritten (its contents
+ * afterwards are A*B); A and C follow tsmm_execute's rules.  The plan may
+ * allocate a larger workspace for a candidate.  Synchronous; best_ms
+ * (optional) receives the winner's median milliseconds (0 when nothing
+ * runs: m, n or k is 0).
+ * Errors: INVALID_VALUE (NULL arguments, batched plan, reps), NO_DEVICE
+ * (plan built for explicit caps), NOT_SUPPORTED, SHAPE_MISMATCH, HIP; on
+ * error the plan keeps its tile. */
+tsmm_status tsmm_plan_tune(tsmm_plan_t plan, const void *A, tsmm_packed_t packed, void *C, int reps,
+                           double *best_ms);
+
+/* Forget every tile tsmm_plan_tune remembered in this process. */
+void tsmm_tune_cache_clear(void);
 
 void tsmm_plan_destroy(tsmm_plan_t plan);
 

@@ -23,6 +23,7 @@
 #include <sstream>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "tsmm_internal.h"
 
@@ -592,24 +593,55 @@ tsmm_status set_batched_tile(tsmm_plan_s &p, const tsmm_tile &t) {
     return TSMM_SUCCESS;
 }
 
+// The tile-table key of a plan's shape class.
+TableKey plan_key(const tsmm_plan_s &p) {
+    TableKey key{};
+    key.layout = p.layout;
+    key.dtype = p.dtype;
+    key.mode = p.mode;
+    if (p.layout == TSMM_OP_N) {
+        key.kc = natural_kernel(p) == TSMM_KERNEL_SPLITBF16 ? kclass32(p.k) : kclass4(p.k);
+        key.nt = ntclass(p.n);
+        key.mclass = mclass_of(p.m);
+    } else {
+        key.kc = pow2_tiles(p.m);
+        key.nt = pow2_tiles(p.n);
+        key.mclass = mclass_of(p.k);
+    }
+    return key;
+}
+
+// Tiles the runtime evaluator (tsmm_plan_tune) chose in this process, by
+// shape class; they take precedence over the tile table.
+struct RuntimeCache {
+    std::mutex mu;
+    std::map<TableKey, tsmm_tile> entries;
+};
+RuntimeCache &runtime_cache() {
+    static RuntimeCache c;
+    return c;
+}
+
 tsmm_status choose_tile(tsmm_plan_s &p) {
     const int nat = natural_kernel(p);
     Table &tab = table();
-    p.tile_from_table = false;
-    if (tab.loaded) {
-        TableKey key{};
-        key.layout = p.layout;
-        key.dtype = p.dtype;
-        key.mode = p.mode;
-        if (p.layout == TSMM_OP_N) {
-            key.kc = nat == TSMM_KERNEL_SPLITBF16 ? kclass32(p.k) : kclass4(p.k);
-            key.nt = ntclass(p.n);
-            key.mclass = mclass_of(p.m);
-        } else {
-            key.kc = pow2_tiles(p.m);
-            key.nt = pow2_tiles(p.n);
-            key.mclass = mclass_of(p.k);
+    p.tile_from_table = 0;
+    {
+        RuntimeCache &rc = runtime_cache();
+        std::lock_guard<std::mutex> lock(rc.mu);
+        auto it = rc.entries.find(plan_key(p));
+        if (it != rc.entries.end() && eligible(p, it->second.kernel)) {
+            tsmm_plan_s trial = p;
+            if (apply_tile(trial, it->second) == TSMM_SUCCESS) {
+                p = trial;
+                p.tile_from_table = 2;
+                return TSMM_SUCCESS;
+            }
+            g_err.clear();
         }
+    }
+    if (tab.loaded) {
+        const TableKey key = plan_key(p);
         auto it = tab.entries.find(key);
         if (it != tab.entries.end() && eligible(p, it->second.kernel)) {
             tsmm_plan_s trial = p;
@@ -1109,6 +1141,122 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
         break;
     }
     return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "kernel launch");
+}
+
+// ------------------------------------------------------ runtime evaluator
+
+}  // extern "C"
+
+namespace {
+// Candidate tiles of the plan's kernel family (the paper's two search
+// patterns over the register / thread blocking: multiples of the tile under
+// the capacity bounds, and powers of two), the plan's current tile first.
+std::vector<tsmm_tile> tune_candidates(const tsmm_plan_s &p) {
+    std::vector<tsmm_tile> out;
+    out.push_back(p.tile);
+    auto add = [&](int kernel, int rt, int wpc, int sk, int ns) {
+        out.push_back(tsmm_tile{kernel, rt, 4, wpc, sk, ns, 0});
+    };
+    const int nat = natural_kernel(p);
+    const tsmm_tile d = default_tile(p, nat);
+    switch (nat) {
+    case TSMM_KERNEL_STREAM:
+        for (int ns : {d.nsplit, 2 * d.nsplit})
+            for (int rt : {1, 2, 4, 8})
+                for (int wpc : {1, 2, 4, 8, 16}) add(nat, rt, wpc, 1, ns);
+        break;
+    case TSMM_KERNEL_SPLITBF16:
+        for (int ns : {d.nsplit, 2 * d.nsplit})
+            for (int rt : {1, 2})
+                for (int wpc : {1, 2, 4, 8}) add(nat, rt, wpc, 1, ns);
+        break;
+    case TSMM_KERNEL_SPLITK:
+        for (int rg : {1, 2, 4})
+            for (int P : {256, 512, 1024, 2048}) add(nat, rg, 1, P, 1);
+        break;
+    case TSMM_KERNEL_SLAB:
+        for (int rt : {1, 2, 4})
+            for (int sk : {1, 2, 3, 4, 5, 6, 8, 12, 16}) add(nat, rt, 1, sk, 1);
+        break;
+    default:
+        break;
+    }
+    if (wide_ok(p))
+        for (int rt : {2, 4}) add(TSMM_KERNEL_WIDE, rt, 1, 1, 1);
+    return out;
+}
+}  // namespace
+
+extern "C" {
+
+tsmm_status tsmm_plan_tune(tsmm_plan_t p, const void *A, tsmm_packed_t packed, void *C, int reps, double *best_ms) {
+    g_err.clear();
+    if (!p || !packed || !C) return fail(TSMM_ERROR_INVALID_VALUE, "NULL plan, packed operand or C");
+    if (p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "batched plans take their tile with tsmm_plan_set_tile");
+    if (p->device < 0) return fail(TSMM_ERROR_NO_DEVICE, "plan was built for explicit caps, not a device");
+    if (reps < 1 || reps > 1000) return fail(TSMM_ERROR_INVALID_VALUE, "reps must be in 1..1000");
+    if (best_ms) *best_ms = 0.0;
+    if (p->m == 0 || p->n == 0 || p->k == 0) return TSMM_SUCCESS;  // nothing runs
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "evaluator events");
+    }
+    const tsmm_tile orig = p->tile;
+    const int orig_src = p->tile_from_table;
+    double best = -1.0;
+    tsmm_tile best_tile = orig;
+    tsmm_status st = TSMM_SUCCESS;
+    for (const tsmm_tile &cand : tune_candidates(*p)) {
+        if (tsmm_plan_set_tile(p, &cand) != TSMM_SUCCESS) continue;  // not for this shape or device
+        st = tsmm_execute(p, A, packed, C, 1.0, 0.0);  // warm-up
+        if (st != TSMM_SUCCESS) break;
+        std::vector<float> ms;
+        for (int r = 0; r < reps && st == TSMM_SUCCESS; ++r) {
+            e = hipEventRecord(e0, p->stream);
+            if (e == hipSuccess) st = tsmm_execute(p, A, packed, C, 1.0, 0.0);
+            if (e == hipSuccess && st == TSMM_SUCCESS) e = hipEventRecord(e1, p->stream);
+            if (e == hipSuccess && st == TSMM_SUCCESS) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess && st == TSMM_SUCCESS) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess && st == TSMM_SUCCESS) st = hip_fail(e, "evaluator timing");
+            ms.push_back(t);
+        }
+        if (st != TSMM_SUCCESS) break;
+        std::sort(ms.begin(), ms.end());
+        const double med = ms[ms.size() / 2];
+        if (best < 0.0 || med < best) {
+            best = med;
+            best_tile = p->tile;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != TSMM_SUCCESS || best < 0.0) {
+        const std::string err = g_err;
+        (void)tsmm_plan_set_tile(p, &orig);
+        p->tile_from_table = orig_src;
+        g_err = err;
+        return st != TSMM_SUCCESS ? st : fail(TSMM_ERROR_NOT_SUPPORTED, "no candidate tile runs this plan");
+    }
+    st = tsmm_plan_set_tile(p, &best_tile);
+    if (st != TSMM_SUCCESS) return st;
+    p->tile_from_table = 2;
+    {
+        RuntimeCache &rc = runtime_cache();
+        std::lock_guard<std::mutex> lock(rc.mu);
+        rc.entries[plan_key(*p)] = p->tile;
+    }
+    if (best_ms) *best_ms = best;
+    return TSMM_SUCCESS;
+}
+
+void tsmm_tune_cache_clear(void) {
+    RuntimeCache &rc = runtime_cache();
+    std::lock_guard<std::mutex> lock(rc.mu);
+    rc.entries.clear();
 }
 
 // --------------------------------------------------------------- batched

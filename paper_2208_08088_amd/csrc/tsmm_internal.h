@@ -172,7 +172,7 @@ struct tsmm_plan_s {
     tsmm_device_caps caps{};
     int device = 0;
     tsmm_tile tile{};
-    bool tile_from_table = false;
+    int tile_from_table = 0;  // tile source: 0 built-in default or the caller's, 1 tile table, 2 runtime evaluator
     // derived launch geometry
     int KC = 0, NT = 0;
     bool vec = false;

@@ -86,6 +86,8 @@ SIGNATURES = [
                                            ctypes.POINTER(_Caps), _PVP]),
     ("tsmm_plan_set_mode", ctypes.c_int, [_VP, ctypes.c_int]),
     ("tsmm_plan_set_tile", ctypes.c_int, [_VP, ctypes.POINTER(_Tile)]),
+    ("tsmm_plan_tune", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    ("tsmm_tune_cache_clear", None, []),
     ("tsmm_plan_get_tile", ctypes.c_int, [_VP, ctypes.POINTER(_Tile)]),
     ("tsmm_plan_set_stream", ctypes.c_int, [_VP, _VP]),
     ("tsmm_plan_workspace_bytes", ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
@@ -237,6 +239,23 @@ class Plan:
     def get_tile(self) -> dict:
         return _get_tile(self._h)
 
+    def tune(self, A: torch.Tensor, packed: "Packed", C: torch.Tensor, reps: int = 3) -> float:
+        """Runtime evaluator (tsmm_plan_tune): time the candidate tiles on
+        these operands, keep the fastest (also for later plans of the same
+        shape class in this process).  C is overwritten.  Returns the
+        winner's median milliseconds."""
+        in_dt = _TORCH_OF_DT[self.dtype]
+        a_shape = (self.m, self.k) if self.layout == OP_N else (self.k, self.m)
+        _need_cuda(A, "A", in_dt, a_shape)
+        _need_cuda(C, "C", _OUT_OF_DT[self.dtype], (self.m, self.n))
+        lib = _lib()
+        _check(lib.tsmm_plan_set_stream(self._h, _stream()), "tsmm_plan_set_stream")
+        ms = ctypes.c_double(0.0)
+        _check(lib.tsmm_plan_tune(self._h, _ptr(A), packed.handle, _ptr(C), int(reps), ctypes.byref(ms)),
+               "tsmm_plan_tune")
+        self._ws = None
+        return ms.value
+
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t(0)
         _check(_lib().tsmm_plan_workspace_bytes(self._h, ctypes.byref(b)), "tsmm_plan_workspace_bytes")
@@ -262,6 +281,11 @@ class Plan:
         h, self._h = getattr(self, "_h", None), None
         if h and _LIB is not None:
             _LIB.tsmm_plan_destroy(h)
+
+
+def tune_cache_clear():
+    """Forget the tiles the runtime evaluator chose in this process."""
+    _lib().tsmm_tune_cache_clear()
 
 
 def plan(m: int, n: int, k: int, layout: str = "N", dtype=torch.float64) -> Plan:

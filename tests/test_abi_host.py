@@ -297,3 +297,12 @@ def test_slab_tile_rules(T):
     assert T.plan_with_caps(100, 64, (1 << 20) + 32, "N").info()["kernel"] == "simple"
     with pytest.raises(T.TsmmError):
         T.plan_with_caps(1000, 64, 1000, "N", dtype=torch.bfloat16).set_tile(kernel=T.KERNEL_SLAB)
+
+
+def test_tune_validates_before_any_hip_call(T):
+    lib = T._lib()
+    p = T.plan_with_caps(4096, 16, 16, "N")
+    # NULL packed operand / C
+    assert lib.tsmm_plan_tune(p.handle, None, None, None, 3, None) == T.INVALID_VALUE
+    assert lib.tsmm_plan_tune(None, None, None, None, 3, None) == T.INVALID_VALUE
+    lib.tsmm_tune_cache_clear()  # no-op without entries
