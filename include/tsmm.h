@@ -73,8 +73,12 @@ typedef enum tsmm_dtype {
 } tsmm_dtype;
 
 typedef enum tsmm_layout {
-    TSMM_OP_N = 0, /* C = alpha*A*B + beta*C,   A m x k */
-    TSMM_OP_T = 1  /* C = alpha*A^T*B + beta*C, A k x m */
+    TSMM_OP_N = 0,     /* C = alpha*A*B + beta*C,   A m x k, all row-major */
+    TSMM_OP_T = 1,     /* C = alpha*A^T*B + beta*C, A k x m, all row-major */
+    TSMM_COLMAJOR = 2  /* C = alpha*A*B + beta*C with A (m x k), B (k x n)
+                          and C (m x n) column-major (element (i, j) at
+                          i + j * rows), the layout of the paper's analysis
+                          (Sec. IV-A); binary64 / binary32, NATIVE mode */
 } tsmm_layout;
 
 /* Arithmetic used for TSMM_F32 inputs (other types accept NATIVE only).
@@ -112,13 +116,18 @@ typedef enum tsmm_kernel {
                                   aligned                                    */
     TSMM_KERNEL_BATCHED = 7,   /* batched plans only: the persistent launch
                                   over chunks of instance rows               */
-    TSMM_KERNEL_SLAB = 8       /* op N TSMM_F64 / TSMM_F32 (native) with a long
+    TSMM_KERNEL_SLAB = 8,      /* op N TSMM_F64 / TSMM_F32 (native) with a long
                                   k (beyond 256, up to 2^20; also any k class
                                   of 32 and more), n <= 256: a wavefront keeps
                                   its rows' accumulators for all n columns,
                                   packed B streams through LDS in 32-k slabs;
                                   splitk cuts the k range (binary64 partials,
                                   ordered second pass)                       */
+    TSMM_KERNEL_COLMAJOR = 9   /* TSMM_COLMAJOR, TSMM_F64 / TSMM_F32, k and
+                                  n <= 256, m a multiple of the 16-byte vector
+                                  width: packed B as the matrix-core product's
+                                  first operand, A columns streamed as the
+                                  second; A and C 16-byte aligned          */
 } tsmm_kernel;
 
 /* One entry of the tile table: the register/LDS blocking and launch shape
@@ -183,6 +192,8 @@ int32_t tsmm_version(void);
  *           power-of-two scale per column).  TSMM_OP_T: both operands are
  *           tall and nothing is copied: the handle refers to B itself, which
  *           the caller keeps alive and unchanged while the handle is used.
+ *           TSMM_COLMAJOR: B is column-major k x n (binary64 / binary32,
+ *           NATIVE), packed into the same fragment order.
  *   mode    tsmm_mode; only TSMM_F32 accepts a mode other than NATIVE.
  *   stream  hipStream_t or NULL.
  *   out     receives the handle (host object owning device memory that the

@@ -1,0 +1,235 @@
+// Column-major operands (the layout the paper's analysis assumes):
+// C = alpha*A*B + beta*C with A (m x k), B (k x n) and C (m x n) stored
+// column by column, m large, k and n small.  binary64 or binary32.
+//
+// In row-major terms this is C^T = B^T * A^T: a small matrix times a wide
+// one.  On the matrix cores the roles of the operands swap with respect to
+// the row-major streaming kernel: the packed B (the same 16x16x4 fragment
+// image, lane 16*q + j holding B(col(s, q), 16*t + j)) is the product's
+// first operand, whose rows are now columns of C, and A streams in as the
+// second operand: lane (q, j) supplies A(i, col(s, q)) for an m index i of
+// its own.  A column of A is contiguous, so the 16 lanes of one q read 16
+// consecutive m indices; each lane loads VW of them as one 16-byte vector
+// (VW = 2 binary64, 4 binary32) and feeds them to VW products, one per
+// m-tile u, in which lane j stands for m index i0 + VW*j + u.  The
+// accumulators of lane (q, j) then hold, for each C column (row of the
+// product), VW adjacent m indices: every C access is one 16-byte vector.
+//
+// A wavefront owns column blocks of 16*VW m indices over all k and the
+// workgroup's NT column tiles of C; A moves in chunks of CH k-steps, the
+// next chunk in flight while the current one is multiplied.  Column groups
+// (nsplit) divide the C columns among workgroups as in the row-major kernel
+// when the packed slice would not fit the LDS.
+#include "k_common.h"
+#include "k_stream.h"  // BlockMap: workgroup -> (row block, column group)
+#include "tsmm_internal.h"
+
+namespace tsmm {
+
+constexpr int kColBlock = 256;
+
+template <typename T, int KC> struct ColCfg {
+    static constexpr int S = KC / 4;                // k-steps
+    static constexpr int CH = S < 4 ? S : 4;        // k-steps per A chunk
+    static constexpr int NCH = S / CH;              // chunks per column block
+};
+
+// The lane's A vectors of chunk c of column block `blk` (k-slot mapping
+// col(s, q) = 4*s + q, the packed image's scalar mapping).  Columns past k
+// and m indices past m read 0 (m is a multiple of VW, so a vector lies
+// wholly inside or outside).
+template <typename T, int KC>
+__device__ __forceinline__ void col_load(const T *__restrict__ A, int64_t m, int k, int64_t blk, int c, int j, int q,
+                                         typename Mfma4<T>::vec (&x)[ColCfg<T, KC>::CH]) {
+    typedef typename Mfma4<T>::vec vec_t;
+    constexpr int VW = Mfma4<T>::VW;
+    constexpr int CH = ColCfg<T, KC>::CH;
+    const int64_t i = blk * 16 * VW + VW * j;
+#pragma unroll
+    for (int e = 0; e < CH; ++e) {
+        const int col = 4 * (c * CH + e) + q;
+        x[e] = (i < m && col < k) ? __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(A + i + (int64_t)col * m))
+                                  : vec_t{};
+    }
+}
+
+// Products of chunk c: CH k-steps x NT column tiles x VW m-tiles.
+template <typename T, int KC, int NT>
+__device__ __forceinline__ void col_products(const T *__restrict__ sB, int c, int bofs,
+                                             const typename Mfma4<T>::vec (&x)[ColCfg<T, KC>::CH],
+                                             typename Mfma4<T>::acc (&acc)[Mfma4<T>::VW][NT]) {
+    constexpr int VW = Mfma4<T>::VW;
+    constexpr int CH = ColCfg<T, KC>::CH;
+#pragma unroll
+    for (int e = 0; e < CH; ++e) {
+        const int s = c * CH + e;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const T b = sB[bofs + (s * NT + t) * 64];
+#pragma unroll
+            for (int u = 0; u < VW; ++u) acc[u][t] = Mfma4<T>::op(b, x[e][u], acc[u][t]);
+        }
+    }
+}
+
+// Epilogue of column block blk: lane (q, j) holds C columns n0 + 16*t +
+// row(q, r) at m indices i0 + VW*j + u, u < VW (one 16-byte vector).
+template <typename T, int NT>
+__device__ __forceinline__ void col_epilogue(T *__restrict__ C, int64_t m, int n, int64_t blk, int n0, int j, int q,
+                                             double alpha, double beta,
+                                             const typename Mfma4<T>::acc (&acc)[Mfma4<T>::VW][NT]) {
+    typedef Mfma4<T> M;
+    typedef typename M::vec vec_t;
+    constexpr int VW = M::VW;
+    const int64_t i = blk * 16 * VW + VW * j;
+    if (i >= m) return;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int col = n0 + 16 * t + M::row(q, r);
+            if (col >= n) continue;
+            vec_t *p = reinterpret_cast<vec_t *>(C + i + (int64_t)col * m);
+            const vec_t cv = beta != 0.0 ? __builtin_nontemporal_load(p) : vec_t{};
+            vec_t v;
+#pragma unroll
+            for (int u = 0; u < VW; ++u) v[u] = (T)epilogue(alpha, (double)acc[u][t][r], beta, (double)cv[u]);
+            __builtin_nontemporal_store(v, p);
+        }
+}
+
+// One column block: zero the accumulators, run the NCH chunks (chunk c in
+// buffer (PAR + c) % 2; the load of the chunk after it goes to the other
+// buffer), then the epilogue.  nb: the next column block of this wavefront
+// (its first chunk is loaded during the last chunk of this one).
+template <typename T, int KC, int NT, int PAR>
+__device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__restrict__ sB, T *__restrict__ C,
+                                          int64_t m, int n, int k, int64_t blk, int64_t nb, int n0, int lane, int j,
+                                          int q, double alpha, double beta,
+                                          typename Mfma4<T>::vec (&x0)[ColCfg<T, KC>::CH],
+                                          typename Mfma4<T>::vec (&x1)[ColCfg<T, KC>::CH]) {
+    typedef Mfma4<T> M;
+    constexpr int VW = M::VW;
+    constexpr int NCH = ColCfg<T, KC>::NCH;
+    typename M::acc acc[VW][NT];
+#pragma unroll
+    for (int u = 0; u < VW; ++u)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[u][t] = typename M::acc{};
+    // the fragments are re-read from LDS for every block: an opaque lane
+    // offset keeps the compiler from holding them in registers across blocks
+    int bofs = lane;
+    asm volatile("" : "+v"(bofs));
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const bool last = c + 1 == NCH;
+        const int64_t lb = last ? nb : blk;
+        const int lc = last ? 0 : c + 1;
+        if (((PAR + c) & 1) == 0) {
+            col_load<T, KC>(A, m, k, lb, lc, j, q, x1);
+            __builtin_amdgcn_sched_barrier(0);
+            col_products<T, KC, NT>(sB, c, bofs, x0, acc);
+        } else {
+            col_load<T, KC>(A, m, k, lb, lc, j, q, x0);
+            __builtin_amdgcn_sched_barrier(0);
+            col_products<T, KC, NT>(sB, c, bofs, x1, acc);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    col_epilogue<T, NT>(C, m, n, blk, n0, j, q, alpha, beta, acc);
+}
+
+// KC: packed k class; NT: column tiles of C per workgroup (all of n, or one
+// column group); nt_total: column tiles of the packed image.
+template <typename T, int KC, int NT>
+__global__ __launch_bounds__(kColBlock) void k_colmajor(const T *__restrict__ A, const T *__restrict__ Bf,
+                                                         T *__restrict__ C, int64_t m, int n, int k, double alpha,
+                                                         double beta, int nt_total, int nsplit) {
+    typedef Mfma4<T> M;
+    typedef typename M::vec vec_t;
+    constexpr int VW = M::VW;
+    constexpr int S = KC / 4;
+    constexpr int FRAG = S * NT * 64;
+    constexpr int NCH = ColCfg<T, KC>::NCH;
+    const BlockMap bm = block_map(nsplit);
+    const int n0 = bm.group * NT * 16;
+
+    __shared__ T sB[FRAG];
+    for (int idx = threadIdx.x * VW; idx < FRAG; idx += blockDim.x * VW) {
+        const int s = idx / (NT * 64), rem = idx % (NT * 64);
+        *reinterpret_cast<vec_t *>(&sB[idx]) =
+            *reinterpret_cast<const vec_t *>(&Bf[(s * nt_total + bm.group * NT) * 64 + rem]);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+    const int wpb = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nblk = (m + 16 * VW - 1) / (16 * VW);
+    const int64_t stride = bm.nrb * wpb;
+    int64_t blk = bm.rb * wpb + wave;
+    if (blk >= nblk) return;
+    vec_t x0[ColCfg<T, KC>::CH], x1[ColCfg<T, KC>::CH];
+    col_load<T, KC>(A, m, k, blk, 0, j, q, x0);
+    // Blocks go in pairs: a block of NCH chunks that starts in buffer p
+    // leaves the next block's first chunk in buffer (p + NCH) % 2, so after
+    // a pair the first chunk is back in x0.  A pair's second block may lie
+    // past the last one, where nothing is loaded or stored.
+    for (; blk < nblk; blk += 2 * stride) {
+        col_block<T, KC, NT, 0>(A, sB, C, m, n, k, blk, blk + stride, n0, lane, j, q, alpha, beta, x0, x1);
+        col_block<T, KC, NT, NCH & 1>(A, sB, C, m, n, k, blk + stride, blk + 2 * stride, n0, lane, j, q, alpha,
+                                      beta, x0, x1);
+    }
+}
+
+template <typename T, int KC, int NT>
+hipError_t run_colmajor(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k, double alpha,
+                        double beta, int64_t grid, int nt_total, int nsplit, hipStream_t s) {
+    hipLaunchKernelGGL((k_colmajor<T, KC, NT>), dim3((unsigned)grid), dim3(kColBlock), 0, s,
+                       static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C), m, (int)n,
+                       (int)k, alpha, beta, nt_total, nsplit);
+    return hipGetLastError();
+}
+
+typedef hipError_t (*ColFn)(const void *, const void *, void *, int64_t, int64_t, int64_t, double, double, int64_t,
+                            int, int, hipStream_t);
+struct ColEntry {
+    tsmm_dtype dt;
+    int KC, NT;
+    ColFn fn;
+};
+
+// packed slice (KC/4 * NT * 64 values) within 128 KiB of LDS; accumulators
+// VW * NT tiles within 128 registers; at k classes of 128 and more at most
+// 4 column tiles (8 spilled to scratch when compiled)
+#define TSMM_COL_NT4(T, DT, KC) {DT, KC, 1, &run_colmajor<T, KC, 1>}, {DT, KC, 2, &run_colmajor<T, KC, 2>}, \
+    {DT, KC, 4, &run_colmajor<T, KC, 4>},
+#define TSMM_COL_NT8(T, DT, KC) TSMM_COL_NT4(T, DT, KC) {DT, KC, 8, &run_colmajor<T, KC, 8>},
+static const ColEntry kColTable[] = {
+    TSMM_COL_NT8(double, TSMM_F64, 4) TSMM_COL_NT8(double, TSMM_F64, 8) TSMM_COL_NT8(double, TSMM_F64, 16)
+    TSMM_COL_NT8(double, TSMM_F64, 32) TSMM_COL_NT8(double, TSMM_F64, 64) TSMM_COL_NT4(double, TSMM_F64, 128)
+    TSMM_COL_NT4(double, TSMM_F64, 256)
+    TSMM_COL_NT8(float, TSMM_F32, 4) TSMM_COL_NT8(float, TSMM_F32, 8) TSMM_COL_NT8(float, TSMM_F32, 16)
+    TSMM_COL_NT8(float, TSMM_F32, 32) TSMM_COL_NT8(float, TSMM_F32, 64) TSMM_COL_NT4(float, TSMM_F32, 128)
+    TSMM_COL_NT4(float, TSMM_F32, 256)
+};
+#undef TSMM_COL_NT4
+#undef TSMM_COL_NT8
+
+static const ColEntry *find_col(tsmm_dtype dt, int KC, int NT) {
+    for (const ColEntry &e : kColTable)
+        if (e.dt == dt && e.KC == KC && e.NT == NT) return &e;
+    return nullptr;
+}
+
+bool colmajor_variant_exists(tsmm_dtype dt, int KC, int NT) { return find_col(dt, KC, NT) != nullptr; }
+
+hipError_t launch_colmajor(tsmm_dtype dt, int KC, int NT, const void *A, const void *Bf, void *C, int64_t m,
+                           int64_t n, int64_t k, double alpha, double beta, int64_t grid, int nt_total, int nsplit,
+                           hipStream_t s) {
+    const ColEntry *e = find_col(dt, KC, NT);
+    if (!e || NT * nsplit != nt_total || m % (dt == TSMM_F64 ? 2 : 4) != 0) return hipErrorInvalidValue;
+    return e->fn(A, Bf, C, m, n, k, alpha, beta, grid, nt_total, nsplit, s);
+}
+
+}  // namespace tsmm

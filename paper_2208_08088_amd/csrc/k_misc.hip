@@ -19,7 +19,7 @@ static inline unsigned blocks_for(int64_t count, int block) {
 
 template <typename T>
 __global__ void k_pack_frag4(const T *__restrict__ B, T *__restrict__ frag, int64_t k, int64_t n,
-                             int KC, int NT, int vec, int pg, int64_t total) {
+                             int KC, int NT, int vec, int pg, int bcol, int64_t total) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int lane = (int)(idx & 63);
@@ -29,20 +29,20 @@ __global__ void k_pack_frag4(const T *__restrict__ B, T *__restrict__ frag, int6
     constexpr int VW = 16 / (int)sizeof(T);
     const int64_t col = vec ? (int64_t)(s / VW) * 4 * VW + q * VW + (s % VW) : 4 * (int64_t)s + q;
     const int64_t nc = 16 * pg * (int64_t)(t / pg) + pg * j + t % pg;  // colp(t, j)
-    frag[idx] = (col < k && nc < n) ? B[col * n + nc] : T(0);
+    frag[idx] = (col < k && nc < n) ? B[bcol ? col + nc * k : col * n + nc] : T(0);
 }
 
-hipError_t launch_pack_frag4(tsmm_dtype dt, const void *B, void *frag, int64_t k, int64_t n,
+hipError_t launch_pack_frag4(tsmm_dtype dt, bool bcol, const void *B, void *frag, int64_t k, int64_t n,
                              int KC, int NT, bool vec, int pg, hipStream_t s) {
     const int64_t total = (int64_t)(KC / 4) * NT * 64;
     if (dt == TSMM_F64)
         hipLaunchKernelGGL(k_pack_frag4<double>, dim3(blocks_for(total, 256)), dim3(256), 0, s,
                            static_cast<const double *>(B), static_cast<double *>(frag), k, n, KC, NT,
-                           (int)vec, pg, total);
+                           (int)vec, pg, (int)bcol, total);
     else if (dt == TSMM_F32)
         hipLaunchKernelGGL(k_pack_frag4<float>, dim3(blocks_for(total, 256)), dim3(256), 0, s,
                            static_cast<const float *>(B), static_cast<float *>(frag), k, n, KC, NT,
-                           (int)vec, pg, total);
+                           (int)vec, pg, (int)bcol, total);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

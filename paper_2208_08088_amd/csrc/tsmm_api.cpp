@@ -56,7 +56,7 @@ int log_level() {
 }
 
 bool valid_dtype(int d) { return d == TSMM_F64 || d == TSMM_F32 || d == TSMM_BF16; }
-bool valid_layout(int l) { return l == TSMM_OP_N || l == TSMM_OP_T; }
+bool valid_layout(int l) { return l == TSMM_OP_N || l == TSMM_OP_T || l == TSMM_COLMAJOR; }
 bool valid_mode(int m) { return m == TSMM_MODE_NATIVE || m == TSMM_MODE_BF16X3 || m == TSMM_MODE_BF16X6; }
 
 const char *dtype_name(tsmm_dtype d) { return d == TSMM_F64 ? "f64" : d == TSMM_F32 ? "f32" : "bf16"; }
@@ -73,6 +73,7 @@ const char *kernel_name(int k) {
     case TSMM_KERNEL_WIDE: return "wide";
     case TSMM_KERNEL_BATCHED: return "batched";
     case TSMM_KERNEL_SLAB: return "slab";
+    case TSMM_KERNEL_COLMAJOR: return "colmajor";
     default: return "auto";
     }
 }
@@ -131,7 +132,7 @@ tsmm_status query_caps(tsmm_device_caps *caps, int *device) {
 
 // Tile-table layout "B": the entry of batched plans of one dtype (key
 // fields kc, nt, mclass are 0).
-constexpr int kLayoutBatched = 2;
+constexpr int kLayoutBatched = 16;
 
 struct TableKey {
     int layout, dtype, mode, kc, nt, mclass;
@@ -167,6 +168,7 @@ int parse_kernel(const std::string &s) {
     if (s == "wide") return TSMM_KERNEL_WIDE;
     if (s == "batched") return TSMM_KERNEL_BATCHED;
     if (s == "slab") return TSMM_KERNEL_SLAB;
+    if (s == "colmajor") return TSMM_KERNEL_COLMAJOR;
     return -1;
 }
 
@@ -253,7 +255,15 @@ bool slab_ok(const tsmm_plan_s &p) {
 }
 
 // Which kernel family serves (layout, dtype, mode, shape)?
+// Column-major shapes the column-major kernel serves.
+bool colmajor_ok(const tsmm_plan_s &p) {
+    const int vw = p.dtype == TSMM_F64 ? 2 : 4;
+    return p.layout == TSMM_COLMAJOR && p.mode == TSMM_MODE_NATIVE && (p.dtype == TSMM_F64 || p.dtype == TSMM_F32) &&
+           kclass4(p.k) && ntclass(p.n) && p.m % vw == 0;
+}
+
 int natural_kernel(const tsmm_plan_s &p) {
+    if (p.layout == TSMM_COLMAJOR) return colmajor_ok(p) ? TSMM_KERNEL_COLMAJOR : TSMM_KERNEL_SIMPLE;
     if (p.layout == TSMM_OP_T) return p.dtype == TSMM_F64 ? TSMM_KERNEL_SPLITK : TSMM_KERNEL_SIMPLE;
     if (p.dtype == TSMM_BF16 || p.mode != TSMM_MODE_NATIVE)
         return (kclass32(p.k) && ntclass(p.n)) ? TSMM_KERNEL_SPLITBF16 : TSMM_KERNEL_SIMPLE;
@@ -277,6 +287,7 @@ bool eligible(const tsmm_plan_s &p, int kernel) {
     case TSMM_KERNEL_VALU64: return valu64_ok(p);
     case TSMM_KERNEL_WIDE: return wide_ok(p);
     case TSMM_KERNEL_SLAB: return slab_ok(p);
+    case TSMM_KERNEL_COLMAJOR: return colmajor_ok(p);
     default: return kernel == natural_kernel(p);
     }
 }
@@ -355,6 +366,20 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
         t.rows_per_wave = (p.n == 128 && p.mode == TSMM_MODE_NATIVE) ? 4 : 2;
         t.wg_per_cu = 1;
         break;
+    case TSMM_KERNEL_COLMAJOR: {
+        // column groups: at most 8 column tiles of C per wavefront (4 at k
+        // classes of 128 and more; the accumulators of two or four m-tiles)
+        // and a packed slice within the LDS budget
+        const int KC = kclass4(p.k), NT = ntclass(p.n);
+        t.nsplit = 1;
+        while ((NT / t.nsplit > (KC >= 128 ? 4 : 8) ||
+                (size_t)(KC / 4) * (NT / t.nsplit) * 64 * elem_bytes(p.dtype) > kLdsBudget) &&
+               t.nsplit < NT)
+            t.nsplit *= 2;
+        t.rows_per_wave = 1;
+        t.wg_per_cu = 8;
+        break;
+    }
     case TSMM_KERNEL_SLAB: {
         // row tiles per wavefront: accumulators (RT * NT tiles of 8 or 4
         // registers) and two A register sets (2 * RT * 8 values) within
@@ -411,7 +436,8 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         t.nsplit > 16 || !is_pow2(t.nsplit))
         return fail(TSMM_ERROR_INVALID_VALUE, "tile out of range (waves_per_wg 1/2/4, wg_per_cu 1..32, "
                                               "splitk 1..65536, nsplit 1/2/4/8/16)");
-    if (t.nsplit > 1 && t.kernel != TSMM_KERNEL_STREAM && t.kernel != TSMM_KERNEL_SPLITBF16)
+    if (t.nsplit > 1 && t.kernel != TSMM_KERNEL_STREAM && t.kernel != TSMM_KERNEL_SPLITBF16 &&
+        t.kernel != TSMM_KERNEL_COLMAJOR)
         return fail(TSMM_ERROR_INVALID_VALUE, "nsplit applies to the op N fragment kernels only");
     const int64_t cus = std::max(1, p.caps.compute_units);
     p.block = 64 * t.waves_per_wg;
@@ -482,6 +508,26 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
                         "the wide kernel runs one workgroup of 4 wavefronts per compute unit, no column split");
         const int64_t tiles = (p.m + wide_rows_per_wg(t.rows_per_wave) - 1) / wide_rows_per_wg(t.rows_per_wave);
         p.grid = std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
+        break;
+    }
+    case TSMM_KERNEL_COLMAJOR: {
+        p.KC = kclass4(p.k);
+        p.NT = ntclass(p.n);
+        p.vec = false;
+        if (t.nsplit > p.NT) return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d > %d column tiles", t.nsplit, p.NT);
+        const int NTs = p.NT / t.nsplit;
+        if (t.rows_per_wave != 1 || !colmajor_variant_exists(p.dtype, p.KC, NTs))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no column-major kernel for KC=%d NT=%d (rows_per_wave 1)", p.KC,
+                        NTs);
+        if (t.waves_per_wg != 4)
+            return fail(TSMM_ERROR_INVALID_VALUE, "the column-major kernel runs 4 wavefronts per workgroup");
+        // column blocks of 16 * VW m indices, one per wavefront step
+        const int vw = p.dtype == TSMM_F64 ? 2 : 4;
+        const int64_t blocks = (p.m + 16 * vw - 1) / (16 * vw);
+        const int64_t wgs = (blocks + t.waves_per_wg - 1) / t.waves_per_wg;
+        int64_t rows = std::max<int64_t>(1, std::min<int64_t>(wgs, cus * t.wg_per_cu / t.nsplit));
+        if (t.nsplit > 1) rows = (rows + 7) / 8 * 8;
+        p.grid = rows * t.nsplit;
         break;
     }
     case TSMM_KERNEL_SLAB: {
@@ -695,8 +741,10 @@ tsmm_status check_plan_args(int64_t m, int64_t n, int64_t k, int layout, int dty
     if (!valid_dtype(dtype)) return fail(TSMM_ERROR_INVALID_VALUE, "bad dtype %d", dtype);
     if (m > (INT64_C(1) << 40) || n > (INT64_C(1) << 30) || k > (INT64_C(1) << 40))
         return fail(TSMM_ERROR_NOT_SUPPORTED, "size beyond the library's index range");
-    if (layout == TSMM_OP_N && (n > INT32_MAX || k > INT32_MAX))
-        return fail(TSMM_ERROR_NOT_SUPPORTED, "op N needs n, k < 2^31");
+    if (layout != TSMM_OP_T && (n > INT32_MAX || k > INT32_MAX))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "op N and column-major need n, k < 2^31");
+    if (layout == TSMM_COLMAJOR && dtype == TSMM_BF16)
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "column-major operands take binary64 or binary32");
     if (layout == TSMM_OP_T && (m > INT32_MAX || n > INT32_MAX))
         return fail(TSMM_ERROR_NOT_SUPPORTED, "op T needs m, n < 2^31");
     return TSMM_SUCCESS;
@@ -739,6 +787,8 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
     if (!valid_mode(mode)) return fail(TSMM_ERROR_INVALID_VALUE, "bad mode %d", (int)mode);
     if (mode != TSMM_MODE_NATIVE && (dtype != TSMM_F32 || layout != TSMM_OP_N))
         return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes take op N binary32 operands");
+    if (layout == TSMM_COLMAJOR && dtype == TSMM_BF16)
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "column-major operands take binary64 or binary32");
     if (k * n > 0 && !B) return fail(TSMM_ERROR_INVALID_VALUE, "B is NULL");
     if (k > INT32_MAX || n > INT32_MAX) return fail(TSMM_ERROR_NOT_SUPPORTED, "k, n must be < 2^31");
     const int terms = split_terms(dtype, mode);
@@ -778,6 +828,15 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
             L.off_exps = off;
             off = align(off + (size_t)n * 4);
         }
+    } else if (layout == TSMM_COLMAJOR) {
+        // the column-major kernel: scalar k-slot mapping (A's columns are
+        // separate streams), plain column order
+        L.KC = kclass4(k);
+        L.NT = ntclass(n);
+        if (L.KC && L.NT) {
+            L.off_frag = off;
+            off = align(off + (size_t)L.KC * L.NT * 16 * eb);
+        }
     } else {
         L.KC = (int)frag4_depth(k);
         L.NT = ntclass(n);
@@ -812,7 +871,8 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
                                  mode != TSMM_MODE_NATIVE ? reinterpret_cast<int32_t *>(base + L.off_exps) : nullptr,
                                  k, n, L.KC, L.NT, terms, L.pg, s);
         else
-            e = launch_pack_frag4(dtype, B, base + L.off_frag, k, n, L.KC, L.NT, L.vec, L.pg, s);
+            e = launch_pack_frag4(dtype, layout == TSMM_COLMAJOR, B, base + L.off_frag, k, n, L.KC, L.NT, L.vec,
+                                  L.pg, s);
     }
     if (e == hipSuccess && L.wide_KC)  // after the split planes it reads
         e = launch_pack_wide(B, terms > 0 ? base + L.off_planes : nullptr, base + L.off_wide, k, n, L.wide_KC,
@@ -929,7 +989,7 @@ tsmm_status tsmm_plan_set_tile(tsmm_plan_t p, const tsmm_tile *tile) {
     g_err.clear();
     if (!p || !tile) return fail(TSMM_ERROR_INVALID_VALUE, "NULL argument");
     if (p->batched) return set_batched_tile(*p, *tile);
-    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_SLAB || tile->kernel == TSMM_KERNEL_BATCHED)
+    if (tile->kernel < 0 || tile->kernel > TSMM_KERNEL_COLMAJOR || tile->kernel == TSMM_KERNEL_BATCHED)
         return fail(TSMM_ERROR_INVALID_VALUE, "bad kernel id %d", tile->kernel);
     if (tile->chunk_rows != 0) return fail(TSMM_ERROR_INVALID_VALUE, "chunk_rows is for batched plans");
     tsmm_plan_s trial = *p;
@@ -996,7 +1056,7 @@ tsmm_status tsmm_plan_describe(tsmm_plan_t p, char *buf, size_t len) {
              "op=%c dtype=%s mode=%s m=%" PRId64 " n=%" PRId64 " k=%" PRId64
              " kernel=%s kc=%d nt=%d vec=%d rt=%d waves=%d wg_per_cu=%d splitk=%d nsplit=%d grid=%" PRId64 "x%" PRId64
              " block=%d workspace=%zu table=%d",
-             p->layout == TSMM_OP_N ? 'N' : 'T', dtype_name(p->dtype), mode_name(p->mode), p->m, p->n, p->k,
+             p->layout == TSMM_OP_N ? 'N' : (p->layout == TSMM_OP_T ? 'T' : 'C'), dtype_name(p->dtype), mode_name(p->mode), p->m, p->n, p->k,
              kernel_name(p->tile.kernel), p->KC, p->NT, (int)p->vec, p->tile.rows_per_wave, p->tile.waves_per_wg,
              p->tile.wg_per_cu, p->tile.splitk, p->tile.nsplit, p->grid, p->grid_y, p->block, p->workspace_bytes,
              (int)p->tile_from_table);
@@ -1061,7 +1121,8 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
         return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "scale launch");
     }
     const char *base = static_cast<const char *>(packed->dev);
-    const void *Brow = p->layout == TSMM_OP_N ? base + packed->L.off_rowmajor : nullptr;
+    // the caller's copy of B: row-major (op N), column-major (TSMM_COLMAJOR)
+    const void *Brow = p->layout != TSMM_OP_T ? base + packed->L.off_rowmajor : nullptr;
     int kernel = p->tile.kernel;
     if (kernel == TSMM_KERNEL_STREAM && ((p->vec && (reinterpret_cast<uintptr_t>(A) & 15)) ||
                                          (frag4_pg(p->dtype, p->NT, p->n) > 1 && (reinterpret_cast<uintptr_t>(C) & 15))))
@@ -1110,6 +1171,14 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
                                                     : nullptr,
                         C, p->m, p->n, p->k, alpha, beta, p->grid, s);
         break;
+    case TSMM_KERNEL_COLMAJOR:
+        if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(C)) & 15) {
+            e = launch_simple_n(p->dtype, Brow, A, C, p->n, p->m, p->k, alpha, beta, s);  // C^T = B^T A^T
+            break;
+        }
+        e = launch_colmajor(p->dtype, p->KC, p->NT / p->tile.nsplit, A, base + packed->L.off_frag, C, p->m, p->n,
+                            p->k, alpha, beta, p->grid, p->NT, p->tile.nsplit, s);
+        break;
     case TSMM_KERNEL_SLAB: {
         const bool il = frag4_pg(p->dtype, p->NT, p->n) > 1;
         if ((p->vec && (reinterpret_cast<uintptr_t>(A) & 15)) || (il && (reinterpret_cast<uintptr_t>(C) & 15))) {
@@ -1136,6 +1205,8 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
     default:
         if (p->layout == TSMM_OP_T)
             e = launch_simple_t(p->dtype, A, packed->ref, C, p->m, p->n, p->k, alpha, beta, s);
+        else if (p->layout == TSMM_COLMAJOR)  // column-major C = A B is row-major C^T = B^T A^T
+            e = launch_simple_n(p->dtype, Brow, A, C, p->n, p->m, p->k, alpha, beta, s);
         else
             e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
         break;
@@ -1177,6 +1248,10 @@ std::vector<tsmm_tile> tune_candidates(const tsmm_plan_s &p) {
     case TSMM_KERNEL_SLAB:
         for (int rt : {1, 2, 4})
             for (int sk : {1, 2, 3, 4, 5, 6, 8, 12, 16}) add(nat, rt, 1, sk, 1);
+        break;
+    case TSMM_KERNEL_COLMAJOR:
+        for (int ns : {d.nsplit, 2 * d.nsplit})
+            for (int wpc : {1, 2, 4, 8, 16}) add(nat, 1, wpc, 1, ns);
         break;
     default:
         break;

@@ -211,7 +211,8 @@ namespace tsmm {
 // Each returns hipSuccess or the launch error.  All are asynchronous.
 
 // Pack B (k x n row-major) into the 16x16x4 fragment order.
-hipError_t launch_pack_frag4(tsmm_dtype dt, const void *B, void *frag, int64_t k, int64_t n,
+// bcol: B is column-major (element (l, j) at l + j*k) instead of row-major.
+hipError_t launch_pack_frag4(tsmm_dtype dt, bool bcol, const void *B, void *frag, int64_t k, int64_t n,
                              int KC, int NT, bool vec, int pg, hipStream_t s);
 // Split-bf16 pack: column exponents, row-major planes and fragments.
 // For TSMM_BF16 inputs (terms == 1) B is bf16 and no scaling is applied.
@@ -283,6 +284,14 @@ hipError_t launch_slab(tsmm_dtype dt, int NT, int RT, bool vec, bool il, const v
                        int64_t grid, hipStream_t s);
 bool slab_variant_exists(tsmm_dtype dt, int NT, int RT, bool vec, bool il);
 int slab_rows(int RT);  // rows of one work item (four wavefronts of RT 16-row tiles)
+
+// Column-major operands: packed B (scalar k-slot mapping, plain column
+// order, nt_total column tiles) times column-major A into column-major C;
+// m a multiple of the vector width, A and C 16-byte aligned.
+hipError_t launch_colmajor(tsmm_dtype dt, int KC, int NT, const void *A, const void *Bf, void *C, int64_t m,
+                           int64_t n, int64_t k, double alpha, double beta, int64_t grid, int nt_total, int nsplit,
+                           hipStream_t s);
+bool colmajor_variant_exists(tsmm_dtype dt, int KC, int NT);
 
 // Batched persistent launch: workgroup w runs work tiles
 // [wg_begin[w], wg_begin[w+1]) of the instance sequence described by

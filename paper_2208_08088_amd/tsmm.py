@@ -22,13 +22,13 @@ LIB_PATH = os.path.join(HERE, "libtsmm.so")
 
 SUCCESS, INVALID_VALUE, SHAPE_MISMATCH, NOT_SUPPORTED, TABLE, OUT_OF_MEMORY, NO_DEVICE, HIP = range(8)
 F64, F32, BF16 = 0, 1, 2
-OP_N, OP_T = 0, 1
+OP_N, OP_T, COLMAJOR = 0, 1, 2
 MODE_NATIVE, MODE_BF16X3, MODE_BF16X6 = 0, 1, 2
 (KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_STREAM, KERNEL_SPLITK, KERNEL_SPLITBF16, KERNEL_VALU64, KERNEL_WIDE,
- KERNEL_BATCHED, KERNEL_SLAB) = range(9)
+ KERNEL_BATCHED, KERNEL_SLAB, KERNEL_COLMAJOR) = range(10)
 
 _MODES = {"native": MODE_NATIVE, "bf16x3": MODE_BF16X3, "bf16x6": MODE_BF16X6}
-_LAYOUTS = {"N": OP_N, "T": OP_T}
+_LAYOUTS = {"N": OP_N, "T": OP_T, "C": COLMAJOR}
 _DT_OF_TORCH = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
 _TORCH_OF_DT = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
 _OUT_OF_DT = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
@@ -134,12 +134,16 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def _need_cuda(t, name, dtype=None, shape=None):
+def _need_cuda(t, name, dtype=None, shape=None, colmajor=False):
     if not isinstance(t, torch.Tensor):
         raise TypeError("%s must be a torch.Tensor" % name)
     if t.device.type != "cuda":
         raise ValueError("%s must be a device tensor" % name)
-    if not t.is_contiguous():
+    if colmajor:
+        # a column-major matrix is the transpose of a contiguous tensor
+        if t.dim() != 2 or not t.t().is_contiguous():
+            raise ValueError("%s must be column-major (the transpose of a contiguous tensor)" % name)
+    elif not t.is_contiguous():
         raise ValueError("%s must be contiguous (row-major)" % name)
     if dtype is not None and t.dtype != dtype:
         raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
@@ -177,10 +181,11 @@ class Packed:
 
 
 def pack(B: torch.Tensor, layout: str = "N", mode: str = "native") -> Packed:
-    """Pack B (k x n, row-major, on the device) once for reuse."""
+    """Pack B (k x n on the device; row-major, or column-major for layout
+    "C") once for reuse."""
     if B.dtype not in _DT_OF_TORCH:
         raise TypeError("B must be float64, float32 or bfloat16")
-    _need_cuda(B, "B")
+    _need_cuda(B, "B", colmajor=layout == "C")
     if B.dim() != 2:
         raise ValueError("B must be 2-D")
     k, n = B.shape
@@ -193,7 +198,10 @@ def pack(B: torch.Tensor, layout: str = "N", mode: str = "native") -> Packed:
 
 def unpack(p: Packed) -> torch.Tensor:
     out_dt = torch.float32 if p.mode != MODE_NATIVE else _TORCH_OF_DT[p.dtype]
-    out = torch.empty((p.k, p.n), dtype=out_dt, device="cuda")
+    if p.layout == COLMAJOR:  # the stored copy is column-major
+        out = torch.empty((p.n, p.k), dtype=out_dt, device="cuda").t()
+    else:
+        out = torch.empty((p.k, p.n), dtype=out_dt, device="cuda")
     _check(_lib().tsmm_unpack(p.handle, _ptr(out), _stream()), "tsmm_unpack")
     return out
 
@@ -245,9 +253,10 @@ class Plan:
         shape class in this process).  C is overwritten.  Returns the
         winner's median milliseconds."""
         in_dt = _TORCH_OF_DT[self.dtype]
-        a_shape = (self.m, self.k) if self.layout == OP_N else (self.k, self.m)
-        _need_cuda(A, "A", in_dt, a_shape)
-        _need_cuda(C, "C", _OUT_OF_DT[self.dtype], (self.m, self.n))
+        a_shape = (self.k, self.m) if self.layout == OP_T else (self.m, self.k)
+        cm = self.layout == COLMAJOR
+        _need_cuda(A, "A", in_dt, a_shape, colmajor=cm)
+        _need_cuda(C, "C", _OUT_OF_DT[self.dtype], (self.m, self.n), colmajor=cm)
         lib = _lib()
         _check(lib.tsmm_plan_set_stream(self._h, _stream()), "tsmm_plan_set_stream")
         ms = ctypes.c_double(0.0)
@@ -311,9 +320,10 @@ def execute(p: Plan, A: torch.Tensor, packed: Packed, C: torch.Tensor, alpha: fl
             beta: float = 0.0) -> torch.Tensor:
     """C = alpha*op(A)*B + beta*C in place on torch's current stream."""
     in_dt = _TORCH_OF_DT[p.dtype]
-    a_shape = (p.m, p.k) if p.layout == OP_N else (p.k, p.m)
-    _need_cuda(A, "A", in_dt, a_shape)
-    _need_cuda(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n))
+    a_shape = (p.k, p.m) if p.layout == OP_T else (p.m, p.k)
+    cm = p.layout == COLMAJOR
+    _need_cuda(A, "A", in_dt, a_shape, colmajor=cm)
+    _need_cuda(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n), colmajor=cm)
     if packed.layout == OP_T and packed._keep is not None:
         _need_cuda(packed._keep, "B")
     p._ensure_workspace()

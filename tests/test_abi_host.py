@@ -306,3 +306,29 @@ def test_tune_validates_before_any_hip_call(T):
     assert lib.tsmm_plan_tune(p.handle, None, None, None, 3, None) == T.INVALID_VALUE
     assert lib.tsmm_plan_tune(None, None, None, None, 3, None) == T.INVALID_VALUE
     lib.tsmm_tune_cache_clear()  # no-op without entries
+
+
+def test_colmajor_plan_rules(T):
+    torch = __import__("torch")
+    # binary64, m a multiple of 2: the column-major kernel; 32 m indices per
+    # wavefront block, 4 wavefronts per workgroup
+    p = T.plan_with_caps(1 << 20, 64, 64, "C")
+    info = p.info()
+    assert info["kernel"] == "colmajor" and info["op"] == "C"
+    assert p.get_tile()["nsplit"] == 1
+    # n = 256 at k class 256: at most 4 column tiles per group -> 4 groups
+    q = T.plan_with_caps(1 << 20, 256, 256, "C")
+    assert q.info()["kernel"] == "colmajor" and q.get_tile()["nsplit"] == 4
+    # odd m (binary64) or m not a multiple of 4 (binary32): any-shape kernel
+    assert T.plan_with_caps(1001, 16, 16, "C").info()["kernel"] == "simple"
+    assert T.plan_with_caps(1002, 16, 16, "C", dtype=torch.float32).info()["kernel"] == "simple"
+    assert T.plan_with_caps(1004, 16, 16, "C", dtype=torch.float32).info()["kernel"] == "colmajor"
+    # k beyond 256: any-shape kernel
+    assert T.plan_with_caps(1000, 16, 300, "C").info()["kernel"] == "simple"
+    with pytest.raises(T.TsmmError):
+        T.plan_with_caps(1 << 20, 64, 64, "C").set_tile(kernel=T.KERNEL_COLMAJOR, waves_per_wg=2)
+    with pytest.raises(T.TsmmError):
+        T.plan_with_caps(1 << 20, 64, 64, "C").set_tile(kernel=T.KERNEL_STREAM)
+    with pytest.raises(T.TsmmError) as e:
+        T.plan_with_caps(1000, 16, 16, "C", dtype=torch.bfloat16)
+    assert e.value.status == T.NOT_SUPPORTED
