@@ -17,8 +17,9 @@ case, the op T split-k shape (C(64x64) = A^T B, A and B 2^22 x 64), the
 binary32 precision comparison (m = 2^24, k = n = 256: binary32 products,
 split-bf16 x3 / x6, binary64 on binary64 copies), the batched persistent
 launch (512 uneven instances, replayed from a HIP graph), the paper's own
-shape (square A 25600 x 25600 times B 25600 x N, N in {16, 64, 240}) and
-the runtime evaluator on a shape class the tile table does not hold.
+shape (square A 25600 x 25600 times B 25600 x N, N in {16, 64, 240}), the
+runtime evaluator on a shape class the tile table does not hold, and the
+headline sizes with column-major operands.
 
 The `roofline` object is for the kernel that takes the most time in a step,
 timed with HIP events on the stream it runs on; `cpu_baseline` times the
@@ -321,6 +322,35 @@ def extras_square(torch, T, I, steps, warmup):
     return out, keep
 
 
+def extras_colmajor(torch, T, I, steps, warmup):
+    """The headline sizes with column-major operands (the layout of the
+    paper's analysis): binary64, m = 2^23, k = n in {8, 32, 128}, beta in
+    {0, 1}; the bytes and the GB/s are counted as for the headline."""
+    out = {}
+    for k in KS:
+        n = k
+        A = I.device_uniform((k, M_ROWS), I.BASE_SEED, 400 + k, torch.float64).t()
+        B = I.device_uniform((n, k), I.BASE_SEED, 410 + k, torch.float64).t()
+        C = I.device_uniform((n, M_ROWS), I.BASE_SEED, 420 + k, torch.float64).t()
+        pk = T.pack(B, "C")
+        p = T.plan(M_ROWS, n, k, "C", torch.float64)
+        for beta in BETAS:
+            for _ in range(warmup):
+                T.execute(p, A, pk, C, 1.0, beta)
+            timer = Timer(torch)
+            for _ in range(steps):
+                e0 = timer.start()
+                T.execute(p, A, pk, C, 1.0, beta)
+                timer.stop("c", e0)
+            ms = float(np.median(timer.per_key_ms()["c"]))
+            byt = opn_bytes(M_ROWS, n, k, beta)
+            out["k%db%d" % (k, int(beta))] = dict(plan=p.describe(), us=ms * 1e3, GB_s=byt / ms / 1e6,
+                                                   hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS)
+        del A, B, C, pk
+        torch.cuda.empty_cache()
+    return out
+
+
 def extras_tune(torch, T, I, steps, warmup):
     """The runtime evaluator on a shape class the tile table does not hold
     (binary64, m = 2^22, k = 24, n = 48): the built-in default tile against
@@ -574,9 +604,12 @@ def main():
         print("[bench] square done", file=sys.stderr, flush=True)
         tune = extras_tune(torch, T, I, args.steps, args.warmup)
         print("[bench] runtime evaluator done", file=sys.stderr, flush=True)
+        colm = extras_colmajor(torch, T, I, args.steps, args.warmup)
+        print("[bench] column-major done", file=sys.stderr, flush=True)
         del keep_t
         result["extras"] = dict(small_4096x16=small, op_t_splitk=opt, precision_m2p24_k256=prec,
-                                batched_512=bat, square_25600=sq, runtime_evaluator=tune)
+                                batched_512=bat, square_25600=sq, runtime_evaluator=tune,
+                                colmajor_m2p23=colm)
 
     if not args.no_cpu_baseline and not args.only:
         result["cpu_baseline"] = cpu_baseline(torch, I, cases, keep_s)

@@ -50,12 +50,21 @@ CLASSES = {
     "n_f64_k64": ("N", torch.float64, "native", 1 << 23, 64, 64),
     "n_f64_k128": ("N", torch.float64, "native", 1 << 23, 128, 128),
     "n_f64_k256": ("N", torch.float64, "native", 1 << 24, 256, 256),
+    "n_f32_k8": ("N", torch.float32, "native", 1 << 23, 8, 8),
+    "n_f32_k16": ("N", torch.float32, "native", 1 << 23, 16, 16),
+    "n_f32_k32": ("N", torch.float32, "native", 1 << 23, 32, 32),
+    "n_f32_k64": ("N", torch.float32, "native", 1 << 23, 64, 64),
+    "n_f32_k128": ("N", torch.float32, "native", 1 << 23, 128, 128),
     "n_f32_k256": ("N", torch.float32, "native", 1 << 24, 256, 256),
     "n_f32x6_k256": ("N", torch.float32, "bf16x6", 1 << 24, 256, 256),
     "n_f32x3_k256": ("N", torch.float32, "bf16x3", 1 << 24, 256, 256),
     "t_f64_64x64": ("T", torch.float64, "native", 64, 64, 1 << 22),
     # the paper's own shape: square A (25600 x 25600) x B (25600 x 240)
     "n_f64_sq25600": ("N", torch.float64, "native", 25600, 240, 25600),
+    # column-major operands (m = 2^23)
+    "c_f64_k8": ("C", torch.float64, "native", 1 << 23, 8, 8),
+    "c_f64_k32": ("C", torch.float64, "native", 1 << 23, 32, 32),
+    "c_f64_k128": ("C", torch.float64, "native", 1 << 23, 128, 128),
     "n_f32_sq25600": ("N", torch.float32, "native", 25600, 240, 25600),
     # batched: the 512-instance workload (m uniform in [1024, 262144], k and
     # n from {4, ..., 128}); the tile is the chunk of rows a workgroup takes
@@ -88,6 +97,8 @@ def table_key(layout, dt, mode, m, n, k):
 
 
 def natural_kernel(p):
+    if p.layout == T.COLMAJOR:
+        return T.KERNEL_COLMAJOR
     if p.layout == T.OP_T:
         return T.KERNEL_SPLITK
     if p.dtype == T.BF16 or p.mode != T.MODE_NATIVE:
@@ -134,6 +145,10 @@ def candidates(p):
         for rt in (1, 2, 4):
             for sk in sorted({nat["splitk"], 1, 2, 3, 4, 5, 6, 8, 12, 16}):
                 out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=1, splitk=sk, nsplit=1))
+    elif kern == T.KERNEL_COLMAJOR:
+        for ns in sorted({nat["nsplit"], nat["nsplit"] * 2}):
+            for wpc in (1, 2, 4, 8, 16):
+                out.append(dict(kernel=kern, rows_per_wave=1, waves_per_wg=4, wg_per_cu=wpc, splitk=1, nsplit=ns))
     elif kern == T.KERNEL_SPLITK:
         for rg in (1, 2, 4):
             for P in (256, 512, 1024, 2048):
@@ -217,6 +232,11 @@ def tune_class(name, spec, reps, log):
             B = I.device_uniform((k, n), I.BASE_SEED, 910, dt)
         pk = T.pack(B, "N", mode)
         C = torch.zeros((m, n), dtype=dt if dt != torch.bfloat16 else torch.float32, device="cuda")
+    elif layout == "C":  # column-major operands: transposes of contiguous tensors
+        As = [I.device_uniform((k, m), I.BASE_SEED, 900 + r, dt).t() for r in range(2)]
+        B = I.device_uniform((n, k), I.BASE_SEED, 910, dt).t()
+        pk = T.pack(B, "C")
+        C = torch.zeros((n, m), dtype=dt, device="cuda").t()
     else:
         As = [I.device_normal((k, m), I.BASE_SEED, 920 + r, dt) for r in range(2)]
         B = I.device_normal((k, n), I.BASE_SEED, 930, dt)

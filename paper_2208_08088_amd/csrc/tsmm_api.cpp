@@ -177,7 +177,11 @@ bool parse_table_line(const std::string &line, TableKey *key, tsmm_tile *tile) {
     std::string lay, dt, md, colon, kern;
     if (!(is >> lay >> dt >> md >> key->kc >> key->nt >> key->mclass >> colon >> kern)) return false;
     if (colon != ":") return false;
-    key->layout = lay == "N" ? TSMM_OP_N : lay == "T" ? TSMM_OP_T : lay == "B" ? kLayoutBatched : -1;
+    key->layout = lay == "N"   ? TSMM_OP_N
+                  : lay == "T" ? TSMM_OP_T
+                  : lay == "C" ? TSMM_COLMAJOR
+                  : lay == "B" ? kLayoutBatched
+                               : -1;
     key->dtype = dt == "f64" ? TSMM_F64 : dt == "f32" ? TSMM_F32 : dt == "bf16" ? TSMM_BF16 : -1;
     key->mode = md == "native" ? TSMM_MODE_NATIVE : md == "bf16x3" ? TSMM_MODE_BF16X3 : md == "bf16x6" ? TSMM_MODE_BF16X6 : -1;
     if (key->layout < 0 || key->dtype < 0 || key->mode < 0) return false;
@@ -645,7 +649,7 @@ TableKey plan_key(const tsmm_plan_s &p) {
     key.layout = p.layout;
     key.dtype = p.dtype;
     key.mode = p.mode;
-    if (p.layout == TSMM_OP_N) {
+    if (p.layout != TSMM_OP_T) {
         key.kc = natural_kernel(p) == TSMM_KERNEL_SPLITBF16 ? kclass32(p.k) : kclass4(p.k);
         key.nt = ntclass(p.n);
         key.mclass = mclass_of(p.m);
