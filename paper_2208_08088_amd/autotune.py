@@ -35,7 +35,7 @@ DEFAULT_TABLE = os.path.join(HERE, "tile_table.txt")
 _DT_NAME = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}
 _KERNEL_NAME = {T.KERNEL_SIMPLE: "simple", T.KERNEL_STREAM: "stream", T.KERNEL_SPLITK: "splitk",
                 T.KERNEL_SPLITBF16: "splitbf16", T.KERNEL_VALU64: "valu64", T.KERNEL_WIDE: "wide",
-                T.KERNEL_BATCHED: "batched", T.KERNEL_SLAB: "slab"}
+                T.KERNEL_BATCHED: "batched", T.KERNEL_SLAB: "slab", T.KERNEL_COLMAJOR: "colmajor"}
 
 
 def mclass_of(m):
