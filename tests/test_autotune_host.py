@@ -1,0 +1,70 @@
+"""Host checks of the install-time autotuner (no GPU): every shape class
+yields candidate tiles the planner accepts, every kernel a candidate can
+name has a tile-table name, and the table key it writes is the one
+tsmm_plan looks up (the plan reports table=1 for it)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_2208_08088_amd import tsmm
+    if not os.path.exists(tsmm.LIB_PATH):
+        pytest.skip("libtsmm.so not built")
+    from paper_2208_08088_amd import autotune
+    return autotune
+
+
+def test_every_class_has_valid_candidates(A):
+    T = A.T
+    for name, (layout, dt, mode, m, n, k) in A.CLASSES.items():
+        if layout == "B":
+            continue  # batched plans need a device
+        p = T.plan_with_caps(m, n, k, layout, dtype=dt)
+        if mode != "native":
+            p.set_mode(mode)
+        valid = []
+        for cand in A.candidates(p):
+            try:
+                p.set_tile(**cand)
+            except T.TsmmError:
+                continue
+            valid.append(p.get_tile())
+        assert valid, name
+        for t in valid:
+            assert t["kernel"] in A._KERNEL_NAME, (name, t)
+
+
+def test_written_keys_are_the_planner_keys(A, tmp_path):
+    # one entry per class as the autotuner formats it; a child process
+    # (the table is read once per process) plans each class from it
+    lines = []
+    for name, (layout, dt, mode, m, n, k) in A.CLASSES.items():
+        if layout == "B":
+            continue
+        p = A.T.plan_with_caps(m, n, k, layout, dtype=dt)
+        if mode != "native":
+            p.set_mode(mode)
+        t = p.get_tile()
+        kc, nt, mcl = A.table_key(layout, dt, mode, m, n, k)
+        lines.append("%s %s %s %d %d %d : %s %d %d %d %d %d" % (
+            layout, A._DT_NAME[dt], mode, kc, nt, mcl, A._KERNEL_NAME[t["kernel"]], t["rows_per_wave"],
+            t["waves_per_wg"], t["wg_per_cu"], t["splitk"], t["nsplit"]))
+    tab = tmp_path / "t.txt"
+    tab.write_text("\n".join(lines) + "\n")
+    code = ("import torch\n"
+            "from paper_2208_08088_amd import autotune as A\n"
+            "for name, (layout, dt, mode, m, n, k) in A.CLASSES.items():\n"
+            "    if layout == 'B': continue\n"
+            "    p = A.T.plan_with_caps(m, n, k, layout, dtype=dt)\n"
+            "    if mode != 'native': p.set_mode(mode)\n"
+            "    assert p.info()['table'] == '1', (name, p.describe())\n"
+            "print('ok')\n")
+    env = dict(os.environ, TSMM_TILE_TABLE=str(tab), TSMM_STRICT_TABLE="1")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True)
+    assert out.returncode == 0 and "ok" in out.stdout, out.stderr[-2000:]
