@@ -53,6 +53,14 @@ def opn_bytes(m, n, k, beta, sa=8, sc=8):
     return m * (k * sa + n * sc * (2 if beta != 0.0 else 1))
 
 
+T_START = time.perf_counter()
+
+
+def log(msg):
+    """Progress line on stderr with the seconds since the start."""
+    print("[bench] %s (%.1f s)" % (msg, time.perf_counter() - T_START), file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser(description="pre-packed TSMM benchmark")
     ap.add_argument("--gpus", type=int, default=1)
@@ -537,9 +545,9 @@ def main():
     torch.cuda.set_device(0)
 
     ceiling = copy_ceiling(torch)
-    print("[bench] copy ceiling %.0f GB/s" % ceiling["GB_s"], file=sys.stderr, flush=True)
+    log("copy ceiling %.0f GB/s" % ceiling["GB_s"])
     cases = headline(torch, T, I, args)
-    print("[bench] headline cases ready: %s" % ", ".join(c["tag"] for c in cases), file=sys.stderr, flush=True)
+    log("headline cases ready: %s" % ", ".join(c["tag"] for c in cases))
     # snapshot sampled C0 rows and check one call of each case (for the CPU leg)
     rows = I.sample_rows(M_ROWS, CPU_SAMPLE_ROWS, 3)
     idx = torch.from_numpy(rows).cuda()
@@ -577,7 +585,7 @@ def main():
                                                                    pd["nsplit"], c["tag"]), bound=bnd,
                     achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=measured_traffic(c["tag"], c["p"].describe()),
                     per_launch_bytes=c["bytes"], per_launch_flops=c["flops"], avg_launch_us=ms * 1e3)
-    print("[bench] headline done: %.1f GB/s" % value, file=sys.stderr, flush=True)
+    log("headline done: %.1f GB/s" % value)
 
     result = dict(metric="TSMM GB/s (frac of HBM peak): FP64 plain vs split-BF16/FP32 at <=1e-6 rel err",
                   value=value, unit="GB/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -592,20 +600,20 @@ def main():
     keep_s = None
     if not args.no_extras and not args.only:
         small, keep_s = extras_small(torch, T, I)
-        print("[bench] small case done", file=sys.stderr, flush=True)
+        log("small case done")
         opt, keep_t = extras_opt(torch, T, I, args.steps, args.warmup)
-        print("[bench] op T done", file=sys.stderr, flush=True)
+        log("op T done")
         prec, keep_p = extras_precision(torch, T, I, args.steps, args.warmup)
-        print("[bench] precision done", file=sys.stderr, flush=True)
+        log("precision done")
         torch.cuda.empty_cache()
         bat, keep_b = extras_batched(torch, T, I, args.steps, args.warmup)
-        print("[bench] batched done", file=sys.stderr, flush=True)
+        log("batched done")
         sq, keep_q = extras_square(torch, T, I, max(3, args.steps // 4), args.warmup)
-        print("[bench] square done", file=sys.stderr, flush=True)
+        log("square done")
         tune = extras_tune(torch, T, I, args.steps, args.warmup)
-        print("[bench] runtime evaluator done", file=sys.stderr, flush=True)
+        log("runtime evaluator done")
         colm = extras_colmajor(torch, T, I, args.steps, args.warmup)
-        print("[bench] column-major done", file=sys.stderr, flush=True)
+        log("column-major done")
         del keep_t
         result["extras"] = dict(small_4096x16=small, op_t_splitk=opt, precision_m2p24_k256=prec,
                                 batched_512=bat, square_25600=sq, runtime_evaluator=tune,
@@ -626,7 +634,7 @@ def main():
             # batched: the first rows of every 64th instance
             for name, row in result["extras"]["batched_512"].items():
                 row["sample_err"] = max(oracle.normwise_rel_err(C, oracle.gemm_n(A, B)) for A, B, C in keep_b[name])
-        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+        log("cpu baseline done")
     print(json.dumps(result), flush=True)
 
 
