@@ -251,9 +251,9 @@ def tune_class(name, spec, reps, log):
             p.set_tile(**cand)
         except T.TsmmError:
             continue
-        # op N classes are timed with beta = 0 and beta = 1 (both are used)
+        # op N and column-major classes are timed with beta = 0 and beta = 1 (both are used)
         ms = time_plan(p, As, pk, C, 0.0, reps)
-        if layout == "N":
+        if layout != "T":
             ms += time_plan(p, As, pk, C, 1.0, reps)
         log("  %-14s %s  %.3f ms" % (name, " ".join("%s=%d" % kv for kv in sorted(cand.items())), ms))
         if best is None or ms < best[0]:
@@ -316,7 +316,7 @@ def main(argv=None):
         entry, ms = tune_class(name, spec, a.reps, log)
         assert " ".join(entry.split(":")[0].split()) == key, (entry, key)
         where = ("%d batched instances" % spec[3]) if spec[0] == "B" else "x".join(str(v) for v in spec[3:])
-        entries[key] = entry + "  # %.3f ms at %s%s" % (ms, where, " (beta 0 + beta 1)" if spec[0] == "N" else "")
+        entries[key] = entry + "  # %.3f ms at %s%s" % (ms, where, " (beta 0 + beta 1)" if spec[0] in "NC" else "")
         write_table(a.out, entries, header)
         log("[autotune] %s -> %s (%.3f ms)" % (name, entry, ms))
     return 0

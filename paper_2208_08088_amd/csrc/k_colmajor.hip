@@ -30,7 +30,9 @@ constexpr int kColBlock = 256;
 
 template <typename T, int KC> struct ColCfg {
     static constexpr int S = KC / 4;                // k-steps
-    static constexpr int CH = S < 4 ? S : 4;        // k-steps per A chunk
+    // k-steps per A chunk: 8 for binary64 at k classes of 128 and more (a
+    // longer prefetch ahead of the matrix-core bound products), else 4
+    static constexpr int CH = S < 4 ? S : (sizeof(T) == 8 && KC >= 128 ? 8 : 4);
     static constexpr int NCH = S / CH;              // chunks per column block
 };
 
