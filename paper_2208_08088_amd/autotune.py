@@ -146,9 +146,13 @@ def candidates(p):
             for sk in sorted({nat["splitk"], 1, 2, 3, 4, 5, 6, 8, 12, 16}):
                 out.append(dict(kernel=kern, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=1, splitk=sk, nsplit=1))
     elif kern == T.KERNEL_COLMAJOR:
-        for ns in sorted({nat["nsplit"], nat["nsplit"] * 2}):
-            for wpc in (1, 2, 4, 8, 16):
-                out.append(dict(kernel=kern, rows_per_wave=1, waves_per_wg=4, wg_per_cu=wpc, splitk=1, nsplit=ns))
+        # rows_per_wave: column groups inside the workgroup (1 or 2)
+        total = nat["nsplit"] * nat["rows_per_wave"]
+        for ng in (1, 2):
+            for ns in sorted({max(1, total // ng), max(1, 2 * total // ng)}):
+                for wpc in (1, 2, 4, 8, 16):
+                    out.append(dict(kernel=kern, rows_per_wave=ng, waves_per_wg=4, wg_per_cu=wpc, splitk=1,
+                                    nsplit=ns))
     elif kern == T.KERNEL_SPLITK:
         for rg in (1, 2, 4):
             for P in (256, 512, 1024, 2048):

@@ -55,8 +55,10 @@ __device__ __forceinline__ void col_load(const T *__restrict__ A, int64_t m, int
     }
 }
 
-// Products of chunk c: CH k-steps x NT column tiles x VW m-tiles.
-template <typename T, int KC, int NT>
+// Products of chunk c: CH k-steps x NT column tiles x VW m-tiles (SNT
+// column tiles per k-step in LDS; bofs holds the lane and the wavefront
+// group's first tile).
+template <typename T, int KC, int NT, int SNT>
 __device__ __forceinline__ void col_products(const T *__restrict__ sB, int c, int bofs,
                                              const typename Mfma4<T>::vec (&x)[ColCfg<T, KC>::CH],
                                              typename Mfma4<T>::acc (&acc)[Mfma4<T>::VW][NT]) {
@@ -67,7 +69,7 @@ __device__ __forceinline__ void col_products(const T *__restrict__ sB, int c, in
         const int s = c * CH + e;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const T b = sB[bofs + (s * NT + t) * 64];
+            const T b = sB[bofs + (s * SNT + t) * 64];
 #pragma unroll
             for (int u = 0; u < VW; ++u) acc[u][t] = Mfma4<T>::op(b, x[e][u], acc[u][t]);
         }
@@ -104,10 +106,10 @@ __device__ __forceinline__ void col_epilogue(T *__restrict__ C, int64_t m, int n
 // buffer (PAR + c) % 2; the load of the chunk after it goes to the other
 // buffer), then the epilogue.  nb: the next column block of this wavefront
 // (its first chunk is loaded during the last chunk of this one).
-template <typename T, int KC, int NT, int PAR>
+template <typename T, int KC, int NT, int SNT, int PAR>
 __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__restrict__ sB, T *__restrict__ C,
-                                          int64_t m, int n, int k, int64_t blk, int64_t nb, int n0, int lane, int j,
-                                          int q, double alpha, double beta,
+                                          int64_t m, int n, int k, int64_t blk, int64_t nb, int n0, int t0, int lane,
+                                          int j, int q, double alpha, double beta,
                                           typename Mfma4<T>::vec (&x0)[ColCfg<T, KC>::CH],
                                           typename Mfma4<T>::vec (&x1)[ColCfg<T, KC>::CH]) {
     typedef Mfma4<T> M;
@@ -120,7 +122,7 @@ __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__re
         for (int t = 0; t < NT; ++t) acc[u][t] = typename M::acc{};
     // the fragments are re-read from LDS for every block: an opaque lane
     // offset keeps the compiler from holding them in registers across blocks
-    int bofs = lane;
+    int bofs = lane + t0 * 64;
     asm volatile("" : "+v"(bofs));
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -130,20 +132,24 @@ __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__re
         if (((PAR + c) & 1) == 0) {
             col_load<T, KC>(A, m, k, lb, lc, j, q, x1);
             __builtin_amdgcn_sched_barrier(0);
-            col_products<T, KC, NT>(sB, c, bofs, x0, acc);
+            col_products<T, KC, NT, SNT>(sB, c, bofs, x0, acc);
         } else {
             col_load<T, KC>(A, m, k, lb, lc, j, q, x0);
             __builtin_amdgcn_sched_barrier(0);
-            col_products<T, KC, NT>(sB, c, bofs, x1, acc);
+            col_products<T, KC, NT, SNT>(sB, c, bofs, x1, acc);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
     col_epilogue<T, NT>(C, m, n, blk, n0, j, q, alpha, beta, acc);
 }
 
-// KC: packed k class; NT: column tiles of C per workgroup (all of n, or one
-// column group); nt_total: column tiles of the packed image.
-template <typename T, int KC, int NT>
+// KC: packed k class; NT: column tiles of C per wavefront; NG: column
+// groups inside the workgroup (its wavefronts split into NG groups that
+// walk the same column blocks, each over NT tiles of its own, so the
+// second group's read of an A chunk follows the first through the cache);
+// nt_total: column tiles of the packed image; nsplit: column groups across
+// workgroups.
+template <typename T, int KC, int NT, int NG>
 __global__ __launch_bounds__(kColBlock) void k_colmajor(const T *__restrict__ A, const T *__restrict__ Bf,
                                                          T *__restrict__ C, int64_t m, int n, int k, double alpha,
                                                          double beta, int nt_total, int nsplit) {
@@ -151,25 +157,28 @@ __global__ __launch_bounds__(kColBlock) void k_colmajor(const T *__restrict__ A,
     typedef typename M::vec vec_t;
     constexpr int VW = M::VW;
     constexpr int S = KC / 4;
-    constexpr int FRAG = S * NT * 64;
+    constexpr int SNT = NT * NG;  // column tiles of this workgroup
+    constexpr int FRAG = S * SNT * 64;
     constexpr int NCH = ColCfg<T, KC>::NCH;
     const BlockMap bm = block_map(nsplit);
-    const int n0 = bm.group * NT * 16;
 
     __shared__ T sB[FRAG];
     for (int idx = threadIdx.x * VW; idx < FRAG; idx += blockDim.x * VW) {
-        const int s = idx / (NT * 64), rem = idx % (NT * 64);
+        const int s = idx / (SNT * 64), rem = idx % (SNT * 64);
         *reinterpret_cast<vec_t *>(&sB[idx]) =
-            *reinterpret_cast<const vec_t *>(&Bf[(s * nt_total + bm.group * NT) * 64 + rem]);
+            *reinterpret_cast<const vec_t *>(&Bf[(s * nt_total + bm.group * SNT) * 64 + rem]);
     }
     __syncthreads();
 
     const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
-    const int wpb = blockDim.x >> 6;
+    const int wpg = (blockDim.x >> 6) / NG;  // wavefronts per column group
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = wave / wpg, wig = wave % wpg;
+    const int t0 = grp * NT;                         // first LDS tile of this wavefront's group
+    const int n0 = (bm.group * SNT + t0) * 16;       // its first column of C
     const int64_t nblk = (m + 16 * VW - 1) / (16 * VW);
-    const int64_t stride = bm.nrb * wpb;
-    int64_t blk = bm.rb * wpb + wave;
+    const int64_t stride = bm.nrb * wpg;
+    int64_t blk = bm.rb * wpg + wig;
     if (blk >= nblk) return;
     vec_t x0[ColCfg<T, KC>::CH], x1[ColCfg<T, KC>::CH];
     col_load<T, KC>(A, m, k, blk, 0, j, q, x0);
@@ -178,16 +187,17 @@ __global__ __launch_bounds__(kColBlock) void k_colmajor(const T *__restrict__ A,
     // a pair the first chunk is back in x0.  A pair's second block may lie
     // past the last one, where nothing is loaded or stored.
     for (; blk < nblk; blk += 2 * stride) {
-        col_block<T, KC, NT, 0>(A, sB, C, m, n, k, blk, blk + stride, n0, lane, j, q, alpha, beta, x0, x1);
-        col_block<T, KC, NT, NCH & 1>(A, sB, C, m, n, k, blk + stride, blk + 2 * stride, n0, lane, j, q, alpha,
-                                      beta, x0, x1);
+        col_block<T, KC, NT, SNT, 0>(A, sB, C, m, n, k, blk, blk + stride, n0, t0, lane, j, q, alpha, beta, x0,
+                                     x1);
+        col_block<T, KC, NT, SNT, NCH & 1>(A, sB, C, m, n, k, blk + stride, blk + 2 * stride, n0, t0, lane, j, q,
+                                           alpha, beta, x0, x1);
     }
 }
 
-template <typename T, int KC, int NT>
+template <typename T, int KC, int NT, int NG>
 hipError_t run_colmajor(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k, double alpha,
                         double beta, int64_t grid, int nt_total, int nsplit, hipStream_t s) {
-    hipLaunchKernelGGL((k_colmajor<T, KC, NT>), dim3((unsigned)grid), dim3(kColBlock), 0, s,
+    hipLaunchKernelGGL((k_colmajor<T, KC, NT, NG>), dim3((unsigned)grid), dim3(kColBlock), 0, s,
                        static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C), m, (int)n,
                        (int)k, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
@@ -197,40 +207,42 @@ typedef hipError_t (*ColFn)(const void *, const void *, void *, int64_t, int64_t
                             int, int, hipStream_t);
 struct ColEntry {
     tsmm_dtype dt;
-    int KC, NT;
+    int KC, NT, NG;
     ColFn fn;
 };
 
-// packed slice (KC/4 * NT * 64 values) within 128 KiB of LDS; accumulators
-// VW * NT tiles within 128 registers; at k classes of 128 and more at most
-// 4 column tiles (8 spilled to scratch when compiled)
-#define TSMM_COL_NT4(T, DT, KC) {DT, KC, 1, &run_colmajor<T, KC, 1>}, {DT, KC, 2, &run_colmajor<T, KC, 2>}, \
-    {DT, KC, 4, &run_colmajor<T, KC, 4>},
-#define TSMM_COL_NT8(T, DT, KC) TSMM_COL_NT4(T, DT, KC) {DT, KC, 8, &run_colmajor<T, KC, 8>},
+// packed slice (KC/4 * NT * NG * 64 values) within 128 KiB of LDS;
+// accumulators VW * NT tiles within 128 registers; at k classes of 128 and
+// more at most 4 column tiles per wavefront (8 spilled to scratch when
+// compiled), and two groups of them in one workgroup where the slice fits
+#define TSMM_COL_NT4(T, DT, KC) {DT, KC, 1, 1, &run_colmajor<T, KC, 1, 1>}, {DT, KC, 2, 1, &run_colmajor<T, KC, 2, 1>}, \
+    {DT, KC, 4, 1, &run_colmajor<T, KC, 4, 1>},
+#define TSMM_COL_NT8(T, DT, KC) TSMM_COL_NT4(T, DT, KC) {DT, KC, 8, 1, &run_colmajor<T, KC, 8, 1>},
 static const ColEntry kColTable[] = {
     TSMM_COL_NT8(double, TSMM_F64, 4) TSMM_COL_NT8(double, TSMM_F64, 8) TSMM_COL_NT8(double, TSMM_F64, 16)
     TSMM_COL_NT8(double, TSMM_F64, 32) TSMM_COL_NT8(double, TSMM_F64, 64) TSMM_COL_NT4(double, TSMM_F64, 128)
-    TSMM_COL_NT4(double, TSMM_F64, 256)
+    TSMM_COL_NT4(double, TSMM_F64, 256) {TSMM_F64, 128, 4, 2, &run_colmajor<double, 128, 4, 2>},
     TSMM_COL_NT8(float, TSMM_F32, 4) TSMM_COL_NT8(float, TSMM_F32, 8) TSMM_COL_NT8(float, TSMM_F32, 16)
     TSMM_COL_NT8(float, TSMM_F32, 32) TSMM_COL_NT8(float, TSMM_F32, 64) TSMM_COL_NT4(float, TSMM_F32, 128)
-    TSMM_COL_NT4(float, TSMM_F32, 256)
+    TSMM_COL_NT4(float, TSMM_F32, 256) {TSMM_F32, 128, 4, 2, &run_colmajor<float, 128, 4, 2>},
+    {TSMM_F32, 256, 4, 2, &run_colmajor<float, 256, 4, 2>},
 };
 #undef TSMM_COL_NT4
 #undef TSMM_COL_NT8
 
-static const ColEntry *find_col(tsmm_dtype dt, int KC, int NT) {
+static const ColEntry *find_col(tsmm_dtype dt, int KC, int NT, int NG) {
     for (const ColEntry &e : kColTable)
-        if (e.dt == dt && e.KC == KC && e.NT == NT) return &e;
+        if (e.dt == dt && e.KC == KC && e.NT == NT && e.NG == NG) return &e;
     return nullptr;
 }
 
-bool colmajor_variant_exists(tsmm_dtype dt, int KC, int NT) { return find_col(dt, KC, NT) != nullptr; }
+bool colmajor_variant_exists(tsmm_dtype dt, int KC, int NT, int NG) { return find_col(dt, KC, NT, NG) != nullptr; }
 
-hipError_t launch_colmajor(tsmm_dtype dt, int KC, int NT, const void *A, const void *Bf, void *C, int64_t m,
+hipError_t launch_colmajor(tsmm_dtype dt, int KC, int NT, int NG, const void *A, const void *Bf, void *C, int64_t m,
                            int64_t n, int64_t k, double alpha, double beta, int64_t grid, int nt_total, int nsplit,
                            hipStream_t s) {
-    const ColEntry *e = find_col(dt, KC, NT);
-    if (!e || NT * nsplit != nt_total || m % (dt == TSMM_F64 ? 2 : 4) != 0) return hipErrorInvalidValue;
+    const ColEntry *e = find_col(dt, KC, NT, NG);
+    if (!e || NT * NG * nsplit != nt_total || m % (dt == TSMM_F64 ? 2 : 4) != 0) return hipErrorInvalidValue;
     return e->fn(A, Bf, C, m, n, k, alpha, beta, grid, nt_total, nsplit, s);
 }
 

@@ -380,7 +380,15 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
                 (size_t)(KC / 4) * (NT / t.nsplit) * 64 * elem_bytes(p.dtype) > kLdsBudget) &&
                t.nsplit < NT)
             t.nsplit *= 2;
+        // rows_per_wave: column groups inside the workgroup.  Two groups of
+        // wavefronts in one workgroup instead of two workgroups when both
+        // slices fit the LDS: the second read of A then hits the cache.
         t.rows_per_wave = 1;
+        if (t.nsplit == 2 && (size_t)(KC / 4) * NT * 64 * elem_bytes(p.dtype) <= kLdsBudget &&
+            colmajor_variant_exists(p.dtype, KC, NT / 2, 2)) {
+            t.rows_per_wave = 2;
+            t.nsplit = 1;
+        }
         t.wg_per_cu = 8;
         break;
     }
@@ -518,17 +526,21 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         p.KC = kclass4(p.k);
         p.NT = ntclass(p.n);
         p.vec = false;
-        if (t.nsplit > p.NT) return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d > %d column tiles", t.nsplit, p.NT);
-        const int NTs = p.NT / t.nsplit;
-        if (t.rows_per_wave != 1 || !colmajor_variant_exists(p.dtype, p.KC, NTs))
-            return fail(TSMM_ERROR_NOT_SUPPORTED, "no column-major kernel for KC=%d NT=%d (rows_per_wave 1)", p.KC,
-                        NTs);
+        const int NG = t.rows_per_wave;  // column groups inside a workgroup
+        if (NG != 1 && NG != 2)
+            return fail(TSMM_ERROR_INVALID_VALUE, "column-major: rows_per_wave (column groups per workgroup) 1 or 2");
+        if (t.nsplit * NG > p.NT)
+            return fail(TSMM_ERROR_INVALID_VALUE, "nsplit %d x %d groups > %d column tiles", t.nsplit, NG, p.NT);
+        const int NTw = p.NT / (t.nsplit * NG);
+        if (!colmajor_variant_exists(p.dtype, p.KC, NTw, NG))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no column-major kernel for KC=%d NT=%d groups=%d", p.KC, NTw,
+                        NG);
         if (t.waves_per_wg != 4)
             return fail(TSMM_ERROR_INVALID_VALUE, "the column-major kernel runs 4 wavefronts per workgroup");
-        // column blocks of 16 * VW m indices, one per wavefront step
+        // column blocks of 16 * VW m indices, one per wavefront step of each group
         const int vw = p.dtype == TSMM_F64 ? 2 : 4;
         const int64_t blocks = (p.m + 16 * vw - 1) / (16 * vw);
-        const int64_t wgs = (blocks + t.waves_per_wg - 1) / t.waves_per_wg;
+        const int64_t wgs = (blocks + t.waves_per_wg / NG - 1) / (t.waves_per_wg / NG);
         int64_t rows = std::max<int64_t>(1, std::min<int64_t>(wgs, cus * t.wg_per_cu / t.nsplit));
         if (t.nsplit > 1) rows = (rows + 7) / 8 * 8;
         p.grid = rows * t.nsplit;
@@ -1180,8 +1192,9 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
             e = launch_simple_n(p->dtype, Brow, A, C, p->n, p->m, p->k, alpha, beta, s);  // C^T = B^T A^T
             break;
         }
-        e = launch_colmajor(p->dtype, p->KC, p->NT / p->tile.nsplit, A, base + packed->L.off_frag, C, p->m, p->n,
-                            p->k, alpha, beta, p->grid, p->NT, p->tile.nsplit, s);
+        e = launch_colmajor(p->dtype, p->KC, p->NT / (p->tile.nsplit * p->tile.rows_per_wave), p->tile.rows_per_wave,
+                            A, base + packed->L.off_frag, C, p->m, p->n, p->k, alpha, beta, p->grid, p->NT,
+                            p->tile.nsplit, s);
         break;
     case TSMM_KERNEL_SLAB: {
         const bool il = frag4_pg(p->dtype, p->NT, p->n) > 1;
@@ -1254,8 +1267,10 @@ std::vector<tsmm_tile> tune_candidates(const tsmm_plan_s &p) {
             for (int sk : {1, 2, 3, 4, 5, 6, 8, 12, 16}) add(nat, rt, 1, sk, 1);
         break;
     case TSMM_KERNEL_COLMAJOR:
-        for (int ns : {d.nsplit, 2 * d.nsplit})
-            for (int wpc : {1, 2, 4, 8, 16}) add(nat, 1, wpc, 1, ns);
+        for (int ng : {1, 2})
+            for (int ns : {d.nsplit * d.rows_per_wave / ng, 2 * d.nsplit * d.rows_per_wave / ng})
+                for (int wpc : {1, 2, 4, 8, 16})
+                    if (ns >= 1) add(nat, ng, wpc, 1, ns);
         break;
     default:
         break;

@@ -288,10 +288,11 @@ int slab_rows(int RT);  // rows of one work item (four wavefronts of RT 16-row t
 // Column-major operands: packed B (scalar k-slot mapping, plain column
 // order, nt_total column tiles) times column-major A into column-major C;
 // m a multiple of the vector width, A and C 16-byte aligned.
-hipError_t launch_colmajor(tsmm_dtype dt, int KC, int NT, const void *A, const void *Bf, void *C, int64_t m,
+// NT column tiles per wavefront, NG column groups inside a workgroup.
+hipError_t launch_colmajor(tsmm_dtype dt, int KC, int NT, int NG, const void *A, const void *Bf, void *C, int64_t m,
                            int64_t n, int64_t k, double alpha, double beta, int64_t grid, int nt_total, int nsplit,
                            hipStream_t s);
-bool colmajor_variant_exists(tsmm_dtype dt, int KC, int NT);
+bool colmajor_variant_exists(tsmm_dtype dt, int KC, int NT, int NG);
 
 // Batched persistent launch: workgroup w runs work tiles
 // [wg_begin[w], wg_begin[w+1]) of the instance sequence described by

@@ -98,3 +98,21 @@ def test_colmajor_rejects_row_major_and_other_types():
     with pytest.raises(T.TsmmError) as e:
         T.plan(1000, 8, 8, "C", torch.bfloat16)
     assert e.value.status == T.NOT_SUPPORTED
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_colmajor_column_groups_in_and_across_workgroups(dtype):
+    # k = n = 128: two column groups, as two groups of wavefronts in one
+    # workgroup (rows_per_wave 2) or across workgroups (nsplit 2): the same
+    # products, so the same bits
+    m, k, n = 6000, 128, 128
+    f = np.float64 if dtype == torch.float64 else np.float32
+    A = I.host_uniform((m, k), 73, 1, dtype=f)
+    B = I.host_uniform((k, n), 73, 2, dtype=f)
+    C0 = I.host_uniform((m, n), 73, 3, dtype=f)
+    inside, p, _ = run(A, B, C0, 1.5, 0.5, dtype, dict(kernel=T.KERNEL_COLMAJOR, rows_per_wave=2, nsplit=1))
+    assert p.get_tile()["rows_per_wave"] == 2
+    across, q, _ = run(A, B, C0, 1.5, 0.5, dtype, dict(kernel=T.KERNEL_COLMAJOR, rows_per_wave=1, nsplit=2))
+    assert q.get_tile()["nsplit"] == 2
+    assert np.array_equal(inside, across)
+    assert_normwise(inside, oracle.gemm_n(A, B, C0, 1.5, 0.5), 1e-12 if dtype == torch.float64 else 1e-6)
