@@ -314,7 +314,10 @@ void tsmm_plan_destroy(tsmm_plan_t plan);
  * need 16-byte aligned A (and C, where they store 16-byte vectors) and the
  * plan then runs the any-shape kernel instead (split-bf16 modes report
  * INVALID_VALUE).
- * Asynchronous on the plan's stream.
+ * Asynchronous on the plan's stream.  An execute may be captured in a HIP
+ * graph (it launches kernels only: no allocation, copy or memset) once the
+ * plan's workspace, if it needs one, is attached or was allocated by an
+ * earlier execute; every replay then gives the eager result.
  * Errors: INVALID_VALUE, SHAPE_MISMATCH, OUT_OF_MEMORY (lazy workspace),
  * HIP (launch failure; text in tsmm_last_error). */
 tsmm_status tsmm_execute(tsmm_plan_t plan, const void *A, tsmm_packed_t packed,
