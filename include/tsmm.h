@@ -78,7 +78,12 @@ typedef enum tsmm_layout {
     TSMM_COLMAJOR = 2  /* C = alpha*A*B + beta*C with A (m x k), B (k x n)
                           and C (m x n) column-major (element (i, j) at
                           i + j * rows), the layout of the paper's analysis
-                          (Sec. IV-A); binary64 / binary32, NATIVE mode */
+                          (Sec. IV-A); binary64 / binary32, NATIVE mode.
+                          Also the row-major small-A times wide-B
+                          orientation: row-major C = A B is column-major
+                          C^T = B^T A^T on the same memory, i.e. this
+                          layout with (m, n, k) = (n, m, k), the wide B as
+                          A, the small A packed as B (k x m)         */
 } tsmm_layout;
 
 /* Arithmetic used for TSMM_F32 inputs (other types accept NATIVE only).

@@ -116,3 +116,25 @@ def test_colmajor_column_groups_in_and_across_workgroups(dtype):
     assert q.get_tile()["nsplit"] == 2
     assert np.array_equal(inside, across)
     assert_normwise(inside, oracle.gemm_n(A, B, C0, 1.5, 0.5), 1e-12 if dtype == torch.float64 else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_small_times_wide_row_major_through_colmajor(dtype):
+    # row-major C (m x n) = A (m x k, small) * B (k x n, wide) is, on the
+    # same memory, the column-major problem C^T = B^T A^T: the wide B is the
+    # column-major "A" (n x k), the small A the packed column-major "B"
+    # (k x m), C the column-major n x m result
+    m, k, n = 24, 32, 100000
+    f = np.float64 if dtype == torch.float64 else np.float32
+    A = I.host_uniform((m, k), 81, 1, dtype=f)
+    B = I.host_uniform((k, n), 81, 2, dtype=f)
+    C0 = I.host_uniform((m, n), 81, 3, dtype=f)
+    Ad = torch.from_numpy(A).to(dtype).cuda()        # row-major m x k
+    Bd = torch.from_numpy(B).to(dtype).cuda()        # row-major k x n
+    Cd = torch.from_numpy(C0).to(dtype).cuda()       # row-major m x n
+    p = T.plan(n, m, k, "C", dtype)
+    pk = T.pack(Ad.t(), "C")                         # A^T: column-major k x m
+    announce("small x wide", dtype)
+    T.execute(p, Bd.t(), pk, Cd.t(), 1.5, 0.5)       # B^T: column-major n x k; C^T: column-major n x m
+    assert p.info()["kernel"] == "colmajor"
+    assert_normwise(host(Cd), oracle.gemm_n(A, B, C0, 1.5, 0.5), 1e-12 if dtype == torch.float64 else 1e-6)
