@@ -328,6 +328,21 @@ void tsmm_plan_destroy(tsmm_plan_t plan);
 tsmm_status tsmm_execute(tsmm_plan_t plan, const void *A, tsmm_packed_t packed,
                          void *C, double alpha, double beta);
 
+/* tsmm_execute with leading dimensions (strided operands, as in BLAS):
+ *   lda  TSMM_OP_N: row stride of A (>= k); TSMM_OP_T: row stride of the
+ *        k x m A (>= m); TSMM_COLMAJOR: column stride of A (>= m).
+ *   ldc  TSMM_OP_N / TSMM_OP_T: row stride of C (>= n); TSMM_COLMAJOR:
+ *        column stride of C (>= m).
+ * In elements.  tsmm_execute is this call with the natural strides.  The
+ * streaming, k-slab and column-major kernels take strides (vector accesses
+ * need the stride to be a multiple of the 16-byte vector width, else the
+ * any-shape kernel runs); the other kernels run the any-shape kernel when
+ * a stride is not the natural one, and the split-bf16 modes refuse it.
+ * Errors: as tsmm_execute; INVALID_VALUE for strides below the natural
+ * ones or, in the split-bf16 modes, other than them. */
+tsmm_status tsmm_execute_ld(tsmm_plan_t plan, const void *A, int64_t lda, tsmm_packed_t packed,
+                            void *C, int64_t ldc, double alpha, double beta);
+
 /* ----------------------------------------------------------------- batched */
 
 /* Plan `count` independent op N multiplies that run in ONE persistent

@@ -46,11 +46,11 @@ __device__ __forceinline__ void segment_f32(const BatchDesc &d, int64_t row_a, i
     int64_t t = (row_a >> 4) + (int64_t)wave * RT;
     if (t >= tend) return;
     float a0[RT][S], a1[RT][S];
-    stream_load_a<float, KC, RT, VEC>(A, row_b, k, kfull, t, voff0, q, a0);
+    stream_load_a<float, KC, RT, VEC>(A, row_b, k, k, kfull, t, voff0, q, a0);
     for (; t < tend; t += 2 * tstride) {
-        stream_step<float, KC, NT, RT, VEC, IL, CPRE>(A, sB, NT, C, row_b, n, k, kfull, d.alpha, d.beta, 0, t,
+        stream_step<float, KC, NT, RT, VEC, IL, CPRE>(A, sB, NT, C, row_b, n, k, k, n, kfull, d.alpha, d.beta, 0, t,
                                                       t + tstride, voff0, q, lane, j, a0, a1);
-        stream_step<float, KC, NT, RT, VEC, IL, CPRE>(A, sB, NT, C, row_b, n, k, kfull, d.alpha, d.beta, 0,
+        stream_step<float, KC, NT, RT, VEC, IL, CPRE>(A, sB, NT, C, row_b, n, k, k, n, kfull, d.alpha, d.beta, 0,
                                                       t + tstride, t + 2 * tstride, voff0, q, lane, j, a1, a0);
     }
 }

@@ -41,7 +41,8 @@ template <typename T, int KC> struct ColCfg {
 // and m indices past m read 0 (m is a multiple of VW, so a vector lies
 // wholly inside or outside).
 template <typename T, int KC>
-__device__ __forceinline__ void col_load(const T *__restrict__ A, int64_t m, int k, int64_t blk, int c, int j, int q,
+__device__ __forceinline__ void col_load(const T *__restrict__ A, int64_t m, int k, int64_t lda, int64_t blk, int c,
+                                         int j, int q,
                                          typename Mfma4<T>::vec (&x)[ColCfg<T, KC>::CH]) {
     typedef typename Mfma4<T>::vec vec_t;
     constexpr int VW = Mfma4<T>::VW;
@@ -50,7 +51,7 @@ __device__ __forceinline__ void col_load(const T *__restrict__ A, int64_t m, int
 #pragma unroll
     for (int e = 0; e < CH; ++e) {
         const int col = 4 * (c * CH + e) + q;
-        x[e] = (i < m && col < k) ? __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(A + i + (int64_t)col * m))
+        x[e] = (i < m && col < k) ? __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(A + i + col * lda))
                                   : vec_t{};
     }
 }
@@ -79,7 +80,8 @@ __device__ __forceinline__ void col_products(const T *__restrict__ sB, int c, in
 // Epilogue of column block blk: lane (q, j) holds C columns n0 + 16*t +
 // row(q, r) at m indices i0 + VW*j + u, u < VW (one 16-byte vector).
 template <typename T, int NT>
-__device__ __forceinline__ void col_epilogue(T *__restrict__ C, int64_t m, int n, int64_t blk, int n0, int j, int q,
+__device__ __forceinline__ void col_epilogue(T *__restrict__ C, int64_t m, int n, int64_t ldc, int64_t blk, int n0,
+                                             int j, int q,
                                              double alpha, double beta,
                                              const typename Mfma4<T>::acc (&acc)[Mfma4<T>::VW][NT]) {
     typedef Mfma4<T> M;
@@ -93,7 +95,7 @@ __device__ __forceinline__ void col_epilogue(T *__restrict__ C, int64_t m, int n
         for (int r = 0; r < 4; ++r) {
             const int col = n0 + 16 * t + M::row(q, r);
             if (col >= n) continue;
-            vec_t *p = reinterpret_cast<vec_t *>(C + i + (int64_t)col * m);
+            vec_t *p = reinterpret_cast<vec_t *>(C + i + col * ldc);
             const vec_t cv = beta != 0.0 ? __builtin_nontemporal_load(p) : vec_t{};
             vec_t v;
 #pragma unroll
@@ -108,8 +110,8 @@ __device__ __forceinline__ void col_epilogue(T *__restrict__ C, int64_t m, int n
 // (its first chunk is loaded during the last chunk of this one).
 template <typename T, int KC, int NT, int SNT, int PAR>
 __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__restrict__ sB, T *__restrict__ C,
-                                          int64_t m, int n, int k, int64_t blk, int64_t nb, int n0, int t0, int lane,
-                                          int j, int q, double alpha, double beta,
+                                          int64_t m, int n, int k, int64_t lda, int64_t ldc, int64_t blk, int64_t nb,
+                                          int n0, int t0, int lane, int j, int q, double alpha, double beta,
                                           typename Mfma4<T>::vec (&x0)[ColCfg<T, KC>::CH],
                                           typename Mfma4<T>::vec (&x1)[ColCfg<T, KC>::CH]) {
     typedef Mfma4<T> M;
@@ -130,17 +132,17 @@ __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__re
         const int64_t lb = last ? nb : blk;
         const int lc = last ? 0 : c + 1;
         if (((PAR + c) & 1) == 0) {
-            col_load<T, KC>(A, m, k, lb, lc, j, q, x1);
+            col_load<T, KC>(A, m, k, lda, lb, lc, j, q, x1);
             __builtin_amdgcn_sched_barrier(0);
             col_products<T, KC, NT, SNT>(sB, c, bofs, x0, acc);
         } else {
-            col_load<T, KC>(A, m, k, lb, lc, j, q, x0);
+            col_load<T, KC>(A, m, k, lda, lb, lc, j, q, x0);
             __builtin_amdgcn_sched_barrier(0);
             col_products<T, KC, NT, SNT>(sB, c, bofs, x1, acc);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    col_epilogue<T, NT>(C, m, n, blk, n0, j, q, alpha, beta, acc);
+    col_epilogue<T, NT>(C, m, n, ldc, blk, n0, j, q, alpha, beta, acc);
 }
 
 // KC: packed k class; NT: column tiles of C per wavefront; NG: column
@@ -151,8 +153,9 @@ __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__re
 // workgroups.
 template <typename T, int KC, int NT, int NG>
 __global__ __launch_bounds__(kColBlock) void k_colmajor(const T *__restrict__ A, const T *__restrict__ Bf,
-                                                         T *__restrict__ C, int64_t m, int n, int k, double alpha,
-                                                         double beta, int nt_total, int nsplit) {
+                                                         T *__restrict__ C, int64_t m, int n, int k, int64_t lda,
+                                                         int64_t ldc, double alpha, double beta, int nt_total,
+                                                         int nsplit) {
     typedef Mfma4<T> M;
     typedef typename M::vec vec_t;
     constexpr int VW = M::VW;
@@ -181,30 +184,31 @@ __global__ __launch_bounds__(kColBlock) void k_colmajor(const T *__restrict__ A,
     int64_t blk = bm.rb * wpg + wig;
     if (blk >= nblk) return;
     vec_t x0[ColCfg<T, KC>::CH], x1[ColCfg<T, KC>::CH];
-    col_load<T, KC>(A, m, k, blk, 0, j, q, x0);
+    col_load<T, KC>(A, m, k, lda, blk, 0, j, q, x0);
     // Blocks go in pairs: a block of NCH chunks that starts in buffer p
     // leaves the next block's first chunk in buffer (p + NCH) % 2, so after
     // a pair the first chunk is back in x0.  A pair's second block may lie
     // past the last one, where nothing is loaded or stored.
     for (; blk < nblk; blk += 2 * stride) {
-        col_block<T, KC, NT, SNT, 0>(A, sB, C, m, n, k, blk, blk + stride, n0, t0, lane, j, q, alpha, beta, x0,
-                                     x1);
-        col_block<T, KC, NT, SNT, NCH & 1>(A, sB, C, m, n, k, blk + stride, blk + 2 * stride, n0, t0, lane, j, q,
-                                           alpha, beta, x0, x1);
+        col_block<T, KC, NT, SNT, 0>(A, sB, C, m, n, k, lda, ldc, blk, blk + stride, n0, t0, lane, j, q, alpha, beta,
+                                     x0, x1);
+        col_block<T, KC, NT, SNT, NCH & 1>(A, sB, C, m, n, k, lda, ldc, blk + stride, blk + 2 * stride, n0, t0, lane,
+                                           j, q, alpha, beta, x0, x1);
     }
 }
 
 template <typename T, int KC, int NT, int NG>
-hipError_t run_colmajor(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k, double alpha,
-                        double beta, int64_t grid, int nt_total, int nsplit, hipStream_t s) {
+hipError_t run_colmajor(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k, int64_t lda,
+                        int64_t ldc, double alpha, double beta, int64_t grid, int nt_total, int nsplit,
+                        hipStream_t s) {
     hipLaunchKernelGGL((k_colmajor<T, KC, NT, NG>), dim3((unsigned)grid), dim3(kColBlock), 0, s,
                        static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C), m, (int)n,
-                       (int)k, alpha, beta, nt_total, nsplit);
+                       (int)k, lda, ldc, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
 }
 
-typedef hipError_t (*ColFn)(const void *, const void *, void *, int64_t, int64_t, int64_t, double, double, int64_t,
-                            int, int, hipStream_t);
+typedef hipError_t (*ColFn)(const void *, const void *, void *, int64_t, int64_t, int64_t, int64_t, int64_t, double,
+                            double, int64_t, int, int, hipStream_t);
 struct ColEntry {
     tsmm_dtype dt;
     int KC, NT, NG;
@@ -239,11 +243,13 @@ static const ColEntry *find_col(tsmm_dtype dt, int KC, int NT, int NG) {
 bool colmajor_variant_exists(tsmm_dtype dt, int KC, int NT, int NG) { return find_col(dt, KC, NT, NG) != nullptr; }
 
 hipError_t launch_colmajor(tsmm_dtype dt, int KC, int NT, int NG, const void *A, const void *Bf, void *C, int64_t m,
-                           int64_t n, int64_t k, double alpha, double beta, int64_t grid, int nt_total, int nsplit,
-                           hipStream_t s) {
+                           int64_t n, int64_t k, int64_t lda, int64_t ldc, double alpha, double beta, int64_t grid,
+                           int nt_total, int nsplit, hipStream_t s) {
     const ColEntry *e = find_col(dt, KC, NT, NG);
-    if (!e || NT * NG * nsplit != nt_total || m % (dt == TSMM_F64 ? 2 : 4) != 0) return hipErrorInvalidValue;
-    return e->fn(A, Bf, C, m, n, k, alpha, beta, grid, nt_total, nsplit, s);
+    const int vw = dt == TSMM_F64 ? 2 : 4;
+    if (!e || NT * NG * nsplit != nt_total || m % vw != 0 || lda % vw != 0 || ldc % vw != 0 || lda < m || ldc < m)
+        return hipErrorInvalidValue;
+    return e->fn(A, Bf, C, m, n, k, lda, ldc, alpha, beta, grid, nt_total, nsplit, s);
 }
 
 }  // namespace tsmm

@@ -88,44 +88,54 @@ template <> struct SimpleIO<uint16_t> {
     static __device__ float ld(const uint16_t *p, int64_t i) { return bf16_bits_to_float(p[i]); }
 };
 
+// Row strides: A lda (op N: A(i, l) at i*lda + l; op T: A(l, i) at
+// l*lda + i), B ldb, C ldc.
 template <typename Tin, typename Tout, bool TRANS>
 __global__ void k_simple(const Tin *__restrict__ A, const Tin *__restrict__ B, Tout *__restrict__ C,
-                         int64_t m, int64_t n, int64_t k, double alpha, double beta) {
+                         int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int64_t ldc, double alpha,
+                         double beta) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= m * n) return;
     const int64_t i = idx / n, j = idx % n;
     typedef typename SimpleIO<Tin>::acc Acc;
     Acc s = 0;
     for (int64_t l = 0; l < k; ++l) {
-        const Acc a = TRANS ? SimpleIO<Tin>::ld(A, l * m + i) : SimpleIO<Tin>::ld(A, i * k + l);
-        s = __builtin_fma(a, SimpleIO<Tin>::ld(B, l * n + j), s);
+        const Acc a = TRANS ? SimpleIO<Tin>::ld(A, l * lda + i) : SimpleIO<Tin>::ld(A, i * lda + l);
+        s = __builtin_fma(a, SimpleIO<Tin>::ld(B, l * ldb + j), s);
     }
-    const double c = beta != 0.0 ? (double)C[idx] : 0.0;
-    C[idx] = (Tout)epilogue(alpha, (double)s, beta, c);
+    Tout *c = C + i * ldc + j;
+    const double cv = beta != 0.0 ? (double)*c : 0.0;
+    *c = (Tout)epilogue(alpha, (double)s, beta, cv);
 }
 
 template <typename TI, typename TO>
 static void simple_t(bool trans, const void *A, const void *B, void *C, int64_t m, int64_t n, int64_t k,
-                     double alpha, double beta, hipStream_t s) {
+                     int64_t lda, int64_t ldb, int64_t ldc, double alpha, double beta, hipStream_t s) {
     const dim3 g(blocks_for(m * n, 256)), b(256);
     if (trans)
         hipLaunchKernelGGL((k_simple<TI, TO, true>), g, b, 0, s, (const TI *)A, (const TI *)B, (TO *)C, m, n, k,
-                           alpha, beta);
+                           lda, ldb, ldc, alpha, beta);
     else
         hipLaunchKernelGGL((k_simple<TI, TO, false>), g, b, 0, s, (const TI *)A, (const TI *)B, (TO *)C, m, n, k,
-                           alpha, beta);
+                           lda, ldb, ldc, alpha, beta);
+}
+
+hipError_t launch_simple_ld(tsmm_dtype dt, bool trans, const void *A, int64_t lda, const void *B, int64_t ldb,
+                            void *C, int64_t ldc, int64_t m, int64_t n, int64_t k, double alpha, double beta,
+                            hipStream_t s) {
+    if (m * n <= 0) return hipSuccess;
+    if (dt == TSMM_F64)
+        simple_t<double, double>(trans, A, B, C, m, n, k, lda, ldb, ldc, alpha, beta, s);
+    else if (dt == TSMM_F32)
+        simple_t<float, float>(trans, A, B, C, m, n, k, lda, ldb, ldc, alpha, beta, s);
+    else
+        simple_t<uint16_t, float>(trans, A, B, C, m, n, k, lda, ldb, ldc, alpha, beta, s);
+    return hipGetLastError();
 }
 
 static hipError_t simple(tsmm_dtype dt, bool trans, const void *A, const void *B, void *C, int64_t m,
                          int64_t n, int64_t k, double alpha, double beta, hipStream_t s) {
-    if (m * n <= 0) return hipSuccess;
-    if (dt == TSMM_F64)
-        simple_t<double, double>(trans, A, B, C, m, n, k, alpha, beta, s);
-    else if (dt == TSMM_F32)
-        simple_t<float, float>(trans, A, B, C, m, n, k, alpha, beta, s);
-    else
-        simple_t<uint16_t, float>(trans, A, B, C, m, n, k, alpha, beta, s);
-    return hipGetLastError();
+    return launch_simple_ld(dt, trans, A, trans ? m : k, B, n, C, n, m, n, k, alpha, beta, s);
 }
 
 hipError_t launch_simple_n(tsmm_dtype dt, const void *A, const void *B, void *C, int64_t m,
@@ -150,11 +160,12 @@ bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool
 }
 
 hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il, const void *A,
-                         const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, double alpha,
-                         double beta, int64_t grid, int block, int nt_total, int nsplit, hipStream_t s) {
+                         const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldc,
+                         double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
+                         hipStream_t s) {
     StreamFn fn = find_stream(dt, KC, NT, RT, vec, il);
     if (!fn || nsplit < 1 || NT * nsplit != nt_total) return hipErrorInvalidValue;
-    return fn(A, Bfrag, C, m, n, k, alpha, beta, grid, block, nt_total, nsplit, s);
+    return fn(A, Bfrag, C, m, n, k, lda, ldc, alpha, beta, grid, block, nt_total, nsplit, s);
 }
 
 }  // namespace tsmm

@@ -54,8 +54,8 @@ __device__ __forceinline__ void slab_dma(__amdgpu_buffer_rsrc_t rb, int64_t sl, 
 // the packed fragments use (tsmm_internal.h): with VEC, load p of lane q
 // holds columns 32*sl + 4*VW*p + VW*q + e, e < VW, for k-steps VW*p + e.
 template <typename T, int RT, bool VEC>
-__device__ __forceinline__ void slab_load_a(const T *__restrict__ A, int64_t m, int k, int64_t tile0, int64_t sl,
-                                            int j, int q, T (&a)[RT][kSlabSteps]) {
+__device__ __forceinline__ void slab_load_a(const T *__restrict__ A, int64_t m, int k, int lda, int64_t tile0,
+                                            int64_t sl, int j, int q, T (&a)[RT][kSlabSteps]) {
     typedef typename Mfma4<T>::vec vec_t;
     constexpr int VW = Mfma4<T>::VW;
     constexpr int SZ = (int)sizeof(T);
@@ -63,10 +63,11 @@ __device__ __forceinline__ void slab_load_a(const T *__restrict__ A, int64_t m, 
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((tile0 + rt) * 16);
-        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, tile_rows(m, row0) * (int64_t)k * SZ);
+        const int64_t rows = tile_rows(m, row0);
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * lda, rows ? ((rows - 1) * lda + k) * SZ : 0);
         // rows of a slab are 128 / 256 bytes read by two or four loads, which
         // share each line through the cache (default policy)
-        int vo = j * k * SZ;
+        int vo = j * lda * SZ;
         asm volatile("" : "+v"(vo));
         if constexpr (VEC) {
 #pragma unroll
@@ -124,7 +125,7 @@ __device__ __forceinline__ void slab_products(const T *__restrict__ sb, const T 
 template <typename T, int NT, int RT, bool VEC, bool IL>
 __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_slab(
     const T *__restrict__ A, const T *__restrict__ Bf, T *__restrict__ C, double *__restrict__ W, int64_t m, int n,
-    int k, int64_t nsl, double alpha, double beta, int splitk, int64_t nrb) {
+    int k, int lda, int ldc, int64_t nsl, double alpha, double beta, int splitk, int64_t nrb) {
     typedef Mfma4<T> M;
     typedef typename M::acc acc_t;
     constexpr int SZ = (int)sizeof(T);
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu
         __syncthreads();
         T a0[RT][kSlabSteps], a1[RT][kSlabSteps];
         slab_dma<T, NT>(rb, sl0, wave, lane, sb0);
-        slab_load_a<T, RT, VEC>(A, m, k, tile0, sl0, j, q, a0);
+        slab_load_a<T, RT, VEC>(A, m, k, lda, tile0, sl0, j, q, a0);
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's share of the slab and its A
         __syncthreads();                     // every share has landed
         // slabs go in pairs over the two buffers; the pair's second slab may
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu
             const bool two = sl + 1 < sl1;
             if (two) {
                 slab_dma<T, NT>(rb, sl + 1, wave, lane, sb1);
-                slab_load_a<T, RT, VEC>(A, m, k, tile0, sl + 1, j, q, a1);
+                slab_load_a<T, RT, VEC>(A, m, k, lda, tile0, sl + 1, j, q, a1);
             }
             slab_products<T, NT, RT>(reinterpret_cast<const T *>(sb0), a0, acc, lane);
             __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu
             if (!two) break;
             if (sl + 2 < sl1) {
                 slab_dma<T, NT>(rb, sl + 2, wave, lane, sb0);
-                slab_load_a<T, RT, VEC>(A, m, k, tile0, sl + 2, j, q, a0);
+                slab_load_a<T, RT, VEC>(A, m, k, lda, tile0, sl + 2, j, q, a0);
             }
             slab_products<T, NT, RT>(reinterpret_cast<const T *>(sb1), a1, acc, lane);
             __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -205,15 +206,16 @@ __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int64_t row0 = uniform64((tile0 + rt) * 16);
-            const int64_t bytes = tile_rows(m, row0) * (int64_t)n * SZ;
-            const __amdgpu_buffer_rsrc_t rc = make_rsrc(C + row0 * n, bytes);
-            const __amdgpu_buffer_rsrc_t rl = make_rsrc(C + row0 * n, beta != 0.0 ? bytes : 0);
+            const int64_t rows = tile_rows(m, row0);
+            const int64_t bytes = rows ? ((rows - 1) * ldc + n) * SZ : 0;
+            const __amdgpu_buffer_rsrc_t rc = make_rsrc(C + row0 * ldc, bytes);
+            const __amdgpu_buffer_rsrc_t rl = make_rsrc(C + row0 * ldc, beta != 0.0 ? bytes : 0);
             if constexpr (IL) {
 #pragma unroll
                 for (int g = 0; g < NT / PG; ++g)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int off = colp(PG * g) < n ? (M::row(q, r) * n + colp(PG * g)) * SZ : kOOB;
+                        const int off = colp(PG * g) < n ? (M::row(q, r) * ldc + colp(PG * g)) * SZ : kOOB;
                         const typename M::vec c = BufIO<T>::load_vec(rl, off);
                         typename M::vec v;
 #pragma unroll
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int off = colp(t) < n ? (M::row(q, r) * n + colp(t)) * SZ : kOOB;
+                        const int off = colp(t) < n ? (M::row(q, r) * ldc + colp(t)) * SZ : kOOB;
                         const T c = BufIO<T>::load1(rl, off);
                         BufIO<T>::store1((T)epilogue(alpha, (double)acc[rt][t][r], beta, (double)c), rc, off);
                     }
@@ -240,7 +242,8 @@ __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu
 // column tile, lane), four accumulator rows each.
 template <typename T>
 __global__ __launch_bounds__(256) void k_slab_reduce(const double *__restrict__ W, T *__restrict__ C, int64_t m,
-                                                     int n, int NT, int pg, int splitk, double alpha, double beta) {
+                                                     int n, int ldc, int NT, int pg, int splitk, double alpha,
+                                                     double beta) {
     typedef Mfma4<T> M;
     const int64_t ntile = (m + 15) >> 4;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,22 +263,23 @@ __global__ __launch_bounds__(256) void k_slab_reduce(const double *__restrict__ 
     for (int r = 0; r < 4; ++r) {
         const int64_t row = tile * 16 + M::row(q, r);
         if (row >= m) continue;
-        T *c = C + row * n + col;
+        T *c = C + row * ldc + col;
         *c = (T)epilogue(alpha, s[r], beta, beta != 0.0 ? (double)*c : 0.0);
     }
 }
 
 template <typename T, int NT, int RT, bool VEC, bool IL>
-hipError_t run_slab(const void *A, const void *Bf, void *C, double *W, int64_t m, int64_t n, int64_t k, int64_t nsl,
-                    double alpha, double beta, int splitk, int64_t nrb, int64_t grid, hipStream_t s) {
+hipError_t run_slab(const void *A, const void *Bf, void *C, double *W, int64_t m, int64_t n, int64_t k, int64_t lda,
+                    int64_t ldc, int64_t nsl, double alpha, double beta, int splitk, int64_t nrb, int64_t grid,
+                    hipStream_t s) {
     hipLaunchKernelGGL((k_slab<T, NT, RT, VEC, IL>), dim3((unsigned)grid), dim3(64 * kSlabWaves), 0, s,
                        static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C), W, m, (int)n,
-                       (int)k, nsl, alpha, beta, splitk, nrb);
+                       (int)k, (int)lda, (int)ldc, nsl, alpha, beta, splitk, nrb);
     return hipGetLastError();
 }
 
-typedef hipError_t (*SlabFn)(const void *, const void *, void *, double *, int64_t, int64_t, int64_t, int64_t, double,
-                             double, int, int64_t, int64_t, hipStream_t);
+typedef hipError_t (*SlabFn)(const void *, const void *, void *, double *, int64_t, int64_t, int64_t, int64_t,
+                             int64_t, int64_t, double, double, int, int64_t, int64_t, hipStream_t);
 struct SlabEntry {
     tsmm_dtype dt;
     int NT, RT, vec, il;
@@ -317,24 +321,24 @@ bool slab_variant_exists(tsmm_dtype dt, int NT, int RT, bool vec, bool il) {
 int slab_rows(int RT) { return kSlabWaves * RT * 16; }
 
 hipError_t launch_slab(tsmm_dtype dt, int NT, int RT, bool vec, bool il, const void *A, const void *Bf, void *C,
-                       double *W, int64_t m, int64_t n, int64_t k, int KCimg, double alpha, double beta, int splitk,
-                       int64_t grid, hipStream_t s) {
+                       double *W, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldc, int KCimg, double alpha,
+                       double beta, int splitk, int64_t grid, hipStream_t s) {
     const SlabEntry *e = find_slab(dt, NT, RT, vec, il);
     if (!e || KCimg % kSlabK != 0 || splitk < 1 || (splitk > 1 && !W)) return hipErrorInvalidValue;
     const int64_t nsl = KCimg / kSlabK;
     // LDS-DMA offsets are 32-bit: the image must stay below 4 GiB
     if ((int64_t)KCimg / 4 * NT * 64 * (dt == TSMM_F64 ? 8 : 4) >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
     const int64_t nrb = (m + slab_rows(RT) - 1) / slab_rows(RT);
-    hipError_t err = e->fn(A, Bf, C, W, m, n, k, nsl, alpha, beta, splitk, nrb, grid, s);
+    hipError_t err = e->fn(A, Bf, C, W, m, n, k, lda, ldc, nsl, alpha, beta, splitk, nrb, grid, s);
     if (err != hipSuccess || splitk == 1) return err;
     const int64_t threads = ((m + 15) >> 4) * NT * 64;
     const int pg = il ? 16 / (dt == TSMM_F64 ? 8 : 4) : 1;
     if (dt == TSMM_F64)
         hipLaunchKernelGGL(k_slab_reduce<double>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, W,
-                           static_cast<double *>(C), m, (int)n, NT, pg, splitk, alpha, beta);
+                           static_cast<double *>(C), m, (int)n, (int)ldc, NT, pg, splitk, alpha, beta);
     else
         hipLaunchKernelGGL(k_slab_reduce<float>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, W,
-                           static_cast<float *>(C), m, (int)n, NT, pg, splitk, alpha, beta);
+                           static_cast<float *>(C), m, (int)n, (int)ldc, NT, pg, splitk, alpha, beta);
     return hipGetLastError();
 }
 

@@ -52,9 +52,11 @@ __device__ __forceinline__ BlockMap block_map(int nsplit) {
 // A rows of row tiles t .. t+RT-1 into registers.  One buffer resource per
 // 16-row tile, sized to the tile's rows that exist, so rows beyond m read
 // 0; a lane whose columns lie beyond k (ragged k) reads through the offset
-// kOOB instead of branching.  voff0 is the lane's row offset j*k*sizeof(T).
+// kOOB instead of branching.  voff0 is the lane's row offset j*lda*sizeof(T)
+// (lda: the row stride of A in elements, >= k).
 template <typename T, int KC, int RT, bool VEC>
-__device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m, int k, bool kfull, int64_t t,
+__device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m, int k, int lda, bool kfull,
+                                              int64_t t,
                                               int voff0, int q, T (&a)[RT][KC / 4]) {
     typedef typename Mfma4<T>::vec vec_t;
     constexpr int VW = Mfma4<T>::VW;
@@ -69,7 +71,8 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((t + rt) * 16);
-        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, tile_rows(m, row0) * (int64_t)k * SZ);
+        const int64_t rows = tile_rows(m, row0);
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * lda, rows ? ((rows - 1) * lda + k) * SZ : 0);
         if constexpr (VEC) {
 #pragma unroll
             for (int p = 0; p < S / VW; ++p) {
@@ -95,7 +98,8 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 // epilogue's wait for them does not include the prefetch.
 template <typename T, int KC, int NT, int RT, bool VEC, bool IL, bool CPRE = true>
 __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__restrict__ Bsrc, int bstride,
-                                            T *__restrict__ C, int64_t m, int n, int k, bool kfull, double alpha,
+                                            T *__restrict__ C, int64_t m, int n, int k, int lda, int ldc,
+                                            bool kfull, double alpha,
                                             double beta, int col0, int64_t t, int64_t tnext, int voff0, int q,
                                             int lane, int j, const T (&a_use)[RT][KC / 4],
                                             T (&a_load)[RT][KC / 4]) {
@@ -108,9 +112,10 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((t + rt) * 16);
-        const int64_t bytes = (tile_rows(m, row0) * (int64_t)n - col0) * SZ;
-        rc[rt] = make_rsrc(C + row0 * n + col0, bytes);
-        rl[rt] = make_rsrc(C + row0 * n + col0, beta != 0.0 ? bytes : 0);
+        const int64_t rows = tile_rows(m, row0);
+        const int64_t bytes = rows ? ((rows - 1) * ldc + n - col0) * SZ : 0;
+        rc[rt] = make_rsrc(C + row0 * ldc + col0, bytes);
+        rl[rt] = make_rsrc(C + row0 * ldc + col0, beta != 0.0 ? bytes : 0);
     }
     // With interleaved columns (IL; tsmm_internal.h) tile tt of lane j is
     // column colp(tt) of the column group, a lane holds PG adjacent columns
@@ -123,12 +128,12 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
     // byte offset of accumulator element (tt, r): row M::row(q, r), column
     // colp(tt); kOOB for columns beyond n
     auto coff = [=](int tt, int r) {
-        return (col0 + colp(tt) < n) ? (M::row(q, r) * n + colp(tt)) * SZ : kOOB;
+        return (col0 + colp(tt) < n) ? (M::row(q, r) * ldc + colp(tt)) * SZ : kOOB;
     };
     // byte offset of the vector of group g (columns colp(PG*g) ..): whole
     // vectors lie inside or outside n when n % PG == 0
     auto voff = [=](int g, int r) {
-        return (col0 + colp(PG * g) < n) ? (M::row(q, r) * n + colp(PG * g)) * SZ : kOOB;
+        return (col0 + colp(PG * g) < n) ? (M::row(q, r) * ldc + colp(PG * g)) * SZ : kOOB;
     };
     T cv[RT][NT][4];
     if constexpr (CPRE) {
@@ -154,7 +159,7 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
 
     // past the last tile the resource holds no rows: the loads return 0
     // without touching memory
-    stream_load_a<T, KC, RT, VEC>(A, m, k, kfull, tnext, voff0, q, a_load);
+    stream_load_a<T, KC, RT, VEC>(A, m, k, lda, kfull, tnext, voff0, q, a_load);
     // all loads of this step are issued before any product: the scheduler
     // must not sink the prefetch below the products it is meant to overlap
     __builtin_amdgcn_sched_barrier(0);
@@ -225,8 +230,8 @@ template <typename T, int KC, int NT, int RT, bool VEC, bool IL>
 __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A,
                                                           const T *__restrict__ Bf,
                                                           T *__restrict__ C, int64_t m, int n,
-                                                          int k, double alpha, double beta,
-                                                          int nt_total, int nsplit) {
+                                                          int k, int lda, int ldc, double alpha,
+                                                          double beta, int nt_total, int nsplit) {
     typedef Mfma4<T> M;
     typedef typename M::vec vec_t;
     constexpr int VW = M::VW;
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A
     // whose column lies beyond k (ragged k) or n get the offset kOOB, which
     // is outside every tile, instead of a branch.
     const bool kfull = k == KC;
-    const int voff0 = j * k * SZ;
+    const int voff0 = j * lda * SZ;
 
     // Software pipeline, ping-pong over two register sets (the paper's
     // KERNEL_M1 / KERNEL_M2 alternation, Sec. IV-B.2): while one set feeds
@@ -273,31 +278,32 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A
     T a0[RT][S], a1[RT][S];
     int64_t t = gw * RT;
     if (t >= ntile) return;
-    stream_load_a<T, KC, RT, VEC>(A, m, k, kfull, t, voff0, q, a0);
+    stream_load_a<T, KC, RT, VEC>(A, m, k, lda, kfull, t, voff0, q, a0);
     const T *__restrict__ Bsrc = BLDS ? sB : Bf + bm.group * NT * 64;
     const int bstride = BLDS ? NT : nt_total;  // column tiles per k-step in Bsrc
     // Steps go in pairs with no branch between them (a branch would let the
     // compiler sink the prefetch past it); a pair's second step may lie past
     // the last tile, where its loads return 0 and its stores are dropped.
     for (; t < ntile; t += 2 * tstride) {
-        stream_step<T, KC, NT, RT, VEC, IL>(A, Bsrc, bstride, C, m, n, k, kfull, alpha, beta, col0, t,
+        stream_step<T, KC, NT, RT, VEC, IL>(A, Bsrc, bstride, C, m, n, k, lda, ldc, kfull, alpha, beta, col0, t,
                                             t + tstride, voff0, q, lane, j, a0, a1);
-        stream_step<T, KC, NT, RT, VEC, IL>(A, Bsrc, bstride, C, m, n, k, kfull, alpha, beta, col0, t + tstride,
+        stream_step<T, KC, NT, RT, VEC, IL>(A, Bsrc, bstride, C, m, n, k, lda, ldc, kfull, alpha, beta, col0,
+                                            t + tstride,
                                             t + 2 * tstride, voff0, q, lane, j, a1, a0);
     }
 }
 
 template <typename T, int KC, int NT, int RT, bool VEC, bool IL>
-hipError_t run_stream(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k,
-                      double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
+hipError_t run_stream(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k, int64_t lda,
+                      int64_t ldc, double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
                       hipStream_t s) {
     hipLaunchKernelGGL((k_stream<T, KC, NT, RT, VEC, IL>), dim3((unsigned)grid), dim3(block), 0, s,
                        static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C),
-                       m, (int)n, (int)k, alpha, beta, nt_total, nsplit);
+                       m, (int)n, (int)k, (int)lda, (int)ldc, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
 }
 
-typedef hipError_t (*StreamFn)(const void *, const void *, void *, int64_t, int64_t, int64_t,
+typedef hipError_t (*StreamFn)(const void *, const void *, void *, int64_t, int64_t, int64_t, int64_t, int64_t,
                                double, double, int64_t, int, int, int, hipStream_t);
 struct StreamEntry {
     int KC, NT, RT, vec, il;

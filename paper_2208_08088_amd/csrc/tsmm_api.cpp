@@ -1114,8 +1114,34 @@ tsmm_status ensure_workspace(tsmm_plan_s &p) {
 
 extern "C" {
 
+// Natural strides of a plan's operands: A's and C's row stride (op N,
+// op T) or column stride (column-major).
+void natural_ld(const tsmm_plan_s &p, int64_t *lda, int64_t *ldc) {
+    if (p.layout == TSMM_OP_N) {
+        *lda = p.k;
+        *ldc = p.n;
+    } else if (p.layout == TSMM_OP_T) {
+        *lda = p.m;
+        *ldc = p.n;
+    } else {
+        *lda = p.m;
+        *ldc = p.m;
+    }
+}
+
 tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, void *C, double alpha,
                          double beta) {
+    if (!p) {
+        g_err.clear();
+        return fail(TSMM_ERROR_INVALID_VALUE, "NULL plan or packed operand");
+    }
+    int64_t lda, ldc;
+    natural_ld(*p, &lda, &ldc);
+    return tsmm_execute_ld(p, A, lda, packed, C, ldc, alpha, beta);
+}
+
+tsmm_status tsmm_execute_ld(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_t packed, void *C, int64_t ldc,
+                            double alpha, double beta) {
     g_err.clear();
     if (!p || !packed) return fail(TSMM_ERROR_INVALID_VALUE, "NULL plan or packed operand");
     if (p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan: use tsmm_execute_batched");
@@ -1126,46 +1152,72 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
                     "plan (k=%" PRId64 " n=%" PRId64 " %s %s) vs packed (k=%" PRId64 " n=%" PRId64 " %s %s)", p->k,
                     p->n, dtype_name(p->dtype), mode_name(p->mode), packed->k, packed->n,
                     dtype_name(packed->dtype), mode_name(packed->mode));
+    int64_t nat_a, nat_c;
+    natural_ld(*p, &nat_a, &nat_c);
+    if (lda < std::max<int64_t>(1, nat_a) || ldc < std::max<int64_t>(1, nat_c))
+        return fail(TSMM_ERROR_INVALID_VALUE, "lda %" PRId64 " / ldc %" PRId64 " below the natural %" PRId64
+                                              " / %" PRId64, lda, ldc, nat_a, nat_c);
     if (p->m == 0 || p->n == 0) return TSMM_SUCCESS;
     if (!C) return fail(TSMM_ERROR_INVALID_VALUE, "C is NULL");
     if (alpha != 0.0 && p->k > 0 && !A) return fail(TSMM_ERROR_INVALID_VALUE, "A is NULL");
+    const bool strided = lda != nat_a || ldc != nat_c;
     const tsmm_dtype out_dt = p->dtype == TSMM_F64 ? TSMM_F64 : TSMM_F32;
     hipStream_t s = p->stream;
-    hipError_t e;
-    if (alpha == 0.0 || p->k == 0) {
-        e = launch_scale(out_dt, C, p->m * p->n, beta, s);
-        return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "scale launch");
-    }
     const char *base = static_cast<const char *>(packed->dev);
     // the caller's copy of B: row-major (op N), column-major (TSMM_COLMAJOR)
     const void *Brow = p->layout != TSMM_OP_T ? base + packed->L.off_rowmajor : nullptr;
+    // the any-shape kernel, with strides (column-major: row-major C^T = B^T A^T)
+    auto simple = [&](double a, int64_t kk) -> hipError_t {
+        if (p->layout == TSMM_OP_T)
+            return launch_simple_ld(p->dtype, true, A, lda, packed->ref, p->n, C, ldc, p->m, p->n, kk, a, beta, s);
+        if (p->layout == TSMM_COLMAJOR)
+            return launch_simple_ld(p->dtype, false, Brow, p->k, A, lda, C, ldc, p->n, p->m, kk, a, beta, s);
+        return launch_simple_ld(p->dtype, false, A, lda, Brow, p->n, C, ldc, p->m, p->n, kk, a, beta, s);
+    };
+    hipError_t e;
+    if (alpha == 0.0 || p->k == 0) {
+        if (strided) {  // C = beta*C through the strided any-shape kernel (no product terms)
+            e = simple(0.0, 0);
+        } else {
+            e = launch_scale(out_dt, C, p->m * p->n, beta, s);
+        }
+        return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "scale launch");
+    }
+    const int vw = 16 / elem_bytes(p->dtype);
+    const bool a16 = (reinterpret_cast<uintptr_t>(A) & 15) == 0, c16 = (reinterpret_cast<uintptr_t>(C) & 15) == 0;
+    // strides the 32-bit lane offsets of the row-major kernels cover
+    const bool ld32 = lda <= (1 << 24) && ldc <= (1 << 24);
     int kernel = p->tile.kernel;
-    if (kernel == TSMM_KERNEL_STREAM && ((p->vec && (reinterpret_cast<uintptr_t>(A) & 15)) ||
-                                         (frag4_pg(p->dtype, p->NT, p->n) > 1 && (reinterpret_cast<uintptr_t>(C) & 15))))
-        kernel = TSMM_KERNEL_SIMPLE;  // vector accesses need 16-byte aligned rows
+    if (kernel == TSMM_KERNEL_STREAM || kernel == TSMM_KERNEL_SLAB) {
+        const bool il = frag4_pg(p->dtype, p->NT, p->n) > 1;
+        if (!ld32 || (p->vec && (!a16 || lda % vw)) || (il && (!c16 || ldc % vw)))
+            kernel = TSMM_KERNEL_SIMPLE;  // vector accesses need 16-byte aligned rows
+    } else if (kernel == TSMM_KERNEL_COLMAJOR) {
+        if (!a16 || !c16 || lda % vw || ldc % vw) kernel = TSMM_KERNEL_SIMPLE;
+    } else if (kernel == TSMM_KERNEL_SPLITK || kernel == TSMM_KERNEL_VALU64) {
+        if (strided || (kernel == TSMM_KERNEL_VALU64 && (!a16 || !c16))) kernel = TSMM_KERNEL_SIMPLE;
+    } else if (kernel == TSMM_KERNEL_SPLITBF16 || kernel == TSMM_KERNEL_WIDE) {
+        const bool il = kernel == TSMM_KERNEL_WIDE || bfrag_pg(p->dtype, p->NT, p->n) > 1;
+        const bool needs_c16 = il;
+        if (strided || !a16 || (needs_c16 && !c16)) {
+            if (p->mode != TSMM_MODE_NATIVE)
+                return fail(TSMM_ERROR_INVALID_VALUE,
+                            "split-bf16 modes need natural strides and 16-byte aligned A (and C)");
+            kernel = TSMM_KERNEL_SIMPLE;
+        }
+    }
     switch (kernel) {
     case TSMM_KERNEL_STREAM:
         e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec,
-                          frag4_pg(p->dtype, p->NT, p->n) > 1, A,
-                          base + packed->L.off_frag, C, p->m, p->n, p->k, alpha, beta, p->grid, p->block, p->NT,
-                          p->tile.nsplit, s);
+                          frag4_pg(p->dtype, p->NT, p->n) > 1, A, base + packed->L.off_frag, C, p->m, p->n, p->k,
+                          lda, ldc, alpha, beta, p->grid, p->block, p->NT, p->tile.nsplit, s);
         break;
     case TSMM_KERNEL_VALU64:
-        if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(C)) & 15) {
-            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
-            break;
-        }
         e = launch_valu64(p->tile.rows_per_wave, static_cast<const double *>(A), static_cast<const double *>(Brow),
                           static_cast<double *>(C), p->m, p->n, p->k, alpha, beta, p->grid, s);
         break;
     case TSMM_KERNEL_SPLITBF16: {
         const bool il = bfrag_pg(p->dtype, p->NT, p->n) > 1;  // bfloat16 inputs only (NATIVE mode)
-        if ((reinterpret_cast<uintptr_t>(A) & 15) || (il && (reinterpret_cast<uintptr_t>(C) & 15))) {
-            if (p->mode != TSMM_MODE_NATIVE)
-                return fail(TSMM_ERROR_INVALID_VALUE, "split-bf16 modes need a 16-byte aligned A");
-            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
-            break;
-        }
         e = launch_splitbf16(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave,
                              split_products(p->dtype, p->mode), il, A, base + packed->L.off_frag,
                              p->mode != TSMM_MODE_NATIVE ? reinterpret_cast<const int32_t *>(base + packed->L.off_exps)
@@ -1174,12 +1226,6 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
         break;
     }
     case TSMM_KERNEL_WIDE:
-        if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(C)) & 15) {
-            if (p->mode != TSMM_MODE_NATIVE)
-                return fail(TSMM_ERROR_INVALID_VALUE, "split-bf16 modes need 16-byte aligned A and C");
-            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
-            break;
-        }
         if (!packed->L.wide_KC || packed->L.wide_KC != p->KC)
             return fail(TSMM_ERROR_SHAPE_MISMATCH, "packed operand has no image for the wide kernel");
         e = launch_wide(wide_products(*p), p->KC, p->NT, p->tile.rows_per_wave, A, base + packed->L.off_wide,
@@ -1188,27 +1234,19 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
                         C, p->m, p->n, p->k, alpha, beta, p->grid, s);
         break;
     case TSMM_KERNEL_COLMAJOR:
-        if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(C)) & 15) {
-            e = launch_simple_n(p->dtype, Brow, A, C, p->n, p->m, p->k, alpha, beta, s);  // C^T = B^T A^T
-            break;
-        }
         e = launch_colmajor(p->dtype, p->KC, p->NT / (p->tile.nsplit * p->tile.rows_per_wave), p->tile.rows_per_wave,
-                            A, base + packed->L.off_frag, C, p->m, p->n, p->k, alpha, beta, p->grid, p->NT,
+                            A, base + packed->L.off_frag, C, p->m, p->n, p->k, lda, ldc, alpha, beta, p->grid, p->NT,
                             p->tile.nsplit, s);
         break;
     case TSMM_KERNEL_SLAB: {
         const bool il = frag4_pg(p->dtype, p->NT, p->n) > 1;
-        if ((p->vec && (reinterpret_cast<uintptr_t>(A) & 15)) || (il && (reinterpret_cast<uintptr_t>(C) & 15))) {
-            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
-            break;
-        }
         if (packed->L.KC != p->KC || packed->L.NT != p->NT)
             return fail(TSMM_ERROR_SHAPE_MISMATCH, "packed operand has no image for the k-slab kernel");
         tsmm_status st = ensure_workspace(*p);
         if (st != TSMM_SUCCESS) return st;
         e = launch_slab(p->dtype, p->NT, p->tile.rows_per_wave, p->vec, il, A, base + packed->L.off_frag, C,
-                        static_cast<double *>(p->workspace), p->m, p->n, p->k, p->KC, alpha, beta, p->tile.splitk,
-                        p->grid, s);
+                        static_cast<double *>(p->workspace), p->m, p->n, p->k, lda, ldc, p->KC, alpha, beta,
+                        p->tile.splitk, p->grid, s);
         break;
     }
     case TSMM_KERNEL_SPLITK: {
@@ -1220,12 +1258,7 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
         break;
     }
     default:
-        if (p->layout == TSMM_OP_T)
-            e = launch_simple_t(p->dtype, A, packed->ref, C, p->m, p->n, p->k, alpha, beta, s);
-        else if (p->layout == TSMM_COLMAJOR)  // column-major C = A B is row-major C^T = B^T A^T
-            e = launch_simple_n(p->dtype, Brow, A, C, p->n, p->m, p->k, alpha, beta, s);
-        else
-            e = launch_simple_n(p->dtype, A, Brow, C, p->m, p->n, p->k, alpha, beta, s);
+        e = simple(alpha, p->k);
         break;
     }
     return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "kernel launch");

@@ -238,6 +238,11 @@ hipError_t launch_wide(int products, int KC, int NT, int RT, const void *A, cons
 hipError_t launch_scale(tsmm_dtype out_dt, void *C, int64_t count, double beta, hipStream_t s);
 
 // op N, any shape: one thread per output element, reads the row-major B.
+// Any shape with row strides (op N: A(i, l) at i*lda + l; trans: A(l, i) at
+// l*lda + i; B(l, j) at l*ldb + j; C(i, j) at i*ldc + j).
+hipError_t launch_simple_ld(tsmm_dtype dt, bool trans, const void *A, int64_t lda, const void *B, int64_t ldb,
+                            void *C, int64_t ldc, int64_t m, int64_t n, int64_t k, double alpha, double beta,
+                            hipStream_t s);
 hipError_t launch_simple_n(tsmm_dtype dt, const void *A, const void *B, void *C, int64_t m,
                            int64_t n, int64_t k, double alpha, double beta, hipStream_t s);
 // op T, any shape: one thread per output element.
@@ -248,9 +253,13 @@ hipError_t launch_simple_t(tsmm_dtype dt, const void *A, const void *B, void *C,
 // NT: column tiles per workgroup; nt_total = NT * nsplit column tiles of
 // the packed B.  With nsplit > 1, grid must be a multiple of 8 * nsplit.
 // il: the fragments interleave columns (pg > 1).
+// lda, ldc: row strides of A and C in elements (>= k, >= n); vector
+// k-slot mapping needs lda a multiple of the vector width, interleaved
+// columns ldc a multiple of it.
 hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il, const void *A,
-                         const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, double alpha,
-                         double beta, int64_t grid, int block, int nt_total, int nsplit, hipStream_t s);
+                         const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldc,
+                         double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
+                         hipStream_t s);
 bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il);
 
 // op N, split-bf16 (terms 2 or 3 of binary32 A and B; products 3 or 6) or
@@ -280,8 +289,8 @@ bool splitk_variant_exists(int MT, int NT, int RG);
 // (W: splitk * ceil(m/16) * NT * 64 * 4 binary64 partials when splitk > 1,
 // then an ordered second pass).
 hipError_t launch_slab(tsmm_dtype dt, int NT, int RT, bool vec, bool il, const void *A, const void *Bf, void *C,
-                       double *W, int64_t m, int64_t n, int64_t k, int KCimg, double alpha, double beta, int splitk,
-                       int64_t grid, hipStream_t s);
+                       double *W, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldc, int KCimg, double alpha,
+                       double beta, int splitk, int64_t grid, hipStream_t s);
 bool slab_variant_exists(tsmm_dtype dt, int NT, int RT, bool vec, bool il);
 int slab_rows(int RT);  // rows of one work item (four wavefronts of RT 16-row tiles)
 
@@ -289,9 +298,10 @@ int slab_rows(int RT);  // rows of one work item (four wavefronts of RT 16-row t
 // order, nt_total column tiles) times column-major A into column-major C;
 // m a multiple of the vector width, A and C 16-byte aligned.
 // NT column tiles per wavefront, NG column groups inside a workgroup.
+// lda, ldc: column strides of A and C (>= m, multiples of the vector width).
 hipError_t launch_colmajor(tsmm_dtype dt, int KC, int NT, int NG, const void *A, const void *Bf, void *C, int64_t m,
-                           int64_t n, int64_t k, double alpha, double beta, int64_t grid, int nt_total, int nsplit,
-                           hipStream_t s);
+                           int64_t n, int64_t k, int64_t lda, int64_t ldc, double alpha, double beta, int64_t grid,
+                           int nt_total, int nsplit, hipStream_t s);
 bool colmajor_variant_exists(tsmm_dtype dt, int KC, int NT, int NG);
 
 // Batched persistent launch: workgroup w runs work tiles

@@ -95,6 +95,7 @@ SIGNATURES = [
     ("tsmm_plan_describe", ctypes.c_int, [_VP, ctypes.c_char_p, _SZ]),
     ("tsmm_plan_destroy", None, [_VP]),
     ("tsmm_execute", ctypes.c_int, [_VP, _VP, _VP, _VP, _DBL, _DBL]),
+    ("tsmm_execute_ld", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _I64, _DBL, _DBL]),
     ("tsmm_plan_batched", ctypes.c_int, [_I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                          ctypes.POINTER(_I64), ctypes.c_int, _PVP]),
     ("tsmm_batched_bind", ctypes.c_int, [_VP, _PVP, _PVP, _PVP, ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)]),
@@ -316,21 +317,47 @@ def plan_with_caps(m, n, k, layout="N", dtype=torch.float64, compute_units=256, 
     return Plan(h.value, m, n, k, _LAYOUTS[layout], dt)
 
 
+def _leading_dim(t, name, dtype, shape, colmajor):
+    """The stride between rows (row-major) or columns (column-major) of a
+    2-D device tensor whose elements within a row (column) are adjacent."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    rows, cols = shape
+    inner, outer = (0, 1) if colmajor else (1, 0)
+    lines, width = (cols, rows) if colmajor else (rows, cols)
+    if width > 1 and t.stride(inner) != 1:
+        raise ValueError("%s: elements within a %s must be adjacent" % (name, "column" if colmajor else "row"))
+    if lines <= 1:
+        return max(1, width)
+    ld = t.stride(outer)
+    if ld < width:
+        raise ValueError("%s: stride %d below the %s length %d" % (name, ld, "column" if colmajor else "row", width))
+    return ld
+
+
 def execute(p: Plan, A: torch.Tensor, packed: Packed, C: torch.Tensor, alpha: float = 1.0,
             beta: float = 0.0) -> torch.Tensor:
-    """C = alpha*op(A)*B + beta*C in place on torch's current stream."""
+    """C = alpha*op(A)*B + beta*C in place on torch's current stream.  A and
+    C may be strided views (rows, or columns for layout "C", with adjacent
+    elements): their strides go to tsmm_execute_ld as leading dimensions."""
     in_dt = _TORCH_OF_DT[p.dtype]
     a_shape = (p.k, p.m) if p.layout == OP_T else (p.m, p.k)
     cm = p.layout == COLMAJOR
-    _need_cuda(A, "A", in_dt, a_shape, colmajor=cm)
-    _need_cuda(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n), colmajor=cm)
+    lda = _leading_dim(A, "A", in_dt, a_shape, cm)
+    ldc = _leading_dim(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n), cm)
     if packed.layout == OP_T and packed._keep is not None:
         _need_cuda(packed._keep, "B")
     p._ensure_workspace()
     lib = _lib()
     _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
-    _check(lib.tsmm_execute(p.handle, _ptr(A), packed.handle, _ptr(C), float(alpha), float(beta)),
-           "tsmm_execute")
+    _check(lib.tsmm_execute_ld(p.handle, _ptr(A), lda, packed.handle, _ptr(C), ldc, float(alpha), float(beta)),
+           "tsmm_execute_ld")
     return C
 
 
