@@ -331,6 +331,8 @@ def _leading_dim(t, name, dtype, shape, colmajor):
     rows, cols = shape
     inner, outer = (0, 1) if colmajor else (1, 0)
     lines, width = (cols, rows) if colmajor else (rows, cols)
+    if t.numel() == 0:  # nothing is read or written
+        return max(1, width)
     if width > 1 and t.stride(inner) != 1:
         raise ValueError("%s: elements within a %s must be adjacent" % (name, "column" if colmajor else "row"))
     if lines <= 1:
