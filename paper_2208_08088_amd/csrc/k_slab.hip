@@ -63,8 +63,9 @@ __device__ __forceinline__ void slab_load_a(const T *__restrict__ A, int64_t m, 
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((tile0 + rt) * 16);
-        const int64_t rows = tile_rows(m, row0);
-        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * lda, rows ? ((rows - 1) * lda + k) * SZ : 0);
+        // (rows - 1) * lda + k elements, negative (empty) when no row exists
+        const int rows = (int)tile_rows(m, row0);
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * lda, (int64_t)(rows * lda - (lda - k)) * SZ);
         // rows of a slab are 128 / 256 bytes read by two or four loads, which
         // share each line through the cache (default policy)
         int vo = j * lda * SZ;
@@ -206,8 +207,8 @@ __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int64_t row0 = uniform64((tile0 + rt) * 16);
-            const int64_t rows = tile_rows(m, row0);
-            const int64_t bytes = rows ? ((rows - 1) * ldc + n) * SZ : 0;
+            const int rows = (int)tile_rows(m, row0);
+            const int64_t bytes = (int64_t)(rows * ldc - (ldc - n)) * SZ;
             const __amdgpu_buffer_rsrc_t rc = make_rsrc(C + row0 * ldc, bytes);
             const __amdgpu_buffer_rsrc_t rl = make_rsrc(C + row0 * ldc, beta != 0.0 ? bytes : 0);
             if constexpr (IL) {

@@ -71,8 +71,10 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((t + rt) * 16);
-        const int64_t rows = tile_rows(m, row0);
-        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * lda, rows ? ((rows - 1) * lda + k) * SZ : 0);
+        // (rows - 1) * lda + k elements; negative (an empty resource) when
+        // no row exists, with no branch
+        const int rows = (int)tile_rows(m, row0);
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * lda, (int64_t)(rows * lda - (lda - k)) * SZ);
         if constexpr (VEC) {
 #pragma unroll
             for (int p = 0; p < S / VW; ++p) {
@@ -112,8 +114,8 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int64_t row0 = uniform64((t + rt) * 16);
-        const int64_t rows = tile_rows(m, row0);
-        const int64_t bytes = rows ? ((rows - 1) * ldc + n - col0) * SZ : 0;
+        const int rows = (int)tile_rows(m, row0);
+        const int64_t bytes = (int64_t)(rows * ldc - (ldc - n + col0)) * SZ;
         rc[rt] = make_rsrc(C + row0 * ldc + col0, bytes);
         rl[rt] = make_rsrc(C + row0 * ldc + col0, beta != 0.0 ? bytes : 0);
     }
