@@ -359,6 +359,48 @@ def extras_colmajor(torch, T, I, steps, warmup):
     return out
 
 
+def extras_packed_a(torch, T, I, steps, warmup):
+    """A packed once and reused (PACKA, alpha folded in): binary32 in the
+    split-bf16 modes, beta = 0, fresh A (split in registers on every call,
+    the plan's own kernel) against the pre-split A of tsmm_pack_a (the
+    split-bf16 kernel loading the terms).  Bytes per call: fresh 4*m*k +
+    4*m*n, packed 2*terms*m*k + 4*m*n."""
+    out = {}
+    for m, k, n in ((M_ROWS, 32, 32), (M_ROWS, 128, 128), (1 << 24, 256, 256)):
+        A = I.device_uniform((m, k), I.BASE_SEED, 500 + k, torch.float32)
+        B = I.device_uniform((k, n), I.BASE_SEED, 510 + k, torch.float32)
+        C = torch.empty((m, n), dtype=torch.float32, device="cuda")
+        for mode, terms in (("bf16x3", 2), ("bf16x6", 3)):
+            p = T.plan(m, n, k, "N", torch.float32).set_mode(mode)
+            pk = T.pack(B, "N", mode)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            pa = T.pack_a(A, mode, 1.0)
+            torch.cuda.synchronize()
+            pack_ms = (time.perf_counter() - w0) * 1e3
+            row = dict(fresh_plan=p.describe(), pack_ms=pack_ms, packed_bytes=pa.nbytes())
+            for key, fn in (("fresh", lambda: T.execute(p, A, pk, C, 1.0, 0.0)),
+                            ("packed", lambda: T.execute_packed_a(p, pa, pk, C, 0.0))):
+                for _ in range(warmup):
+                    fn()
+                timer = Timer(torch)
+                for _ in range(steps):
+                    e0 = timer.start()
+                    fn()
+                    timer.stop(key, e0)
+                ms = float(np.median(timer.per_key_ms()[key]))
+                byt = (4 if key == "fresh" else 2 * terms) * m * k + 4 * m * n
+                row[key + "_us"] = ms * 1e3
+                row[key + "_GB_s"] = byt / ms / 1e6
+                row[key + "_hbm_frac"] = byt / ms / 1e6 / HBM_PEAK_GBS
+            row["speedup"] = row["fresh_us"] / row["packed_us"]
+            out["%s_m2p%d_k%d" % (mode, m.bit_length() - 1, k)] = row
+            del pa, pk
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
+
+
 def extras_tune(torch, T, I, steps, warmup):
     """The runtime evaluator on a shape class the tile table does not hold
     (binary64, m = 2^22, k = 24, n = 48): the built-in default tile against
@@ -614,10 +656,12 @@ def main():
         log("runtime evaluator done")
         colm = extras_colmajor(torch, T, I, args.steps, args.warmup)
         log("column-major done")
+        pka = extras_packed_a(torch, T, I, args.steps, args.warmup)
+        log("packed A done")
         del keep_t
         result["extras"] = dict(small_4096x16=small, op_t_splitk=opt, precision_m2p24_k256=prec,
                                 batched_512=bat, square_25600=sq, runtime_evaluator=tune,
-                                colmajor_m2p23=colm)
+                                colmajor_m2p23=colm, packed_a_reuse=pka)
 
     if not args.no_cpu_baseline and not args.only:
         result["cpu_baseline"] = cpu_baseline(torch, I, cases, keep_s)

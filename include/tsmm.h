@@ -16,10 +16,15 @@
  *                 written by the install-time autotuner (the runtime stage
  *                 of Sec. III: cache-blocked designer, multi-thread
  *                 optimizer, performance evaluator; Eqs. (2)-(3));
- *   tsmm_execute  runs the multiply (the COMPUTE step of Algorithm 1).
+ *   tsmm_execute  runs the multiply (the COMPUTE step of Algorithm 1);
+ *   tsmm_pack_a / tsmm_execute_packed_a  pack a big operand that is reused
+ *                 across calls (the PACKA step, alpha folded in) and
+ *                 multiply with it.
  *
  * Conventions shared by every entry point:
- *   - Matrices are dense, row-major and contiguous (no leading dimensions).
+ *   - Matrices are dense and row-major (TSMM_COLMAJOR: column-major);
+ *     tsmm_execute_ld takes leading dimensions of A and C, every other
+ *     entry point the natural ones.
  *   - op N:  A is m x k, B is k x n, C is m x n:      C = a*A*B   + b*C.
  *     op T:  A is k x m, B is k x n, C is m x n:      C = a*A^T*B + b*C,
  *            the reduction shape over a long shared dimension k.
@@ -230,6 +235,32 @@ tsmm_status tsmm_packed_split_planes(tsmm_packed_t packed, void *planes_out,
 
 void tsmm_packed_destroy(tsmm_packed_t packed);
 
+/* Pack the big operand A once, for a caller that multiplies the same A by
+ * many B (Algorithm 1, PACKA: A is scaled by alpha as it is packed; the
+ * reused-operand case of Sec. II-C, e.g. weights against im2col panels).
+ *   A       device pointer, row-major m x k with row stride lda (>= k), of
+ *           `dtype` (binary64 or binary32).  Read asynchronously on `stream`.
+ *   mode    NATIVE: the handle holds RN(alpha*a) in the input type (product
+ *           in binary64), dense row-major; executes read it as a fresh A
+ *           with alpha = 1, so nothing changes per call but the scaling.
+ *           BF16X3 / BF16X6 (binary32, k <= 256): the handle holds
+ *           RN32(alpha*a) already split into its 2 / 3 bfloat16 terms (the
+ *           residual split of those modes), one plane per term, rows padded
+ *           to a multiple of 8 and the row count to a multiple of 16 with
+ *           zeros: executes load the terms instead of splitting A on every
+ *           call (2 / 3 bytes of traffic per term and element instead of 4).
+ *   alpha   folded into the handle; alpha = 0 makes executes compute
+ *           beta*C without reading A or B (reference-BLAS convention).
+ *   out     receives the handle (owns device memory; free it with
+ *           tsmm_packed_destroy after the last execute that uses it).
+ *           tsmm_packed_bytes reports its size; it cannot be unpacked and is
+ *           refused where a packed B is expected.
+ * Errors: INVALID_VALUE (NULL out, NULL A with m*k > 0, negative sizes,
+ * lda < k, bad enum), NOT_SUPPORTED (bfloat16 A, split mode with a type
+ * other than binary32 or k > 256), OUT_OF_MEMORY, HIP. */
+tsmm_status tsmm_pack_a(const void *A, int64_t m, int64_t k, int64_t lda, tsmm_dtype dtype,
+                        tsmm_mode mode, double alpha, void *stream, tsmm_packed_t *out);
+
 /* -------------------------------------------------------------------- plan */
 
 /* Build an execution plan for one shape (the runtime stage of Sec. III):
@@ -342,6 +373,23 @@ tsmm_status tsmm_execute(tsmm_plan_t plan, const void *A, tsmm_packed_t packed,
  * ones or, in the split-bf16 modes, other than them. */
 tsmm_status tsmm_execute_ld(tsmm_plan_t plan, const void *A, int64_t lda, tsmm_packed_t packed,
                             void *C, int64_t ldc, double alpha, double beta);
+
+/* C = A_packed * B + beta*C with A from tsmm_pack_a (alpha was folded in
+ * there): the COMPUTE step of Algorithm 1 on two packed operands.  The plan
+ * is an op N plan of the same m, k, dtype and mode as packed_a; packed is
+ * B packed for that plan; C is row-major m x n (natural stride).
+ * NATIVE plans run their own kernel on the packed copy of A.  Split-bf16
+ * plans run the split-bf16 kernel on the pre-split terms (the plan's tile
+ * when the plan uses that kernel, else its default tile, with fewer rows
+ * per wavefront or more column groups where a variant needs them); for
+ * alpha = 1 the result is bitwise that of tsmm_execute on the same
+ * geometry, since the terms are the same values.
+ * Asynchronous on the plan's stream.
+ * Errors: INVALID_VALUE (NULL argument, packed_a not from tsmm_pack_a,
+ * packed not a packed B, C not 4-byte aligned), SHAPE_MISMATCH (plan and
+ * handles disagree), NOT_SUPPORTED (not an op N plan), HIP. */
+tsmm_status tsmm_execute_packed_a(tsmm_plan_t plan, tsmm_packed_t packed_a, tsmm_packed_t packed,
+                                  void *C, double beta);
 
 /* ----------------------------------------------------------------- batched */
 

@@ -15,7 +15,9 @@ builds and loads that library and marshals numpy arrays into it:
   dimension);
 * :func:`split_bf16` -- binary32 -> bfloat16 residual split, bit-level
   round-to-nearest-even;
-* :func:`column_scale_exp` -- power-of-two exponent per column.
+* :func:`column_scale_exp` -- power-of-two exponent per column;
+* :func:`pack_a` -- Algorithm 1's PACKA scaling of A by alpha, followed (in
+  the split-bf16 modes) by the residual split.
 
 Floating inputs of narrower types are widened to binary64 exactly before
 the call (bfloat16 values arrive as their uint16 bit patterns).
@@ -134,6 +136,28 @@ def split_bf16(x, terms: int) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_split_bf16 rejected its arguments")
     return out
+
+
+def pack_a(A, alpha: float, terms: int = 0) -> np.ndarray:
+    """Algorithm 1, PACKA: A scaled by alpha as it is packed.
+
+    Each product alpha*a is taken in binary64 and rounded once to A's type
+    (binary64 or binary32).  terms = 0 returns the scaled matrix; terms = 2
+    or 3 (binary32 A, the split-bf16 modes) returns its bfloat16 residual
+    split: uint16 planes of shape (terms,) + A.shape.
+    """
+    A = np.asarray(A)
+    if A.dtype == np.float64:
+        scaled = np.float64(alpha) * A
+    elif A.dtype == np.float32:
+        scaled = (np.float64(alpha) * A.astype(np.float64)).astype(np.float32)
+    else:
+        raise TypeError("pack_a takes binary64 or binary32 A")
+    if terms == 0:
+        return scaled
+    if A.dtype != np.float32:
+        raise TypeError("the split takes binary32 A")
+    return split_bf16(scaled, terms)
 
 
 def column_scale_exp(B) -> np.ndarray:

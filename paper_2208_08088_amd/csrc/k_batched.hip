@@ -69,7 +69,7 @@ __device__ __forceinline__ void segment_bf16(const BatchDesc &d, int64_t row_a, 
     const int64_t tstride = (int64_t)kBatchWaves * RT;
     int64_t t = (row_a >> 4) + (int64_t)wave * RT;
     if (t >= tend) return;
-    RawA<false, RT, KC / 32> x0, x1;
+    RawA<0, RT, KC / 32> x0, x1;
     bf16_load_step<uint16_t, KC, RT, 1, VEC>(A, row_b, k, t, j, q, x0);
     for (; t < tend; t += 2 * tstride) {
         bf16_step<uint16_t, KC, NT, RT, 1, VEC, IL, CPRE>(A, sB, NT, nullptr, C, row_b, n, k, d.alpha, d.beta, 0,

@@ -76,60 +76,95 @@ __device__ __forceinline__ void split8(const float (&x)[8], u16x8 (&t)[TERMS]) {
     }
 }
 
-template <bool F32IN, int RT, int NCH> struct RawA;
-template <int RT, int NCH> struct RawA<true, RT, NCH> {
+// How a kernel receives A: 0 bfloat16 values (one term), 1 binary32
+// values split in registers, 2 or 3: A split ahead of time into that many
+// bfloat16 planes (packed A, presplit layout of tsmm_internal.h; uint16_t
+// with PROD > 1).
+template <typename TA, int PROD> constexpr int a_kind() {
+    return PROD == 1 ? 0 : (sizeof(TA) == 4 ? 1 : (PROD == 3 ? 2 : 3));
+}
+template <int KIND, int RT, int NCH> struct RawA {  // pre-split planes
+    u16x8 v[RT][NCH][KIND];
+};
+template <int RT, int NCH> struct RawA<1, RT, NCH> {
     float v[RT][NCH][8];
 };
-template <int RT, int NCH> struct RawA<false, RT, NCH> {
+template <int RT, int NCH> struct RawA<0, RT, NCH> {
     u16x8 v[RT][NCH];
 };
 
-// A of row tiles t .. t+RT-1: binary32 values (split modes) or bf16
-// vectors.  Vector loads go through one buffer resource per 16-row tile
-// sized to the rows that exist (rows beyond m read 0); columns beyond k
-// read through kOOB.
+// A of row tiles t .. t+RT-1: binary32 values (split modes), bf16 vectors,
+// or the vectors of every plane of a pre-split A.  Vector loads go through
+// one buffer resource per 16-row tile sized to the rows that exist (rows
+// beyond m read 0); columns beyond k read through kOOB.
 template <typename TA, int KC, int RT, int PROD, bool VEC>
 __device__ __forceinline__ void bf16_load_step(const TA *__restrict__ A, int64_t m, int k, int64_t t, int j, int q,
-                                               RawA<(PROD > 1), RT, KC / 32> &x) {
+                                               RawA<a_kind<TA, PROD>(), RT, KC / 32> &x) {
     constexpr int NCH = KC / 32;
-    constexpr bool F32IN = PROD > 1;
+    constexpr int KIND = a_kind<TA, PROD>();
+    constexpr bool F32IN = KIND == 1;
     constexpr int SZ = F32IN ? 4 : 2;
-    // rows of 1 KiB and more: default cache policy (see stream_load_a)
-    constexpr int AUX = KC * SZ >= 1024 ? 0 : 2;
+    if constexpr (KIND >= 2) {
+        static_assert(VEC, "pre-split rows are whole vectors");
+        // plane p of tile row0: 16 padded rows (zeros past m), none past
+        // the last tile
+        const int ld = (int)presplit_ld(k);
+        const int64_t pstride = presplit_rows(m) * ld;
+        const int voff0 = j * ld * 2;
+        constexpr int AUX = KC * 2 >= 1024 ? 0 : 2;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-        const int64_t row0 = uniform64((t + rt) * 16);
-        if constexpr (VEC) {
-            const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, tile_rows(m, row0) * (int64_t)k * SZ);
-            const int voff0 = j * k * SZ;
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t row0 = uniform64((t + rt) * 16);
+            const int bytes = row0 < m ? 16 * ld * 2 : 0;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int col = 32 * c + 8 * q;
-                if constexpr (F32IN) {
-                    const f4v v0 = BufIO<float>::load_vec<AUX>(ra, col < k ? voff0 + col * SZ : kOOB);
-                    const f4v v1 = BufIO<float>::load_vec<AUX>(ra, col + 4 < k ? voff0 + (col + 4) * SZ : kOOB);
+            for (int p = 0; p < KIND; ++p) {
+                const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + p * pstride + row0 * ld, bytes);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        x.v[rt][c][e] = v0[e];
-                        x.v[rt][c][4 + e] = v1[e];
-                    }
-                } else {
-                    x.v[rt][c] = __builtin_bit_cast(
-                        u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, col < k ? voff0 + col * SZ : kOOB, 0, AUX));
+                for (int c = 0; c < NCH; ++c) {
+                    const int col = 32 * c + 8 * q;
+                    x.v[rt][c][p] = __builtin_bit_cast(
+                        u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, col < k ? voff0 + col * 2 : kOOB, 0, AUX));
                 }
             }
-        } else {
-            const int64_t row = row0 + j;
-            const bool rok = row < m;
+        }
+    } else {
+        // rows of 1 KiB and more: default cache policy (see stream_load_a)
+        constexpr int AUX = KC * SZ >= 1024 ? 0 : 2;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int col = 32 * c + 8 * q;
-                if constexpr (F32IN)
-                    load_a8<float, false>(reinterpret_cast<const float *>(A) + row * (int64_t)k, col, k, rok,
-                                          x.v[rt][c]);
-                else
-                    x.v[rt][c] = load_a8_bf16<false>(reinterpret_cast<const uint16_t *>(A) + row * (int64_t)k, col, k,
-                                                     rok);
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t row0 = uniform64((t + rt) * 16);
+            if constexpr (VEC) {
+                const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, tile_rows(m, row0) * (int64_t)k * SZ);
+                const int voff0 = j * k * SZ;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int col = 32 * c + 8 * q;
+                    if constexpr (F32IN) {
+                        const f4v v0 = BufIO<float>::load_vec<AUX>(ra, col < k ? voff0 + col * SZ : kOOB);
+                        const f4v v1 = BufIO<float>::load_vec<AUX>(ra, col + 4 < k ? voff0 + (col + 4) * SZ : kOOB);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            x.v[rt][c][e] = v0[e];
+                            x.v[rt][c][4 + e] = v1[e];
+                        }
+                    } else {
+                        x.v[rt][c] = __builtin_bit_cast(
+                            u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, col < k ? voff0 + col * SZ : kOOB, 0, AUX));
+                    }
+                }
+            } else {
+                const int64_t row = row0 + j;
+                const bool rok = row < m;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int col = 32 * c + 8 * q;
+                    if constexpr (F32IN)
+                        load_a8<float, false>(reinterpret_cast<const float *>(A) + row * (int64_t)k, col, k, rok,
+                                              x.v[rt][c]);
+                    else
+                        x.v[rt][c] = load_a8_bf16<false>(reinterpret_cast<const uint16_t *>(A) + row * (int64_t)k, col, k,
+                                                         rok);
+                }
             }
         }
     }
@@ -141,12 +176,13 @@ template <typename TA, int KC, int NT, int RT, int PROD, bool VEC, bool IL = fal
 __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 *__restrict__ Bsrc, int bstride,
                                           const int32_t *__restrict__ exps, float *__restrict__ C, int64_t m, int n,
                                           int k, double alpha, double beta, int col0, int64_t t, int64_t tnext,
-                                          int j, int q, int lane, const RawA<(PROD > 1), RT, KC / 32> &x_use,
-                                          RawA<(PROD > 1), RT, KC / 32> &x_load) {
+                                          int j, int q, int lane,
+                                          const RawA<a_kind<TA, PROD>(), RT, KC / 32> &x_use,
+                                          RawA<a_kind<TA, PROD>(), RT, KC / 32> &x_load) {
     constexpr int TERMS = PROD == 1 ? 1 : (PROD == 3 ? 2 : 3);
     constexpr int NCH = KC / 32;
     constexpr bool TWO_ACC = PROD > 1;
-    constexpr bool F32IN = PROD > 1;
+    constexpr int KIND = a_kind<TA, PROD>();
 
     __amdgpu_buffer_rsrc_t rc[RT], rl[RT];
 #pragma unroll
@@ -210,8 +246,14 @@ __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 
         u16x8 at[RT][TERMS];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-            if constexpr (F32IN) split8<TERMS>(x_use.v[rt][c], at[rt]);
-            else at[rt][0] = x_use.v[rt][c];
+            if constexpr (KIND == 1) {
+                split8<TERMS>(x_use.v[rt][c], at[rt]);
+            } else if constexpr (KIND == 0) {
+                at[rt][0] = x_use.v[rt][c];
+            } else {
+#pragma unroll
+                for (int p = 0; p < TERMS; ++p) at[rt][p] = x_use.v[rt][c][p];
+            }
         }
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) {
@@ -288,8 +330,6 @@ __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__
     constexpr int NCH = KC / 32;
     constexpr int FRAGV = NCH * NT * TERMS * 64;  // 16-byte vectors per workgroup
     constexpr bool BLDS = FRAGV * 16 <= kBf16LdsBudget;
-    constexpr bool TWO_ACC = PROD > 1;
-    constexpr bool F32IN = PROD > 1;
 
     int group = 0;
     int64_t rb = blockIdx.x, nrb = gridDim.x;
@@ -324,7 +364,7 @@ __global__ __launch_bounds__(kBf16Block) void k_splitbf16(const TA *__restrict__
     // Ping-pong over two register sets, steps in pairs with no branch between
     // them (a pair's second step may lie past the last tile: its loads read
     // 0 and its stores are dropped).
-    RawA<F32IN, RT, NCH> x0, x1;
+    RawA<a_kind<TA, PROD>(), RT, NCH> x0, x1;
     int64_t t = gw * RT;
     if (t >= ntile) return;
     bf16_load_step<TA, KC, RT, PROD, VEC>(A, m, k, t, j, q, x0);

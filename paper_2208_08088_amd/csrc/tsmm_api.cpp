@@ -911,6 +911,7 @@ tsmm_status tsmm_packed_bytes(tsmm_packed_t p, size_t *bytes) {
 tsmm_status tsmm_unpack(tsmm_packed_t p, void *B_out, void *stream) {
     g_err.clear();
     if (!p) return fail(TSMM_ERROR_INVALID_VALUE, "packed is NULL");
+    if (p->is_a) return fail(TSMM_ERROR_NOT_SUPPORTED, "packed A handles are not unpacked");
     if (p->layout == TSMM_OP_T) return fail(TSMM_ERROR_NOT_SUPPORTED, "op T handles hold no copy of B");
     if (p->k * p->n == 0) return TSMM_SUCCESS;
     if (!B_out) return fail(TSMM_ERROR_INVALID_VALUE, "B_out is NULL");
@@ -929,7 +930,8 @@ tsmm_status tsmm_unpack(tsmm_packed_t p, void *B_out, void *stream) {
 tsmm_status tsmm_packed_split_planes(tsmm_packed_t p, void *planes_out, void *exps_out, void *stream) {
     g_err.clear();
     if (!p) return fail(TSMM_ERROR_INVALID_VALUE, "packed is NULL");
-    if (p->mode == TSMM_MODE_NATIVE) return fail(TSMM_ERROR_NOT_SUPPORTED, "not a split-mode handle");
+    if (p->is_a || p->mode == TSMM_MODE_NATIVE)
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "not a split-mode packed B handle");
     if (p->k * p->n == 0) return TSMM_SUCCESS;
     if (!planes_out || !exps_out) return fail(TSMM_ERROR_INVALID_VALUE, "NULL output");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -945,6 +947,56 @@ void tsmm_packed_destroy(tsmm_packed_t p) {
     if (!p) return;
     if (p->dev) (void)hipFree(p->dev);
     delete p;
+}
+
+tsmm_status tsmm_pack_a(const void *A, int64_t m, int64_t k, int64_t lda, tsmm_dtype dtype, tsmm_mode mode,
+                        double alpha, void *stream, tsmm_packed_t *out) {
+    g_err.clear();
+    if (!out) return fail(TSMM_ERROR_INVALID_VALUE, "out is NULL");
+    *out = nullptr;
+    if (m < 0 || k < 0) return fail(TSMM_ERROR_INVALID_VALUE, "negative size");
+    if (!valid_dtype(dtype)) return fail(TSMM_ERROR_INVALID_VALUE, "bad dtype %d", (int)dtype);
+    if (!valid_mode(mode)) return fail(TSMM_ERROR_INVALID_VALUE, "bad mode %d", (int)mode);
+    if (dtype == TSMM_BF16) return fail(TSMM_ERROR_NOT_SUPPORTED, "bfloat16 A is read as it is; nothing to pack");
+    if (mode != TSMM_MODE_NATIVE && dtype != TSMM_F32)
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes take binary32 operands");
+    if (mode != TSMM_MODE_NATIVE && k > kMaxKC)
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes need k <= %d", kMaxKC);
+    if (m > INT32_MAX * (int64_t)16 || k > INT32_MAX) return fail(TSMM_ERROR_NOT_SUPPORTED, "A too large");
+    if (lda < std::max<int64_t>(1, k)) return fail(TSMM_ERROR_INVALID_VALUE, "lda %" PRId64 " < k", lda);
+    if (m * k > 0 && !A) return fail(TSMM_ERROR_INVALID_VALUE, "A is NULL");
+
+    std::unique_ptr<tsmm_packed_s> P(new (std::nothrow) tsmm_packed_s());
+    if (!P) return fail(TSMM_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    P->is_a = true;
+    P->m = m;
+    P->k = k;
+    P->n = 0;
+    P->layout = TSMM_OP_N;
+    P->dtype = dtype;
+    P->mode = mode;
+    P->alpha = alpha;
+    const int terms = mode == TSMM_MODE_NATIVE ? 0 : split_terms(dtype, mode);
+    P->L.terms = terms;
+    if (m == 0 || k == 0) {  // nothing to hold
+        *out = P.release();
+        return TSMM_SUCCESS;
+    }
+    P->L.bytes = terms > 0 ? (size_t)terms * presplit_rows(m) * presplit_ld(k) * 2 : (size_t)m * k * elem_bytes(dtype);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(TSMM_ERROR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+    P->device = dev;
+    e = hipMalloc(&P->dev, P->L.bytes);
+    if (e != hipSuccess)
+        return fail(TSMM_ERROR_OUT_OF_MEMORY, "hipMalloc(%zu): %s", P->L.bytes, hipGetErrorString(e));
+    e = launch_pack_a(dtype, terms, A, lda, P->dev, m, k, alpha, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        (void)hipFree(P->dev);
+        return hip_fail(e, "pack A");
+    }
+    *out = P.release();
+    return TSMM_SUCCESS;
 }
 
 // ------------------------------------------------------------------ plan
@@ -1116,6 +1168,7 @@ extern "C" {
 
 // Natural strides of a plan's operands: A's and C's row stride (op N,
 // op T) or column stride (column-major).
+// Natural strides (at least 1, as in BLAS, also for empty matrices).
 void natural_ld(const tsmm_plan_s &p, int64_t *lda, int64_t *ldc) {
     if (p.layout == TSMM_OP_N) {
         *lda = p.k;
@@ -1127,6 +1180,8 @@ void natural_ld(const tsmm_plan_s &p, int64_t *lda, int64_t *ldc) {
         *lda = p.m;
         *ldc = p.m;
     }
+    *lda = std::max<int64_t>(1, *lda);
+    *ldc = std::max<int64_t>(1, *ldc);
 }
 
 tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, void *C, double alpha,
@@ -1146,6 +1201,7 @@ tsmm_status tsmm_execute_ld(tsmm_plan_t p, const void *A, int64_t lda, tsmm_pack
     if (!p || !packed) return fail(TSMM_ERROR_INVALID_VALUE, "NULL plan or packed operand");
     if (p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan: use tsmm_execute_batched");
     if (p->device < 0) return fail(TSMM_ERROR_NO_DEVICE, "plan was built for explicit caps, not a device");
+    if (packed->is_a) return fail(TSMM_ERROR_INVALID_VALUE, "a packed A handle was passed as the packed B operand");
     if (packed->k != p->k || packed->n != p->n || packed->dtype != p->dtype || packed->layout != p->layout ||
         packed->mode != p->mode)
         return fail(TSMM_ERROR_SHAPE_MISMATCH,
@@ -1154,7 +1210,7 @@ tsmm_status tsmm_execute_ld(tsmm_plan_t p, const void *A, int64_t lda, tsmm_pack
                     dtype_name(packed->dtype), mode_name(packed->mode));
     int64_t nat_a, nat_c;
     natural_ld(*p, &nat_a, &nat_c);
-    if (lda < std::max<int64_t>(1, nat_a) || ldc < std::max<int64_t>(1, nat_c))
+    if (lda < nat_a || ldc < nat_c)
         return fail(TSMM_ERROR_INVALID_VALUE, "lda %" PRId64 " / ldc %" PRId64 " below the natural %" PRId64
                                               " / %" PRId64, lda, ldc, nat_a, nat_c);
     if (p->m == 0 || p->n == 0) return TSMM_SUCCESS;
@@ -1315,6 +1371,67 @@ std::vector<tsmm_tile> tune_candidates(const tsmm_plan_s &p) {
 }  // namespace
 
 extern "C" {
+
+// The split-bf16 geometry that runs a pre-split A for plan p: the plan's
+// own tile when it runs the split-bf16 kernel, else that kernel's default;
+// rows per wavefront halve, then column groups double, until a pre-split
+// variant exists.
+static tsmm_status presplit_geometry(const tsmm_plan_s &p, tsmm_plan_s &q) {
+    const int KC = kclass32(p.k), NT = ntclass(p.n), prod = split_products(p.dtype, p.mode);
+    if (!KC || !NT) return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes need k <= %d and n <= 256", kMaxKC);
+    tsmm_tile t = p.tile.kernel == TSMM_KERNEL_SPLITBF16 ? p.tile : default_tile(p, TSMM_KERNEL_SPLITBF16);
+    t.kernel = TSMM_KERNEL_SPLITBF16;
+    t.nsplit = std::max(1, std::min(t.nsplit, NT));
+    for (;;) {
+        const int NTs = NT / t.nsplit;
+        int rt = std::max(1, t.rows_per_wave);
+        while (rt > 1 && !splitbf16_presplit_exists(prod, KC, NTs, rt)) rt /= 2;
+        if (splitbf16_presplit_exists(prod, KC, NTs, rt)) {
+            t.rows_per_wave = rt;
+            break;
+        }
+        if (t.nsplit * 2 > NT) return fail(TSMM_ERROR_NOT_SUPPORTED, "no pre-split kernel for KC=%d NT=%d", KC, NT);
+        t.nsplit *= 2;
+    }
+    q = p;
+    q.workspace = nullptr;
+    q.owns_workspace = false;
+    return apply_tile(q, t);
+}
+
+tsmm_status tsmm_execute_packed_a(tsmm_plan_t p, tsmm_packed_t packed_a, tsmm_packed_t packed, void *C,
+                                  double beta) {
+    g_err.clear();
+    if (!p || !packed_a || !packed) return fail(TSMM_ERROR_INVALID_VALUE, "NULL plan or packed operand");
+    if (!packed_a->is_a) return fail(TSMM_ERROR_INVALID_VALUE, "packed_a is not a packed A handle");
+    if (p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan: use tsmm_execute_batched");
+    if (p->layout != TSMM_OP_N) return fail(TSMM_ERROR_NOT_SUPPORTED, "packed A serves op N plans");
+    if (packed_a->m != p->m || packed_a->k != p->k || packed_a->dtype != p->dtype || packed_a->mode != p->mode)
+        return fail(TSMM_ERROR_SHAPE_MISMATCH,
+                    "plan (m=%" PRId64 " k=%" PRId64 " %s %s) vs packed A (m=%" PRId64 " k=%" PRId64 " %s %s)", p->m,
+                    p->k, dtype_name(p->dtype), mode_name(p->mode), packed_a->m, packed_a->k,
+                    dtype_name(packed_a->dtype), mode_name(packed_a->mode));
+    // alpha = 0 at pack time: reference-BLAS convention, neither A nor B is read
+    const double alpha = packed_a->alpha == 0.0 ? 0.0 : 1.0;
+    if (p->mode == TSMM_MODE_NATIVE || alpha == 0.0 || p->k == 0 || p->m == 0 || p->n == 0)
+        return tsmm_execute(p, packed_a->dev, packed, C, alpha, beta);
+    if (packed->is_a) return fail(TSMM_ERROR_INVALID_VALUE, "a packed A handle was passed as the packed B operand");
+    if (p->device < 0) return fail(TSMM_ERROR_NO_DEVICE, "plan was built for explicit caps, not a device");
+    if (packed->k != p->k || packed->n != p->n || packed->dtype != p->dtype || packed->layout != p->layout ||
+        packed->mode != p->mode)
+        return fail(TSMM_ERROR_SHAPE_MISMATCH, "plan and packed B disagree");
+    if (!C) return fail(TSMM_ERROR_INVALID_VALUE, "C is NULL");
+    if (reinterpret_cast<uintptr_t>(C) & 3) return fail(TSMM_ERROR_INVALID_VALUE, "C must be 4-byte aligned");
+    tsmm_plan_s q;
+    const tsmm_status st = presplit_geometry(*p, q);
+    if (st != TSMM_SUCCESS) return st;
+    const char *base = static_cast<const char *>(packed->dev);
+    const hipError_t e = launch_splitbf16_presplit(
+        split_products(p->dtype, p->mode), q.KC, q.NT / q.tile.nsplit, q.tile.rows_per_wave, packed_a->dev,
+        base + packed->L.off_frag, reinterpret_cast<const int32_t *>(base + packed->L.off_exps), C, p->m, p->n, p->k,
+        beta, q.grid, q.block, q.NT, q.tile.nsplit, p->stream);
+    return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "pre-split launch");
+}
 
 tsmm_status tsmm_plan_tune(tsmm_plan_t p, const void *A, tsmm_packed_t packed, void *C, int reps, double *best_ms) {
     g_err.clear();
@@ -1497,7 +1614,7 @@ tsmm_status tsmm_batched_bind(tsmm_plan_t p, const void *const *A, const tsmm_pa
         const BatchedInstance &I = p->inst[b];
         const tsmm_packed_s *P = packed[b];
         if (!P) return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": packed is NULL", b);
-        if (P->k != I.k || P->n != I.n || P->dtype != p->dtype || P->layout != TSMM_OP_N ||
+        if (P->is_a || P->k != I.k || P->n != I.n || P->dtype != p->dtype || P->layout != TSMM_OP_N ||
             P->mode != TSMM_MODE_NATIVE || !P->dev || !P->L.KC || !P->L.NT)
             return fail(TSMM_ERROR_SHAPE_MISMATCH, "instance %" PRId64 ": packed operand does not match", b);
         if (I.m > 0 && (!A[b] || !C[b])) return fail(TSMM_ERROR_INVALID_VALUE, "instance %" PRId64 ": NULL A or C", b);

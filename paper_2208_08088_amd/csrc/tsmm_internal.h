@@ -100,6 +100,12 @@ inline int ntclass(int64_t n) {
         if (n <= 16 * c) return c;
     return 0;
 }
+// Packed A of the split-bf16 modes: rows padded to a multiple of 8
+// bfloat16 values (whole 16-byte vectors), the row count to a multiple of
+// the 16-row tile, padding holding zeros; plane p starts at
+// p * presplit_rows(m) * presplit_ld(k) elements.
+__host__ __device__ inline int64_t presplit_ld(int64_t k) { return (k + 7) & ~(int64_t)7; }
+__host__ __device__ inline int64_t presplit_rows(int64_t m) { return (m + 15) & ~(int64_t)15; }
 inline bool vec_mapping(tsmm_dtype d, int64_t k, int KC) {
     int vw = 16 / elem_bytes(d);
     return (k % vw) == 0 && (KC % (4 * vw)) == 0;
@@ -132,6 +138,12 @@ struct tsmm_packed_s {
     tsmm::PackedLayout L;
     void *dev = nullptr;        // one device allocation holding every section
     const void *ref = nullptr;  // op T: the caller's B (nothing is copied)
+    // packed A (tsmm_pack_a): m x k, alpha folded in; n stays 0.  Native
+    // modes: dense row-major alpha*A; split modes: L.terms planes
+    // (presplit_ld / presplit_rows).
+    bool is_a = false;
+    int64_t m = 0;
+    double alpha = 1.0;
 };
 
 namespace tsmm {
@@ -269,6 +281,17 @@ hipError_t launch_splitbf16(tsmm_dtype dt, int KC, int NT, int RT, int products,
                             int64_t k, double alpha, double beta, int64_t grid, int block, int nt_total,
                             int nsplit, hipStream_t s);
 bool splitbf16_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, int products, bool il);
+
+// Packed A: alpha*A into `out` (terms 0: dense row-major of the input type;
+// terms 2 / 3: bfloat16 planes of RN32(alpha*A), presplit layout).
+hipError_t launch_pack_a(tsmm_dtype dt, int terms, const void *A, int64_t lda, void *out, int64_t m, int64_t k,
+                         double alpha, hipStream_t s);
+// The split-bf16 kernel on a pre-split A (products 3 or 6; alpha folded in
+// at pack time, so the epilogue takes alpha = 1).
+hipError_t launch_splitbf16_presplit(int products, int KC, int NT, int RT, const void *planes, const void *Bfrag,
+                                     const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k, double beta,
+                                     int64_t grid, int block, int nt_total, int nsplit, hipStream_t s);
+bool splitbf16_presplit_exists(int products, int KC, int NT, int RT);
 
 // op N binary64 on the vector ALU: NB columns per wavefront (16, 32),
 // B row-major; requires n % NB == 0 and k % 8 == 0.  grid = 64-row tiles

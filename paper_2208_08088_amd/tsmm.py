@@ -96,6 +96,8 @@ SIGNATURES = [
     ("tsmm_plan_destroy", None, [_VP]),
     ("tsmm_execute", ctypes.c_int, [_VP, _VP, _VP, _VP, _DBL, _DBL]),
     ("tsmm_execute_ld", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _I64, _DBL, _DBL]),
+    ("tsmm_pack_a", ctypes.c_int, [_VP, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _DBL, _VP, _PVP]),
+    ("tsmm_execute_packed_a", ctypes.c_int, [_VP, _VP, _VP, _VP, _DBL]),
     ("tsmm_plan_batched", ctypes.c_int, [_I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                          ctypes.POINTER(_I64), ctypes.c_int, _PVP]),
     ("tsmm_batched_bind", ctypes.c_int, [_VP, _PVP, _PVP, _PVP, ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)]),
@@ -195,6 +197,46 @@ def pack(B: torch.Tensor, layout: str = "N", mode: str = "native") -> Packed:
     _check(_lib().tsmm_pack(_ptr(B), k, n, _LAYOUTS[layout], dt, _MODES[mode], _stream(), ctypes.byref(h)),
            "tsmm_pack")
     return Packed(h.value, k, n, dt, _LAYOUTS[layout], _MODES[mode], B if layout == "T" else None)
+
+
+class PackedA:
+    """A packed big operand (tsmm_pack_a): alpha*A, pre-split into bfloat16
+    terms in the split-bf16 modes; reusable by any number of
+    execute_packed_a calls."""
+
+    def __init__(self, handle, m, k, dtype, mode, alpha):
+        self._h = handle
+        self.m, self.k, self.dtype, self.mode, self.alpha = m, k, dtype, mode, alpha
+
+    @property
+    def handle(self):
+        return self._h
+
+    def nbytes(self):
+        b = ctypes.c_size_t(0)
+        _check(_lib().tsmm_packed_bytes(self._h, ctypes.byref(b)), "tsmm_packed_bytes")
+        return b.value
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            _LIB.tsmm_packed_destroy(h)
+
+
+def pack_a(A: torch.Tensor, mode: str = "native", alpha: float = 1.0) -> PackedA:
+    """Pack A (m x k on the device, rows with adjacent elements; a row
+    stride is taken as the leading dimension) once, with alpha folded in."""
+    if A.dtype not in _DT_OF_TORCH:
+        raise TypeError("A must be float64, float32 or bfloat16")
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    m, k = A.shape
+    lda = _leading_dim(A, "A", A.dtype, (m, k), False)
+    dt = _DT_OF_TORCH[A.dtype]
+    h = ctypes.c_void_p(0)
+    _check(_lib().tsmm_pack_a(_ptr(A), m, k, lda, dt, _MODES[mode], float(alpha), _stream(), ctypes.byref(h)),
+           "tsmm_pack_a")
+    return PackedA(h.value, m, k, dt, _MODES[mode], float(alpha))
 
 
 def unpack(p: Packed) -> torch.Tensor:
@@ -360,6 +402,18 @@ def execute(p: Plan, A: torch.Tensor, packed: Packed, C: torch.Tensor, alpha: fl
     _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
     _check(lib.tsmm_execute_ld(p.handle, _ptr(A), lda, packed.handle, _ptr(C), ldc, float(alpha), float(beta)),
            "tsmm_execute_ld")
+    return C
+
+
+def execute_packed_a(p: Plan, packed_a: PackedA, packed: Packed, C: torch.Tensor, beta: float = 0.0) -> torch.Tensor:
+    """C = A_packed*B + beta*C (alpha folded into A_packed) in place on
+    torch's current stream; C row-major m x n, contiguous."""
+    _need_cuda(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n))
+    p._ensure_workspace()
+    lib = _lib()
+    _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
+    _check(lib.tsmm_execute_packed_a(p.handle, packed_a.handle, packed.handle, _ptr(C), float(beta)),
+           "tsmm_execute_packed_a")
     return C
 
 

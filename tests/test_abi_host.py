@@ -74,6 +74,36 @@ def test_pack_validates_before_touching_hip(T):
     lib.tsmm_graph_destroy(None)
 
 
+def test_pack_a_validates_before_touching_hip(T):
+    lib = T._lib()
+    h = ctypes.c_void_p(0)
+    A = ctypes.c_void_p(16)
+    assert lib.tsmm_pack_a(A, 4, 4, 4, T.F64, 0, 1.0, None, None) == T.INVALID_VALUE  # NULL out
+    assert lib.tsmm_pack_a(A, -1, 4, 4, T.F64, 0, 1.0, None, ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_pack_a(None, 4, 4, 4, T.F64, 0, 1.0, None, ctypes.byref(h)) == T.INVALID_VALUE  # NULL A
+    assert lib.tsmm_pack_a(A, 4, 4, 3, T.F64, 0, 1.0, None, ctypes.byref(h)) == T.INVALID_VALUE  # lda < k
+    assert lib.tsmm_pack_a(A, 4, 4, 4, 9, 0, 1.0, None, ctypes.byref(h)) == T.INVALID_VALUE
+    assert lib.tsmm_pack_a(A, 4, 4, 4, T.F32, 7, 1.0, None, ctypes.byref(h)) == T.INVALID_VALUE
+    # bfloat16 A is read as it is; the split modes take binary32 with k <= 256
+    assert lib.tsmm_pack_a(A, 4, 4, 4, T.BF16, 0, 1.0, None, ctypes.byref(h)) == T.NOT_SUPPORTED
+    assert lib.tsmm_pack_a(A, 4, 4, 4, T.F64, T.MODE_BF16X6, 1.0, None, ctypes.byref(h)) == T.NOT_SUPPORTED
+    assert lib.tsmm_pack_a(A, 4, 300, 300, T.F32, T.MODE_BF16X3, 1.0, None, ctypes.byref(h)) == T.NOT_SUPPORTED
+    # an empty A needs no device; the handle is refused where a packed B goes
+    assert lib.tsmm_pack_a(None, 0, 8, 8, T.F32, T.MODE_BF16X6, 2.0, None, ctypes.byref(h)) == T.SUCCESS
+    assert h.value
+    nb = ctypes.c_size_t(1)
+    assert lib.tsmm_packed_bytes(h, ctypes.byref(nb)) == T.SUCCESS and nb.value == 0
+    assert lib.tsmm_unpack(h, ctypes.c_void_p(16), None) == T.NOT_SUPPORTED
+    assert lib.tsmm_packed_split_planes(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == T.NOT_SUPPORTED
+    caps = T._Caps(256, 163840, 950)
+    p = ctypes.c_void_p(0)
+    assert lib.tsmm_plan_with_caps(0, 8, 8, 0, T.F32, ctypes.byref(caps), ctypes.byref(p)) == T.SUCCESS
+    assert lib.tsmm_execute_packed_a(p, h, h, None, 0.0) != T.SUCCESS
+    assert lib.tsmm_execute_packed_a(None, h, h, None, 0.0) == T.INVALID_VALUE
+    lib.tsmm_plan_destroy(p)
+    lib.tsmm_packed_destroy(h)
+
+
 def test_plan_validation(T):
     lib = T._lib()
     h = ctypes.c_void_p(0)

@@ -262,3 +262,53 @@ def test_column_scale_exponent():
     e = oracle.column_scale_exp(B2)
     mx = np.max(np.abs(B2), axis=0).astype(np.float64)
     assert np.all((mx * 2.0 ** -e.astype(np.float64) >= 1.0) & (mx * 2.0 ** -e.astype(np.float64) < 2.0))
+
+
+# --- PACKA (Algorithm 1: A scaled by alpha as it is packed) ---------------
+
+def _rn(alpha, a, to32):
+    # the product in exact rational arithmetic, rounded once to binary64
+    # (float() of a Fraction rounds correctly), then to binary32
+    x = float(Fraction(alpha) * Fraction(float(a)))
+    return np.float32(x) if to32 else x
+
+
+@pytest.mark.parametrize("alpha", [3.0, -0.7, 1e-3])
+def test_pack_a_scaling_against_exact_rationals(alpha):
+    A64 = I.host_uniform((7, 9), 21, 1, -4.0, 4.0)
+    A32 = I.host_uniform((7, 9), 21, 2, -4.0, 4.0, dtype=np.float32)
+    P64 = oracle.pack_a(A64, alpha)
+    P32 = oracle.pack_a(A32, alpha)
+    assert P64.dtype == np.float64 and P32.dtype == np.float32
+    for i in range(7):
+        for j in range(9):
+            assert P64[i, j] == _rn(alpha, A64[i, j], False)
+            assert P32[i, j] == _rn(alpha, A32[i, j], True)
+
+
+def test_pack_a_unit_scale_is_the_plain_split():
+    A = I.host_uniform((33, 40), 22, 1, -2.0, 2.0, dtype=np.float32)
+    for terms in (2, 3):
+        assert np.array_equal(oracle.pack_a(A, 1.0, terms), oracle.split_bf16(A, terms))
+    assert np.array_equal(oracle.pack_a(A, 1.0), A)
+
+
+def test_pack_a_power_of_two_shifts_exponents():
+    # alpha = 2^-3 moves every nonzero term's exponent field down by 3 and
+    # changes no significand bit (values stay far from the subnormal range)
+    A = I.host_uniform((50, 24), 23, 1, -8.0, 8.0, dtype=np.float32)
+    base = oracle.split_bf16(A, 3).astype(np.int32)
+    got = oracle.pack_a(A, 2.0 ** -3, 3).astype(np.int32)
+    nz = (base & 0x7FFF) != 0
+    assert np.array_equal(got[~nz], base[~nz])
+    assert np.array_equal(got[nz], base[nz] - (3 << 7))
+
+
+def test_pack_a_split_reconstructs_the_scaled_value():
+    A = I.host_uniform((64, 16), 24, 1, -1.0, 1.0, dtype=np.float32)
+    alpha = 1.37
+    p = oracle.pack_a(A, alpha, 3)
+    rec = _bf16_to_f64(p[0]) + _bf16_to_f64(p[1]) + _bf16_to_f64(p[2])
+    for i in range(0, 64, 7):
+        for j in range(16):
+            assert rec[i, j] == float(_rn(alpha, A[i, j], True))
