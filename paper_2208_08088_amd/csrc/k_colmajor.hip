@@ -37,12 +37,18 @@ template <typename T, int KC> struct ColCfg {
 };
 
 // The lane's A vectors of chunk c of column block `blk` (k-slot mapping
-// col(s, q) = 4*s + q, the packed image's scalar mapping).  Columns past k
-// and m indices past m read 0 (m is a multiple of VW, so a vector lies
-// wholly inside or outside).
+// col(s, q) = 4*s + q, the packed image's scalar mapping).  Every load is
+// issued, with no branch around it and no select after it (a load under a
+// branch makes the compiler wait for every outstanding load, the prefetch
+// included, before the products; a select after it waits for the load
+// right away): a lane whose vector lies past m (m is a multiple of VW, so a
+// vector lies wholly inside or outside) reads A's first vector, whose
+// results are never stored; a lane whose column lies past k reads `zp`, 16
+// zeros of the packed image (its last k-slot, which lies past k whenever a
+// column does), so no infinite A value meets a zero of B.
 template <typename T, int KC>
-__device__ __forceinline__ void col_load(const T *__restrict__ A, int64_t m, int k, int64_t lda, int64_t blk, int c,
-                                         int j, int q,
+__device__ __forceinline__ void col_load(const T *__restrict__ A, const T *__restrict__ zp, int64_t m, int k,
+                                         int64_t lda, int64_t blk, int c, int j, int q,
                                          typename Mfma4<T>::vec (&x)[ColCfg<T, KC>::CH]) {
     typedef typename Mfma4<T>::vec vec_t;
     constexpr int VW = Mfma4<T>::VW;
@@ -51,8 +57,8 @@ __device__ __forceinline__ void col_load(const T *__restrict__ A, int64_t m, int
 #pragma unroll
     for (int e = 0; e < CH; ++e) {
         const int col = 4 * (c * CH + e) + q;
-        x[e] = (i < m && col < k) ? __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(A + i + col * lda))
-                                  : vec_t{};
+        const T *p = col < k ? (i < m ? A + i + col * lda : A) : zp;
+        x[e] = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(p));
     }
 }
 
@@ -77,13 +83,35 @@ __device__ __forceinline__ void col_products(const T *__restrict__ sB, int c, in
     }
 }
 
-// Epilogue of column block blk: lane (q, j) holds C columns n0 + 16*t +
-// row(q, r) at m indices i0 + VW*j + u, u < VW (one 16-byte vector).
+// C vectors of column block blk (beta != 0): lane (q, j) reads C columns
+// n0 + 16*t + row(q, r) at m indices i0 + VW*j + u, u < VW (one 16-byte
+// vector each).  All loads are issued with no branch around them (vectors
+// past m or n read C's first vector; their results are never stored).
 template <typename T, int NT>
+__device__ __forceinline__ void col_load_c(const T *__restrict__ C, int64_t m, int n, int64_t ldc, int64_t blk,
+                                           int n0, int j, int q, typename Mfma4<T>::vec (&cv)[NT][4]) {
+    typedef Mfma4<T> M;
+    typedef typename M::vec vec_t;
+    constexpr int VW = M::VW;
+    const int64_t i = blk * 16 * VW + VW * j;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int col = n0 + 16 * t + M::row(q, r);
+            const T *p = (i < m && col < n) ? C + i + col * ldc : C;
+            cv[t][r] = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(p));
+        }
+}
+
+// Epilogue of column block blk: lane (q, j) holds C columns n0 + 16*t +
+// row(q, r) at m indices i0 + VW*j + u, u < VW (one 16-byte vector); cv
+// holds the C values when BC (beta != 0).
+template <typename T, int NT, bool BC>
 __device__ __forceinline__ void col_epilogue(T *__restrict__ C, int64_t m, int n, int64_t ldc, int64_t blk, int n0,
-                                             int j, int q,
-                                             double alpha, double beta,
-                                             const typename Mfma4<T>::acc (&acc)[Mfma4<T>::VW][NT]) {
+                                             int j, int q, double alpha, double beta,
+                                             const typename Mfma4<T>::acc (&acc)[Mfma4<T>::VW][NT],
+                                             const typename Mfma4<T>::vec (&cv)[NT][4]) {
     typedef Mfma4<T> M;
     typedef typename M::vec vec_t;
     constexpr int VW = M::VW;
@@ -95,21 +123,23 @@ __device__ __forceinline__ void col_epilogue(T *__restrict__ C, int64_t m, int n
         for (int r = 0; r < 4; ++r) {
             const int col = n0 + 16 * t + M::row(q, r);
             if (col >= n) continue;
-            vec_t *p = reinterpret_cast<vec_t *>(C + i + col * ldc);
-            const vec_t cv = beta != 0.0 ? __builtin_nontemporal_load(p) : vec_t{};
             vec_t v;
 #pragma unroll
-            for (int u = 0; u < VW; ++u) v[u] = (T)epilogue(alpha, (double)acc[u][t][r], beta, (double)cv[u]);
-            __builtin_nontemporal_store(v, p);
+            for (int u = 0; u < VW; ++u)
+                v[u] = (T)epilogue(alpha, (double)acc[u][t][r], BC ? beta : 0.0, BC ? (double)cv[t][r][u] : 0.0);
+            __builtin_nontemporal_store(v, reinterpret_cast<vec_t *>(C + i + col * ldc));
         }
 }
 
 // One column block: zero the accumulators, run the NCH chunks (chunk c in
 // buffer (PAR + c) % 2; the load of the chunk after it goes to the other
 // buffer), then the epilogue.  nb: the next column block of this wavefront
-// (its first chunk is loaded during the last chunk of this one).
-template <typename T, int KC, int NT, int SNT, int PAR>
-__device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__restrict__ sB, T *__restrict__ C,
+// (its first chunk is loaded during the last chunk of this one).  BC: the
+// block's C vectors are read at the start of the last chunk, before that
+// prefetch, so that the epilogue's wait for them does not include it.
+template <typename T, int KC, int NT, int SNT, int PAR, bool BC>
+__device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__restrict__ zp, const T *__restrict__ sB,
+                                          T *__restrict__ C,
                                           int64_t m, int n, int k, int64_t lda, int64_t ldc, int64_t blk, int64_t nb,
                                           int n0, int t0, int lane, int j, int q, double alpha, double beta,
                                           typename Mfma4<T>::vec (&x0)[ColCfg<T, KC>::CH],
@@ -118,6 +148,7 @@ __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__re
     constexpr int VW = M::VW;
     constexpr int NCH = ColCfg<T, KC>::NCH;
     typename M::acc acc[VW][NT];
+    typename M::vec cv[NT][4];
 #pragma unroll
     for (int u = 0; u < VW; ++u)
 #pragma unroll
@@ -131,18 +162,21 @@ __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__re
         const bool last = c + 1 == NCH;
         const int64_t lb = last ? nb : blk;
         const int lc = last ? 0 : c + 1;
+        if constexpr (BC) {
+            if (last) col_load_c<T, NT>(C, m, n, ldc, blk, n0, j, q, cv);
+        }
         if (((PAR + c) & 1) == 0) {
-            col_load<T, KC>(A, m, k, lda, lb, lc, j, q, x1);
+            col_load<T, KC>(A, zp, m, k, lda, lb, lc, j, q, x1);
             __builtin_amdgcn_sched_barrier(0);
             col_products<T, KC, NT, SNT>(sB, c, bofs, x0, acc);
         } else {
-            col_load<T, KC>(A, m, k, lda, lb, lc, j, q, x0);
+            col_load<T, KC>(A, zp, m, k, lda, lb, lc, j, q, x0);
             __builtin_amdgcn_sched_barrier(0);
             col_products<T, KC, NT, SNT>(sB, c, bofs, x1, acc);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    col_epilogue<T, NT>(C, m, n, ldc, blk, n0, j, q, alpha, beta, acc);
+    col_epilogue<T, NT, BC>(C, m, n, ldc, blk, n0, j, q, alpha, beta, acc, cv);
 }
 
 // KC: packed k class; NT: column tiles of C per wavefront; NG: column
@@ -150,8 +184,9 @@ __device__ __forceinline__ void col_block(const T *__restrict__ A, const T *__re
 // walk the same column blocks, each over NT tiles of its own, so the
 // second group's read of an A chunk follows the first through the cache);
 // nt_total: column tiles of the packed image; nsplit: column groups across
-// workgroups.
-template <typename T, int KC, int NT, int NG>
+// workgroups; BC: beta != 0 (C is read), a kernel of its own so that the
+// beta = 0 kernel holds no registers for C.
+template <typename T, int KC, int NT, int NG, bool BC>
 __global__ __launch_bounds__(kColBlock) void k_colmajor(const T *__restrict__ A, const T *__restrict__ Bf,
                                                          T *__restrict__ C, int64_t m, int n, int k, int64_t lda,
                                                          int64_t ldc, double alpha, double beta, int nt_total,
@@ -183,17 +218,19 @@ __global__ __launch_bounds__(kColBlock) void k_colmajor(const T *__restrict__ A,
     const int64_t stride = bm.nrb * wpg;
     int64_t blk = bm.rb * wpg + wig;
     if (blk >= nblk) return;
+    // 16 zeros (lanes 48..63 of k-step S-1: k-slot KC-1) for columns past k
+    const T *zp = Bf + (int64_t)(S - 1) * nt_total * 64 + 48;
     vec_t x0[ColCfg<T, KC>::CH], x1[ColCfg<T, KC>::CH];
-    col_load<T, KC>(A, m, k, lda, blk, 0, j, q, x0);
+    col_load<T, KC>(A, zp, m, k, lda, blk, 0, j, q, x0);
     // Blocks go in pairs: a block of NCH chunks that starts in buffer p
     // leaves the next block's first chunk in buffer (p + NCH) % 2, so after
     // a pair the first chunk is back in x0.  A pair's second block may lie
     // past the last one, where nothing is loaded or stored.
     for (; blk < nblk; blk += 2 * stride) {
-        col_block<T, KC, NT, SNT, 0>(A, sB, C, m, n, k, lda, ldc, blk, blk + stride, n0, t0, lane, j, q, alpha, beta,
-                                     x0, x1);
-        col_block<T, KC, NT, SNT, NCH & 1>(A, sB, C, m, n, k, lda, ldc, blk + stride, blk + 2 * stride, n0, t0, lane,
-                                           j, q, alpha, beta, x0, x1);
+        col_block<T, KC, NT, SNT, 0, BC>(A, zp, sB, C, m, n, k, lda, ldc, blk, blk + stride, n0, t0, lane, j, q,
+                                         alpha, beta, x0, x1);
+        col_block<T, KC, NT, SNT, NCH & 1, BC>(A, zp, sB, C, m, n, k, lda, ldc, blk + stride, blk + 2 * stride, n0,
+                                               t0, lane, j, q, alpha, beta, x0, x1);
     }
 }
 
@@ -201,9 +238,14 @@ template <typename T, int KC, int NT, int NG>
 hipError_t run_colmajor(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k, int64_t lda,
                         int64_t ldc, double alpha, double beta, int64_t grid, int nt_total, int nsplit,
                         hipStream_t s) {
-    hipLaunchKernelGGL((k_colmajor<T, KC, NT, NG>), dim3((unsigned)grid), dim3(kColBlock), 0, s,
-                       static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C), m, (int)n,
-                       (int)k, lda, ldc, alpha, beta, nt_total, nsplit);
+    if (beta != 0.0)
+        hipLaunchKernelGGL((k_colmajor<T, KC, NT, NG, true>), dim3((unsigned)grid), dim3(kColBlock), 0, s,
+                           static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C), m, (int)n,
+                           (int)k, lda, ldc, alpha, beta, nt_total, nsplit);
+    else
+        hipLaunchKernelGGL((k_colmajor<T, KC, NT, NG, false>), dim3((unsigned)grid), dim3(kColBlock), 0, s,
+                           static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C), m, (int)n,
+                           (int)k, lda, ldc, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
 }
 
@@ -216,18 +258,19 @@ struct ColEntry {
 };
 
 // packed slice (KC/4 * NT * NG * 64 values) within 128 KiB of LDS;
-// accumulators VW * NT tiles within 128 registers; at k classes of 128 and
-// more at most 4 column tiles per wavefront (8 spilled to scratch when
-// compiled), and two groups of them in one workgroup where the slice fits
+// column tiles per wavefront within the registers: 8 only at k class 4 (at
+// larger classes the beta != 0 kernel spilled to scratch when compiled),
+// else at most 4, and two groups of 4 in one workgroup where the slice
+// fits
 #define TSMM_COL_NT4(T, DT, KC) {DT, KC, 1, 1, &run_colmajor<T, KC, 1, 1>}, {DT, KC, 2, 1, &run_colmajor<T, KC, 2, 1>}, \
     {DT, KC, 4, 1, &run_colmajor<T, KC, 4, 1>},
 #define TSMM_COL_NT8(T, DT, KC) TSMM_COL_NT4(T, DT, KC) {DT, KC, 8, 1, &run_colmajor<T, KC, 8, 1>},
 static const ColEntry kColTable[] = {
-    TSMM_COL_NT8(double, TSMM_F64, 4) TSMM_COL_NT8(double, TSMM_F64, 8) TSMM_COL_NT8(double, TSMM_F64, 16)
-    TSMM_COL_NT8(double, TSMM_F64, 32) TSMM_COL_NT8(double, TSMM_F64, 64) TSMM_COL_NT4(double, TSMM_F64, 128)
+    TSMM_COL_NT8(double, TSMM_F64, 4) TSMM_COL_NT4(double, TSMM_F64, 8) TSMM_COL_NT4(double, TSMM_F64, 16)
+    TSMM_COL_NT4(double, TSMM_F64, 32) TSMM_COL_NT4(double, TSMM_F64, 64) TSMM_COL_NT4(double, TSMM_F64, 128)
     TSMM_COL_NT4(double, TSMM_F64, 256) {TSMM_F64, 128, 4, 2, &run_colmajor<double, 128, 4, 2>},
-    TSMM_COL_NT8(float, TSMM_F32, 4) TSMM_COL_NT8(float, TSMM_F32, 8) TSMM_COL_NT8(float, TSMM_F32, 16)
-    TSMM_COL_NT8(float, TSMM_F32, 32) TSMM_COL_NT8(float, TSMM_F32, 64) TSMM_COL_NT4(float, TSMM_F32, 128)
+    TSMM_COL_NT8(float, TSMM_F32, 4) TSMM_COL_NT4(float, TSMM_F32, 8) TSMM_COL_NT4(float, TSMM_F32, 16)
+    TSMM_COL_NT4(float, TSMM_F32, 32) TSMM_COL_NT4(float, TSMM_F32, 64) TSMM_COL_NT4(float, TSMM_F32, 128)
     TSMM_COL_NT4(float, TSMM_F32, 256) {TSMM_F32, 128, 4, 2, &run_colmajor<float, 128, 4, 2>},
     {TSMM_F32, 256, 4, 2, &run_colmajor<float, 256, 4, 2>},
 };

@@ -371,12 +371,13 @@ tsmm_tile default_tile(const tsmm_plan_s &p, int kernel) {
         t.wg_per_cu = 1;
         break;
     case TSMM_KERNEL_COLMAJOR: {
-        // column groups: at most 8 column tiles of C per wavefront (4 at k
-        // classes of 128 and more; the accumulators of two or four m-tiles)
-        // and a packed slice within the LDS budget
+        // column groups: at most 4 column tiles of C per wavefront (8 at
+        // the k class 4; the accumulators of two or four m-tiles and, with
+        // beta != 0, the C vectors read ahead) and a packed slice within
+        // the LDS budget
         const int KC = kclass4(p.k), NT = ntclass(p.n);
         t.nsplit = 1;
-        while ((NT / t.nsplit > (KC >= 128 ? 4 : 8) ||
+        while ((NT / t.nsplit > (KC >= 8 ? 4 : 8) ||
                 (size_t)(KC / 4) * (NT / t.nsplit) * 64 * elem_bytes(p.dtype) > kLdsBudget) &&
                t.nsplit < NT)
             t.nsplit *= 2;
