@@ -83,7 +83,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, in
 }
 
 // Byte offset outside any tile-sized resource: an access through it reads
-// 0 or is dropped.
+// 0 or is dropped.  Every resource that takes it spans at most 2^30 bytes
+// (the planner keeps 16 rows of a strided operand within that).
 constexpr int kOOB = 0x40000000;
 
 // Rows of the 16-row tile starting at row0 that exist in an m-row matrix.

@@ -54,17 +54,23 @@ __global__ __launch_bounds__(kSplitBlock) void k_splitk_pass1(const double *__re
     const int64_t gstride = (int64_t)nwave * 4 * RG;
     auto load = [&](int64_t g, double (&av)[RG][MT], double (&bv)[RG][NT]) {
         const int64_t rr = uniform64(r0 + g);  // first row of the group
-        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + rr * m + m0, ((r1 - rr) * m - m0) * 8);
-        const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + rr * n + n0, ((r1 - rr) * n - n0) * 8);
+        // the group's rows that exist (at most 4*RG: far below kOOB)
+        const int64_t rows = r1 - rr < 4 * RG ? r1 - rr : 4 * RG;
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + rr * m + m0, (rows * m - m0) * 8);
+        const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + rr * n + n0, (rows * n - n0) * 8);
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) {
             const int row = 4 * rg + q;
+            // columns past m (n) read through kOOB, which returns 0: no
+            // branch around a load (that would make the compiler wait for
+            // every outstanding load, the prefetch included, before the
+            // products)
 #pragma unroll
             for (int a = 0; a < MT; ++a)
-                av[rg][a] = acol[a] ? BufIO<double>::load1(ra, (row * m + 16 * a + j) * 8) : 0.0;
+                av[rg][a] = BufIO<double>::load1(ra, acol[a] ? (row * m + 16 * a + j) * 8 : kOOB);
 #pragma unroll
             for (int b = 0; b < NT; ++b)
-                bv[rg][b] = bcol[b] ? BufIO<double>::load1(rb, (row * n + 16 * b + j) * 8) : 0.0;
+                bv[rg][b] = BufIO<double>::load1(rb, bcol[b] ? (row * n + 16 * b + j) * 8 : kOOB);
         }
     };
     auto mma = [&](const double (&av)[RG][MT], const double (&bv)[RG][NT]) {

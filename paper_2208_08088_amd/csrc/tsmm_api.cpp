@@ -1243,7 +1243,11 @@ tsmm_status tsmm_execute_ld(tsmm_plan_t p, const void *A, int64_t lda, tsmm_pack
     const int vw = 16 / elem_bytes(p->dtype);
     const bool a16 = (reinterpret_cast<uintptr_t>(A) & 15) == 0, c16 = (reinterpret_cast<uintptr_t>(C) & 15) == 0;
     // strides the 32-bit lane offsets of the row-major kernels cover
-    const bool ld32 = lda <= (1 << 24) && ldc <= (1 << 24);
+    // strides the row-major kernels' tile resources cover: 16 rows of
+    // either operand span at most 2^30 bytes, so the out-of-range offset
+    // kOOB (2^30) lies past every tile and the lane offsets fit 32 bits
+    const int64_t eb_in = elem_bytes(p->dtype), eb_out = elem_bytes(out_dt);
+    const bool ld32 = lda * eb_in <= ((int64_t)1 << 26) && ldc * eb_out <= ((int64_t)1 << 26);
     int kernel = p->tile.kernel;
     if (kernel == TSMM_KERNEL_STREAM || kernel == TSMM_KERNEL_SLAB) {
         const bool il = frag4_pg(p->dtype, p->NT, p->n) > 1;

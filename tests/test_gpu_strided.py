@@ -99,3 +99,25 @@ def test_strides_below_natural_and_split_modes():
     pq = T.pack(torch.zeros((k, n), dtype=torch.float32, device="cuda"))
     st = lib.tsmm_execute_ld(q.handle, A.data_ptr(), k - 1, pq.handle, C.data_ptr(), n, 1.0, 0.0)
     assert st == T.INVALID_VALUE
+
+
+def test_huge_strides_take_the_any_shape_kernel():
+    # strides beyond 2^26 bytes: 16 rows of a tile would span more than the
+    # out-of-range lane offset, so the plan runs the any-shape kernel; the
+    # result matches the oracle and nothing between the rows is written
+    m, n, k = 40, 8, 8
+    ld = 1 << 24  # binary64 elements: 15 rows of C span 2^31 bytes
+    A = I.host_uniform((m, k), 9100, 1)
+    B = I.host_uniform((k, n), 9100, 2)
+    C0 = I.host_uniform((m, n), 9100, 3)
+    announce("huge strides", m, n, k, ld)
+    abuf = torch.zeros((m, ld), dtype=torch.float64, device="cuda")
+    abuf[:, :k] = torch.from_numpy(A).cuda()
+    cbuf = torch.full((m, ld), 777.0, dtype=torch.float64, device="cuda")
+    cbuf[:, :n] = torch.from_numpy(C0).cuda()
+    p = T.plan(m, n, k, "N", torch.float64)
+    T.execute(p, abuf[:, :k], T.pack(torch.from_numpy(B).cuda()), cbuf[:, :n], 1.5, 0.5)
+    assert_normwise(host(cbuf[:, :n]), oracle.gemm_n(A, B, C0, 1.5, 0.5), 1e-12)
+    assert int((cbuf[:, n:] != 777.0).sum().item()) == 0
+    del abuf, cbuf
+    torch.cuda.empty_cache()
