@@ -25,42 +25,6 @@ __device__ __forceinline__ f4v mfma_bf16(const u16x8 &a, const u16x8 &b, f4v c) 
                                                    0, 0, 0);
 }
 
-// Load the 8 A values of lane (row, q) for k-chunk c as binary32.
-template <typename TA, bool VEC>
-__device__ __forceinline__ void load_a8(const TA *__restrict__ arow, int col, int k, bool rok, float (&x)[8]);
-
-template <>
-__device__ __forceinline__ void load_a8<float, true>(const float *__restrict__ arow, int col, int k, bool rok,
-                                                     float (&x)[8]) {
-    f4v v0 = {}, v1 = {};
-    if (rok && col < k) v0 = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(arow + col));
-    if (rok && col + 4 < k) v1 = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(arow + col + 4));
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        x[e] = v0[e];
-        x[4 + e] = v1[e];
-    }
-}
-template <>
-__device__ __forceinline__ void load_a8<float, false>(const float *__restrict__ arow, int col, int k, bool rok,
-                                                      float (&x)[8]) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = (rok && col + e < k) ? arow[col + e] : 0.0f;
-}
-
-// bf16 inputs: the 8 raw values (no conversion needed for the product).
-template <bool VEC>
-__device__ __forceinline__ u16x8 load_a8_bf16(const uint16_t *__restrict__ arow, int col, int k, bool rok) {
-    u16x8 v = {};
-    if constexpr (VEC) {
-        if (rok && col < k) v = __builtin_nontemporal_load(reinterpret_cast<const u16x8 *>(arow + col));
-    } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (rok && col + e < k) ? arow[col + e] : (uint16_t)0;
-    }
-    return v;
-}
-
 // Residual split of 8 binary32 values into TERMS bfloat16 vectors.
 template <int TERMS>
 __device__ __forceinline__ void split8(const float (&x)[8], u16x8 (&t)[TERMS]) {
@@ -153,17 +117,22 @@ __device__ __forceinline__ void bf16_load_step(const TA *__restrict__ A, int64_t
                     }
                 }
             } else {
-                const int64_t row = row0 + j;
-                const bool rok = row < m;
+                // one load per value through the tile's resource: values past k
+                // read through kOOB (no branch around a load, so the compiler
+                // need not wait for the prefetch before the products)
+                const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + row0 * k, tile_rows(m, row0) * (int64_t)k * SZ);
+                const int voff0 = j * k * SZ;
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     const int col = 32 * c + 8 * q;
-                    if constexpr (F32IN)
-                        load_a8<float, false>(reinterpret_cast<const float *>(A) + row * (int64_t)k, col, k, rok,
-                                              x.v[rt][c]);
-                    else
-                        x.v[rt][c] = load_a8_bf16<false>(reinterpret_cast<const uint16_t *>(A) + row * (int64_t)k, col, k,
-                                                         rok);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int off = col + e < k ? voff0 + (col + e) * SZ : kOOB;
+                        if constexpr (F32IN)
+                            x.v[rt][c][e] = BufIO<float>::template load1<AUX>(ra, off);
+                        else
+                            x.v[rt][c][e] = __builtin_amdgcn_raw_buffer_load_b16(ra, off, 0, AUX);
+                    }
                 }
             }
         }
