@@ -63,3 +63,38 @@ def test_graph_replays_match_eager(layout, dtype, m, n, k):
         # eager work between replays
         T.execute(p, A, pk, C, 1.5, 0.5)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode,m,n,k", [("bf16x6", 60000, 48, 64), ("bf16x3", 30000, 128, 128), ("native", 50000, 32, 32)])
+def test_packed_a_graph_replays_match_eager(mode, m, n, k):
+    # the packed-A execute launches kernels only, so it can be captured too
+    A = I.device_uniform((m, k), 32, 1, torch.float32)
+    B = I.device_uniform((k, n), 32, 2, torch.float32)
+    p = T.plan(m, n, k, "N", torch.float32)
+    if mode != "native":
+        p.set_mode(mode)
+    pk = T.pack(B, "N", mode)
+    pa = T.pack_a(A, mode, 0.5)
+    C0 = torch.rand((m, n), dtype=torch.float32, device="cuda")
+    C = C0.clone()
+    announce("graph packed A", mode, m, n, k)
+    T.execute_packed_a(p, pa, pk, C, 0.5)
+    eager = C.clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        C.copy_(C0)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            T.execute_packed_a(p, pa, pk, C, 0.5)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        C.copy_(C0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(C, eager), (rep, mode)
+        T.execute_packed_a(p, pa, pk, C, 0.5)
+        torch.cuda.synchronize()
