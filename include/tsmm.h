@@ -157,9 +157,13 @@ typedef struct tsmm_tile {
     int32_t splitk;        /* op T: number of partial sums P (1..65536);
                               TSMM_KERNEL_SLAB: parts of the k range        */
     int32_t nsplit;        /* op N: column groups sharing one row block     */
-    int32_t chunk_rows;    /* batched plans: rows of one instance that a
-                              workgroup takes per work item, a power of two
-                              in 256..65536 (0 = default); 0 elsewhere      */
+    int32_t chunk_rows;    /* batched plans: rows per work item for an
+                              instance whose rows (of A plus of C) take 256
+                              bytes, a power of two in 256..65536 (0 =
+                              default); each instance scales it by 256 / its
+                              row bytes (power of two at or below, within
+                              256..65536), so that work items move about the
+                              same bytes; 0 elsewhere                       */
 } tsmm_tile;
 
 /* Device properties the planner uses; tsmm_plan reads them from the current
@@ -395,8 +399,8 @@ tsmm_status tsmm_execute_packed_a(tsmm_plan_t plan, tsmm_packed_t packed_a, tsmm
 
 /* Plan `count` independent op N multiplies that run in ONE persistent
  * launch: instance b is m[b] x k[b] times k[b] x n[b].  Host arrays.  The
- * plan cuts the instances into chunks of rows (chunk_rows from the tile
- * table's batched entry for the dtype, else 4096; instances of one kernel
+ * plan cuts the instances into chunks of rows (sized from chunk_rows, from
+ * the tile table's batched entry for the dtype, else 4096; instances of one kernel
  * variant together, longest first) that the launch's workgroups take from
  * a device counter; the plan owns that counter, which every launch leaves
  * at zero, so the launches (or graph replays) of one plan must not overlap

@@ -133,8 +133,9 @@ __device__ __forceinline__ void run_segment_bf16(const BatchDesc &d, int64_t row
     }
 }
 
-// Dynamic schedule: the work is a sequence of chunks (chunk_rows rows of
-// one instance; instances of one kernel variant next to each other).  A
+// Dynamic schedule: the work is a sequence of chunks (d.chunk_rows rows of
+// one instance, about the same bytes for every instance; instances of one
+// kernel variant next to each other).  A
 // workgroup takes the next chunk from a counter, loads that instance's
 // packed B into LDS when the instance changes (the per-core resident block
 // of B of the paper's Sec. IV-A.2), and streams the chunk's rows with the
@@ -145,7 +146,7 @@ __device__ __forceinline__ void run_segment_bf16(const BatchDesc &d, int64_t row
 // (and every graph replay) starts from a clean state without a memset.
 template <bool BF16>
 __global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_batched(
-    const BatchDesc *__restrict__ desc, const int64_t *__restrict__ chunk_start, int64_t nchunks, int chunk_rows,
+    const BatchDesc *__restrict__ desc, const int64_t *__restrict__ chunk_start, int64_t nchunks,
     int32_t *__restrict__ ctr) {
     extern __shared__ u16x8 sB[];  // the current instance's packed B
     __shared__ int32_t s_chunk;
@@ -165,8 +166,8 @@ __global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_e
             loaded = inst;
         }
         __syncthreads();  // B in LDS; every lane has read s_chunk
-        const int64_t row_a = (c - chunk_start[inst]) * chunk_rows;
-        const int64_t row_b = row_a + chunk_rows < d.m ? row_a + chunk_rows : d.m;
+        const int64_t row_a = (c - chunk_start[inst]) * d.chunk_rows;
+        const int64_t row_b = row_a + d.chunk_rows < d.m ? row_a + d.chunk_rows : d.m;
         if constexpr (BF16) run_segment_bf16(d, row_a, row_b, sB, wave);
         else run_segment_f32(d, row_a, row_b, reinterpret_cast<const float *>(sB), wave);
     }
@@ -195,10 +196,10 @@ hipError_t launch_batched(tsmm_dtype dt, const BatchDesc *desc, const int64_t *c
         return hipErrorInvalidValue;
     if (dt == TSMM_BF16)
         hipLaunchKernelGGL(k_batched<true>, dim3((unsigned)grid), dim3(block), lds_bytes, s, desc, chunk_start,
-                           nchunks, chunk_rows, ctr);
+                           nchunks, ctr);
     else
         hipLaunchKernelGGL(k_batched<false>, dim3((unsigned)grid), dim3(block), lds_bytes, s, desc, chunk_start,
-                           nchunks, chunk_rows, ctr);
+                           nchunks, ctr);
     return hipGetLastError();
 }
 

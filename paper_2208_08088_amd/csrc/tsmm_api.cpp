@@ -613,7 +613,8 @@ int batched_table_chunk(tsmm_dtype dtype, bool *from_table) {
     return kBatchChunkDefault;
 }
 
-// Cut the instances (in execution order) into chunks of chunk_rows rows:
+// Cut the instances (in execution order) into chunks (batch_instance_chunk
+// rows each):
 // the prefix of chunk counts goes to the device (synchronously) and the
 // grid follows the work.
 tsmm_status batched_chunks(tsmm_plan_s &p, int chunk_rows) {
@@ -621,7 +622,8 @@ tsmm_status batched_chunks(tsmm_plan_s &p, int chunk_rows) {
     std::vector<int64_t> inst_start(count + 1, 0);
     for (size_t e = 0; e < count; ++e) {
         const BatchedInstance &I = p.inst[p.order[e]];
-        inst_start[e + 1] = inst_start[e] + (I.m + chunk_rows - 1) / chunk_rows;
+        const int cr = batch_instance_chunk(chunk_rows, I.k, I.n, (int)elem_bytes(p.dtype));
+        inst_start[e + 1] = inst_start[e] + (I.m + cr - 1) / cr;
     }
     if (inst_start[count] >= (int64_t)1 << 31) return fail(TSMM_ERROR_NOT_SUPPORTED, "batch too large (2^31 chunks)");
     hipError_t e = hipMemcpy(p.d_inst_start, inst_start.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
@@ -653,6 +655,14 @@ tsmm_status set_batched_tile(tsmm_plan_s &p, const tsmm_tile &t) {
     tsmm_status st = batched_chunks(p, chunk);
     if (st != TSMM_SUCCESS) return st;
     p.tile_from_table = from_table;
+    if (p.bound) {  // the bound descriptors carry each instance's chunk rows
+        for (size_t e2 = 0; e2 < p.bound_desc.size(); ++e2) {
+            const BatchedInstance &I = p.inst[p.order[e2]];
+            p.bound_desc[e2].chunk_rows = batch_instance_chunk(chunk, I.k, I.n, (int)elem_bytes(p.dtype));
+        }
+        e = hipMemcpy(p.d_desc, p.bound_desc.data(), sizeof(BatchDesc) * p.bound_desc.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "batched descriptor update");
+    }
     return TSMM_SUCCESS;
 }
 
@@ -1643,6 +1653,7 @@ tsmm_status tsmm_batched_bind(tsmm_plan_t p, const void *const *A, const tsmm_pa
         d.NT = P->L.NT;
         d.vec = vec ? 1 : 0;
         d.il = il ? 1 : 0;
+        d.chunk_rows = batch_instance_chunk(p->tile.chunk_rows, I.k, I.n, (int)elem_bytes(p->dtype));
         if (d.alpha == 0.0 && I.m > 0)
             return fail(TSMM_ERROR_NOT_SUPPORTED, "instance %" PRId64 ": alpha == 0 in a batched plan", b);
     }

@@ -164,6 +164,8 @@ struct alignas(16) BatchDesc {
     int32_t k, n;
     int32_t KC, NT;
     int32_t vec, il;  // vector k-slot mapping; interleaved columns (16-byte C vectors)
+    int32_t chunk_rows;  // rows of this instance per work item
+    int32_t pad_;
 };
 
 // Rows of one batched chunk (the unit of the dynamic schedule) when the
@@ -172,6 +174,18 @@ struct alignas(16) BatchDesc {
 // batched kernel.
 constexpr int kBatchChunkDefault = 4096;
 constexpr int kBatchChunkMin = 256, kBatchChunkMax = 65536;
+// Rows of one work item of an instance: chunk_rows is the size for rows
+// of 256 bytes (a row of A plus a row of C); an instance scales it by
+// 256 / its row bytes, to the power of two at or below, within the
+// allowed range, so that every work item moves about the same bytes and
+// the workgroups finish together.
+inline int batch_instance_chunk(int chunk_rows, int64_t k, int64_t n, int a_bytes) {
+    const int64_t row_bytes = k * a_bytes + n * 4;
+    int64_t c = (int64_t)chunk_rows * 256 / (row_bytes > 0 ? row_bytes : 1);
+    int64_t p2 = kBatchChunkMin;
+    while (p2 * 2 <= c && p2 < kBatchChunkMax) p2 *= 2;
+    return (int)p2;
+}
 constexpr int kBatchWaves = 8;
 
 }  // namespace tsmm
