@@ -5,12 +5,25 @@
 Workload (the headline): binary64 tall-A x small-B,
 C = alpha*A*B + beta*C with m = 2^23 rows, k = n in {8, 32, 128} and
 beta in {0, 1} -- six sub-cases.  B is packed once per k and reused by every
-call; each call reads a different A buffer (a rotation of two per k, each
-larger than the last-level cache), so no call sees its A in cache.  One
-step = one execute of each of the six sub-cases.  The value is the
-algorithmic HBM bytes of a step (A once, C once, plus C once more when
-beta = 1; packing excluded, as the paper excludes it) over the wall time of
-the step: GB/s, whole job.
+call.  A is fresh for every call: three A buffers per k, each larger than
+the last-level cache, taken in turn so that no two consecutive calls of a k
+(beta 0 and beta 1 of one step included) read the same A.  Every beta = 1
+call computes the same contract: its C is restored from a pristine C0
+(untimed device copies at the start of the step, followed by gigabytes of
+other traffic before the call, so no C row is still in the last-level
+cache).  One step = one execute of each of the six sub-cases.  Each execute
+is timed with HIP events on the stream it runs on; the step time is the sum
+of the six, so the untimed restores between steps are not counted.  The
+value is the algorithmic HBM bytes of a step (A once, C once, plus C once
+more when beta = 1; packing excluded, as the paper excludes it) over the
+step time: GB/s, whole job.  The wall time of the bracketed steps, restores
+included, is reported beside it.
+
+Bandwidth ceilings (same run): hand-written read-only, write-only, copy
+(1 read : 1 write) and 2-read : 1-write stream kernels over 4 GiB buffers
+(libtsmm_ceiling.so), best launch shape of a small sweep; each headline
+case is also given as a fraction of the ceiling of its own read : write
+mix (beta 0: copy; beta 1: 2 : 1).
 
 Extras (same run, reported beside the headline): the 4096 x 16 latency
 case, the op T split-k shape (C(64x64) = A^T B, A and B 2^22 x 64), the
@@ -98,37 +111,50 @@ class Timer:
         return out
 
 
+N_A_BUFFERS = 3  # A buffers per k: no two consecutive calls of a k share one
+
+
 def headline(torch, T, I, args):
-    """The binary64 streaming sweep: returns per-sub-case state and timings."""
+    """The binary64 streaming sweep: returns per-sub-case state."""
     cases = []
     for k in KS:
         n = k
         B = I.device_uniform((k, n), I.BASE_SEED, 100 + k, torch.float64)
         pk = T.pack(B)
-        As = [I.device_uniform((M_ROWS, k), I.BASE_SEED, 200 + 10 * k + r, torch.float64) for r in range(2)]
+        As = [I.device_uniform((M_ROWS, k), I.BASE_SEED, 200 + 10 * k + r, torch.float64)
+              for r in range(N_A_BUFFERS)]
         for beta in BETAS:
             tag = "k%db%d" % (k, int(beta))
             if args.only and tag != args.only:
                 continue
             C = I.device_uniform((M_ROWS, n), I.BASE_SEED, 300 + 10 * k + int(beta), torch.float64)
+            C0 = C.clone() if beta != 0.0 else None  # pristine copy, restored before every call
             p = T.plan(M_ROWS, n, k, "N", torch.float64)
-            cases.append(dict(tag=tag, k=k, n=n, beta=beta, B=B, pk=pk, As=As, C=C, p=p,
+            cases.append(dict(tag=tag, k=k, n=n, beta=beta, B=B, pk=pk, As=As, C=C, C0=C0, p=p,
                               bytes=opn_bytes(M_ROWS, n, k, beta), flops=2.0 * M_ROWS * n * k))
     return cases
 
 
 def run_headline(torch, T, cases, steps, warmup):
+    """Warm-up steps, then `steps` timed steps bracketed by synchronisations.
+    Returns the bracketed wall time and the per-call event times."""
     timer = Timer(torch)
-    call = [0]
+    step_no = [0]
 
     def step(record):
+        # untimed: every beta != 0 case starts from its pristine C0
         for c in cases:
-            A = c["As"][call[0] % 2]
+            if c["C0"] is not None:
+                c["C"].copy_(c["C0"])
+        for c in cases:
+            # A index 2*step + beta (mod 3): beta 0 and beta 1 of a step, and
+            # the last call of a step and the first of the next, differ
+            A = c["As"][(2 * step_no[0] + int(c["beta"] != 0.0)) % N_A_BUFFERS]
             e0 = timer.start() if record else None
             T.execute(c["p"], A, c["pk"], c["C"], 1.0, c["beta"])
             if record:
                 timer.stop(c["tag"], e0)
-        call[0] += 1
+        step_no[0] += 1
 
     for _ in range(warmup):
         step(False)
@@ -181,27 +207,63 @@ def bound_of(bytes_, flops, dt):
     return ("hbm", t_hbm) if t_hbm >= t_cmp else ("mfma", t_cmp)
 
 
-def copy_ceiling(torch, nbytes=4 << 30, reps=10):
-    """Achievable HBM rate of a plain device copy (torch's copy kernel) of
-    the same order of size: read + write bytes over time."""
+CEIL_GRIDS = (1024, 2048, 4096)  # workgroups of 256 lanes (4, 8, 16 per compute unit)
+CEIL_UNROLLS = (2, 4, 8)          # 16-byte vectors per lane per step
+
+
+def ceilings(torch, nbytes=4 << 30, reps=5):
+    """Same-run bandwidth ceilings from the hand-written stream kernels of
+    libtsmm_ceiling.so over `nbytes` buffers (16 times the last-level
+    cache): read-only, write-only, copy (1 : 1) and 2 reads : 1 write.  For
+    each mix the best median over the launch shapes; rates count every byte
+    read and written."""
+    import ctypes
+    from paper_2208_08088_amd import build as B
+    lib = ctypes.CDLL(B.CEIL_LIB)
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.ceiling_read.argtypes = [vp, i64, vp, ci, ci, vp]
+    lib.ceiling_write.argtypes = [vp, i64, ci, ci, vp]
+    lib.ceiling_copy.argtypes = [vp, vp, i64, ci, ci, vp]
+    lib.ceiling_mix2.argtypes = [vp, vp, vp, i64, ci, ci, vp]
     n = nbytes // 8
-    src = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    ts = []
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        dst.copy_(src)
-        e1.record()
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    ms = float(np.median(ts))
-    del src, dst
+    s0 = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+    s1 = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    sink = torch.empty(max(CEIL_GRIDS) * 256 * 2, dtype=torch.float64, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    kinds = {
+        "read": (1, 0, lambda g, u, st: lib.ceiling_read(P(s0), nbytes, P(sink), g, u, st)),
+        "write": (0, 1, lambda g, u, st: lib.ceiling_write(P(d), nbytes, g, u, st)),
+        "copy": (1, 1, lambda g, u, st: lib.ceiling_copy(P(s0), P(d), nbytes, g, u, st)),
+        "mix2": (2, 1, lambda g, u, st: lib.ceiling_mix2(P(s0), P(s1), P(d), nbytes, g, u, st)),
+    }
+    out = {}
+    for name, (nr, nw, fn) in kinds.items():
+        best = None
+        for g in CEIL_GRIDS:
+            for u in CEIL_UNROLLS:
+                st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+                assert fn(g, u, st) == 0, (name, g, u)  # warm-up
+                ts = []
+                for _ in range(reps):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    fn(g, u, st)
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+                ms = float(np.median(ts))
+                if best is None or ms < best[0]:
+                    best = (ms, g, u)
+        ms, g, u = best
+        byt = (nr + nw) * nbytes
+        out[name] = dict(reads=nr, writes=nw, bytes=byt, us=ms * 1e3, GB_s=byt / ms / 1e6,
+                         hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, grid=g, unroll=u)
+    del s0, s1, d, sink
     torch.cuda.empty_cache()
-    return dict(kernel="torch copy_", bytes=2 * nbytes, us=ms * 1e3, GB_s=2 * nbytes / ms / 1e6,
-                hbm_frac=2 * nbytes / ms / 1e6 / HBM_PEAK_GBS)
+    out["kernel"] = "libtsmm_ceiling.so stream kernels, %d GiB buffers, 16-byte buffer loads/stores" % (nbytes >> 30)
+    return out
 
 
 def extras_opt(torch, T, I, steps, warmup):
@@ -250,9 +312,40 @@ def extras_small(torch, T, I, calls=200):
     e1.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / calls
     byt = opn_bytes(m, n, k, 0.5)
+    # the same calls captured once in a graph (torch's CUDA-graph API on a
+    # side stream; every execute is a plain kernel launch) and replayed
+    per_graph = 20
+    Cg = C0.clone()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        T.execute(p, A, pk, Cg, 1.5, 0.5)  # warm the plan on the capture stream
+        torch.cuda.synchronize()
+        Cg.copy_(C0)
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(per_graph):
+                T.execute(p, A, pk, Cg, 1.5, 0.5)
+    torch.cuda.current_stream().wait_stream(side)
+    Ce = C0.clone()
+    for _ in range(per_graph):
+        T.execute(p, A, pk, Ce, 1.5, 0.5)
+    Cg.copy_(C0)
+    g.replay()
+    torch.cuda.synchronize()
+    graph_ok = bool(torch.equal(Cg, Ce))  # a replay gives the eager result
+    replays = max(1, calls // per_graph)
+    e0.record()
+    for _ in range(replays):
+        g.replay()
+    e1.record()
+    e1.synchronize()
+    us_graph = e0.elapsed_time(e1) * 1e3 / (replays * per_graph)
+    del g
     keep = dict(A=A.cpu().numpy(), B=B.cpu().numpy(), C0=C0.cpu().numpy(), C=first.cpu().numpy())
     return dict(shape="f64 4096x16 times 16x16, alpha 1.5, beta 0.5", plan=p.describe(), calls=calls,
-                us_per_call=us, GB_s=byt / us / 1e3), keep
+                us_per_call=us, GB_s=byt / us / 1e3, graph_us_per_call=us_graph, graph_calls=replays * per_graph,
+                graph_equals_eager=graph_ok, graph_GB_s=byt / us_graph / 1e3), keep
 
 
 def extras_precision(torch, T, I, steps, warmup):
@@ -586,8 +679,9 @@ def main():
     T._lib()  # fail loudly if the HIP library is missing
     torch.cuda.set_device(0)
 
-    ceiling = copy_ceiling(torch)
-    log("copy ceiling %.0f GB/s" % ceiling["GB_s"])
+    ceiling = ceilings(torch)
+    log("ceilings: read %.0f, write %.0f, copy %.0f, 2:1 %.0f GB/s" % tuple(
+        ceiling[kk]["GB_s"] for kk in ("read", "write", "copy", "mix2")))
     cases = headline(torch, T, I, args)
     log("headline cases ready: %s" % ", ".join(c["tag"] for c in cases))
     # snapshot sampled C0 rows and check one call of each case (for the CPU leg)
@@ -601,7 +695,8 @@ def main():
 
     wall, per = run_headline(torch, T, cases, args.steps, args.warmup)
     step_bytes = sum(c["bytes"] for c in cases)
-    value = step_bytes * args.steps / wall / 1e9
+    step_ms = sum(float(np.mean(per[c["tag"]])) for c in cases)
+    value = step_bytes / step_ms / 1e6
     breakdown = []
     dom = None
     for c in cases:
@@ -613,7 +708,9 @@ def main():
                    GB_s=c["bytes"] / ms / 1e6, hbm_frac=c["bytes"] / ms / 1e6 / HBM_PEAK_GBS,
                    TFLOP_s=c["flops"] / ms / 1e9, bound=bnd, roofline_frac=t_ideal / (ms * 1e-3),
                    us_median=float(q[0]) * 1e3, us_min=float(np.min(msl)) * 1e3, us_p90=float(q[1]) * 1e3,
-                   copy_frac=c["bytes"] / ms / 1e6 / ceiling["GB_s"], plan=c["p"].describe())
+                   ceiling_mix="mix2" if c["beta"] != 0.0 else "copy",
+                   ceiling_frac=c["bytes"] / ms / 1e6 / ceiling["mix2" if c["beta"] != 0.0 else "copy"]["GB_s"],
+                   plan=c["p"].describe())
         breakdown.append(row)
         if dom is None or ms > dom[1]:
             dom = (c, ms, bnd)
@@ -631,19 +728,22 @@ def main():
 
     result = dict(metric="TSMM GB/s (frac of HBM peak): FP64 plain vs split-BF16/FP32 at <=1e-6 rel err",
                   value=value, unit="GB/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-                  ms_per_step=wall / args.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+                  ms_per_step=step_ms, higher_is_better=True, scaling="weak", vs_baseline=None,
                   dtype="f64", data="synthetic",
                   config=dict(workload="binary64 tall-A x small-B, m=2^23, k=n in {8,32,128}, beta in {0,1}, "
                                        "packed B reused, fresh A per call", m=M_ROWS, k_n=list(KS),
                               betas=list(BETAS), step_bytes=step_bytes),
                   hbm_frac=value / HBM_PEAK_GBS, roofline=roofline, breakdown=breakdown,
-                  copy_ceiling=ceiling)
+                  timing="HIP events around each execute on its stream; step = sum of the six; beta = 1 C "
+                         "restores between steps untimed",
+                  wall_ms_per_step=wall / args.steps * 1e3, ceilings=ceiling)
 
     keep_s = None
     if not args.no_extras and not args.only:
         small, keep_s = extras_small(torch, T, I)
         log("small case done")
         opt, keep_t = extras_opt(torch, T, I, args.steps, args.warmup)
+        opt["ceiling_frac"] = opt["GB_s"] / ceiling["read"]["GB_s"]  # op T only reads
         log("op T done")
         prec, keep_p = extras_precision(torch, T, I, args.steps, args.warmup)
         log("precision done")

@@ -191,6 +191,21 @@ const char *tsmm_last_error(void);
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int32_t tsmm_version(void);
 
+/* The key lines a tile table must carry to be used (the install-time stage
+ * of Sec. III: the table records timings taken on one device, runtime and
+ * library, and is only valid there).  Writes three lines,
+ *     key arch gfx<N>\nkey hip <hipRuntimeGetVersion()>\nkey libtsmm <tsmm_version()>\n
+ * into buf (at most len bytes including the terminating NUL) for
+ * architecture gcn_arch (950 for gfx950), or for the current HIP device
+ * when gcn_arch is 0.  tsmm_plan ignores a table whose key lines are
+ * missing or name another runtime or library version (and applies its
+ * entries only to plans for the keyed architecture); it then uses built-in
+ * tiles, or fails with TSMM_ERROR_TABLE when the environment variable
+ * TSMM_STRICT_TABLE is set.
+ * Errors: INVALID_VALUE (NULL buf, len too small, negative gcn_arch),
+ * NO_DEVICE (gcn_arch 0 without a usable device). */
+tsmm_status tsmm_table_key(int32_t gcn_arch, char *buf, size_t len);
+
 /* -------------------------------------------------------------------- pack */
 
 /* Pack the small operand B once, for reuse by any number of executes

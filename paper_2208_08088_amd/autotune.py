@@ -277,10 +277,18 @@ def read_table(path):
     if os.path.exists(path):
         for line in open(path):
             body = line.split("#")[0].strip()
-            if body:
+            if body and not body.startswith("key "):
                 key = " ".join(body.split(":")[0].split())
                 entries[key] = line.rstrip("\n")
     return entries
+
+
+def read_key(path):
+    """The key lines of a table file ('' when it has none)."""
+    if not os.path.exists(path):
+        return ""
+    return "".join(" ".join(l.split("#")[0].split()) + "\n" for l in open(path)
+                   if l.split("#")[0].strip().startswith("key "))
 
 
 def write_table(path, entries, header):
@@ -303,12 +311,19 @@ def main(argv=None):
     names = a.classes or (HEADLINE if a.headline else list(CLASSES))
     T._lib()
     props = torch.cuda.get_device_properties(0)
+    key = T.table_key(0)  # the library only uses a table whose key lines match it
     header = ("# tile table written by paper_2208_08088_amd.autotune\n"
-              "# device: %s (%s, %d CUs); hip %s; libtsmm %d; %s\n"
+              "# device: %s (%s, %d CUs); torch hip %s; %s\n"
+              "%s"
               "# layout dtype mode kc nt mclass : kernel rows_per_wave waves_per_wg wg_per_cu splitk nsplit\n"
               % (props.name, getattr(props, "gcnArchName", "?"), props.multi_processor_count,
-                 torch.version.hip, T.version(), time.strftime("%Y-%m-%d")))
+                 torch.version.hip, time.strftime("%Y-%m-%d"), key))
     entries = read_table(a.out)
+    if entries and read_key(a.out) != key:
+        log = print
+        log("[autotune] %s was tuned for %r; retuning every class for %r"
+            % (a.out, read_key(a.out), key), flush=True)
+        entries = {}
     log = lambda s: print(s, flush=True)
     for name in names:
         spec = CLASSES[name]

@@ -5,7 +5,9 @@
 Every translation unit is compiled with hipcc for gfx950 only, then linked
 into ``paper_2208_08088_amd/libtsmm.so``.  Objects live in
 ``paper_2208_08088_amd/_build/`` and are rebuilt when a source or header is
-newer, or always with ``--force``.
+newer, or always with ``--force``.  The benchmark's bandwidth-ceiling
+kernels (``ceiling/k_ceiling.hip``) are built the same way into
+``paper_2208_08088_amd/libtsmm_ceiling.so``, a library of their own.
 """
 from __future__ import annotations
 
@@ -21,6 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtsmm.so")
+CEIL_SRC = os.path.join(HERE, "ceiling", "k_ceiling.hip")
+CEIL_LIB = os.path.join(HERE, "libtsmm_ceiling.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 ARCH = "gfx950"
 
@@ -82,7 +86,19 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = True) ->
         os.replace(tmp, LIB)
         if verbose:
             print("[build] linked %s" % LIB, flush=True)
+    build_ceiling(force)
     return LIB
+
+
+def build_ceiling(force: bool = False) -> str:
+    """The benchmark's bandwidth-ceiling kernels, a library of their own."""
+    if force or not os.path.exists(CEIL_LIB) or os.path.getmtime(CEIL_LIB) < os.path.getmtime(CEIL_SRC):
+        tmp = CEIL_LIB + ".tmp%d" % os.getpid()
+        r = subprocess.run([HIPCC, *CFLAGS, "-shared", CEIL_SRC, "-o", tmp], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("hipcc failed for k_ceiling.hip:\n%s" % (r.stdout + r.stderr))
+        os.replace(tmp, CEIL_LIB)
+    return CEIL_LIB
 
 
 def main(argv=None):

@@ -55,6 +55,36 @@ int log_level() {
     return lvl;
 }
 
+// Device and pinned-host allocations of the library go through here.
+// TSMM_FAIL_ALLOC (a comma-separated list of allocation names: pack,
+// pack_a, workspace, batched) makes the named allocations fail as if the
+// device were out of memory, so that the error paths can be exercised.
+bool alloc_fails(const char *what) {
+    const char *s = getenv("TSMM_FAIL_ALLOC");
+    if (!s || !*s) return false;
+    const size_t n = strlen(what);
+    for (const char *p = s; *p;) {
+        const char *e = strchr(p, ',');
+        const size_t len = e ? (size_t)(e - p) : strlen(p);
+        if (len == n && strncmp(p, what, n) == 0) return true;
+        if (!e) break;
+        p = e + 1;
+    }
+    return false;
+}
+
+hipError_t dev_malloc(void **ptr, size_t bytes, const char *what) {
+    *ptr = nullptr;
+    if (alloc_fails(what)) return hipErrorOutOfMemory;
+    return hipMalloc(ptr, bytes);
+}
+
+hipError_t host_malloc_pinned(void **ptr, size_t bytes, const char *what) {
+    *ptr = nullptr;
+    if (alloc_fails(what)) return hipErrorOutOfMemory;
+    return hipHostMalloc(ptr, bytes, hipHostMallocDefault);
+}
+
 bool valid_dtype(int d) { return d == TSMM_F64 || d == TSMM_F32 || d == TSMM_BF16; }
 bool valid_layout(int l) { return l == TSMM_OP_N || l == TSMM_OP_T || l == TSMM_COLMAJOR; }
 bool valid_mode(int m) { return m == TSMM_MODE_NATIVE || m == TSMM_MODE_BF16X3 || m == TSMM_MODE_BF16X6; }
@@ -128,7 +158,14 @@ tsmm_status query_caps(tsmm_device_caps *caps, int *device) {
 // op N: kc = packed k class, nt = 16-column tiles class, mclass = row class.
 // op T: kc = 16-row tiles of the output (m), nt = 16-column tiles (n),
 //       mclass = class of the shared dimension.
-// '#' starts a comment.
+// '#' starts a comment.  Three key lines say what the timings were taken
+// on:
+//   key arch gfx<N>        the device architecture
+//   key hip <version>      hipRuntimeGetVersion() of the runtime
+//   key libtsmm <version>  tsmm_version() of the library
+// A table whose keys are missing or differ from the running library and
+// runtime is not used (its tiles were timed for other code); entries apply
+// only to plans for the keyed architecture.
 
 // Tile-table layout "B": the entry of batched plans of one dtype (key
 // fields kc, nt, mclass are 0).
@@ -147,7 +184,14 @@ struct Table {
     std::string path;
     bool loaded = false;
     std::string error;
+    int arch = 0;  // from "key arch gfx<N>"
 };
+
+int hip_runtime_version() {
+    int v = 0;
+    if (hipRuntimeGetVersion(&v) != hipSuccess) v = 0;
+    return v;
+}
 
 std::string library_dir() {
     Dl_info info;
@@ -209,11 +253,27 @@ Table &table() {
         }
         std::string line;
         int lineno = 0;
+        long hip = -1, lib = -1;
         while (std::getline(f, line)) {
             ++lineno;
             size_t h = line.find('#');
             if (h != std::string::npos) line.resize(h);
             if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+            std::istringstream ks(line);
+            std::string w0, w1, w2;
+            if ((ks >> w0) && w0 == "key") {
+                bool ok = static_cast<bool>(ks >> w1 >> w2);
+                if (ok && w1 == "arch") ok = sscanf(w2.c_str(), "gfx%d", &tab.arch) == 1;
+                else if (ok && w1 == "hip") hip = atol(w2.c_str());
+                else if (ok && w1 == "libtsmm") lib = atol(w2.c_str());
+                else ok = false;
+                if (!ok) {
+                    tab.error = tab.path + ":" + std::to_string(lineno) + ": malformed key line";
+                    tab.entries.clear();
+                    return;
+                }
+                continue;
+            }
             TableKey k;
             tsmm_tile t;
             if (!parse_table_line(line, &k, &t)) {
@@ -223,9 +283,50 @@ Table &table() {
             }
             tab.entries[k] = t;
         }
+        char why[256] = "";
+        if (tab.arch <= 0 || hip < 0 || lib < 0)
+            snprintf(why, sizeof why, "%s has no key lines (arch, hip, libtsmm)", tab.path.c_str());
+        else if (lib != tsmm_version())
+            snprintf(why, sizeof why, "%s was tuned for libtsmm %ld, this is %d", tab.path.c_str(), lib,
+                     (int)tsmm_version());
+        else if (hip != hip_runtime_version())
+            snprintf(why, sizeof why, "%s was tuned on HIP runtime %ld, this is %d", tab.path.c_str(), hip,
+                     hip_runtime_version());
+        if (why[0]) {
+            tab.error = why;
+            tab.entries.clear();
+            if (log_level() >= 1) fprintf(stderr, "[tsmm] tile table not used: %s; built-in tiles\n", why);
+            return;
+        }
         tab.loaded = true;
     });
     return tab;
+}
+
+// Is the table usable for a plan on a device of this architecture?  The
+// reason goes to tsmm_last_error when it is not.
+bool table_usable(const tsmm_device_caps &caps) {
+    Table &tab = table();
+    if (!tab.loaded) return false;
+    if (tab.arch != caps.gcn_arch) {
+        static std::once_flag once;
+        std::call_once(once, [&] {
+            if (log_level() >= 1)
+                fprintf(stderr, "[tsmm] tile table %s is for gfx%d, the plan's device is gfx%d; built-in tiles\n",
+                        tab.path.c_str(), tab.arch, caps.gcn_arch);
+        });
+        return false;
+    }
+    return true;
+}
+
+std::string table_unusable_reason(const tsmm_device_caps &caps) {
+    Table &tab = table();
+    if (!tab.loaded) return tab.error;
+    char buf[320];
+    snprintf(buf, sizeof buf, "%s is for gfx%d, the plan's device is gfx%d", tab.path.c_str(), tab.arch,
+             caps.gcn_arch);
+    return buf;
 }
 
 int mclass_of(int64_t m) { return m < (1 << 16) ? 0 : (m < (1 << 21) ? 1 : 2); }
@@ -600,10 +701,10 @@ bool valid_chunk_rows(int c) { return c >= kBatchChunkMin && c <= kBatchChunkMax
 
 // Chunk size of batched plans of `dtype`: the table's batched entry, else
 // the default.
-int batched_table_chunk(tsmm_dtype dtype, bool *from_table) {
+int batched_table_chunk(tsmm_dtype dtype, const tsmm_device_caps &caps, bool *from_table) {
     *from_table = false;
     Table &tab = table();
-    if (tab.loaded) {
+    if (table_usable(caps)) {
         auto it = tab.entries.find(TableKey{kLayoutBatched, dtype, TSMM_MODE_NATIVE, 0, 0, 0});
         if (it != tab.entries.end() && valid_chunk_rows(it->second.chunk_rows)) {
             *from_table = true;
@@ -644,7 +745,7 @@ tsmm_status set_batched_tile(tsmm_plan_s &p, const tsmm_tile &t) {
         return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take only chunk_rows (%d waves, 1 workgroup per CU)",
                     kBatchWaves);
     bool from_table = false;
-    const int chunk = t.chunk_rows ? t.chunk_rows : batched_table_chunk(p.dtype, &from_table);
+    const int chunk = t.chunk_rows ? t.chunk_rows : batched_table_chunk(p.dtype, p.caps, &from_table);
     if (!valid_chunk_rows(chunk))
         return fail(TSMM_ERROR_INVALID_VALUE, "chunk_rows %d: a power of two in %d..%d", chunk, kBatchChunkMin,
                     kBatchChunkMax);
@@ -713,7 +814,7 @@ tsmm_status choose_tile(tsmm_plan_s &p) {
             g_err.clear();
         }
     }
-    if (tab.loaded) {
+    if (table_usable(p.caps)) {
         const TableKey key = plan_key(p);
         auto it = tab.entries.find(key);
         if (it != tab.entries.end() && eligible(p, it->second.kernel)) {
@@ -727,9 +828,9 @@ tsmm_status choose_tile(tsmm_plan_s &p) {
                 fprintf(stderr, "[tsmm] table entry rejected (%s); using the default tile\n", g_err.c_str());
         }
     } else if (getenv("TSMM_STRICT_TABLE")) {
-        return fail(TSMM_ERROR_TABLE, "tile table: %s", tab.error.c_str());
+        return fail(TSMM_ERROR_TABLE, "tile table: %s", table_unusable_reason(p.caps).c_str());
     } else if (log_level() >= 2) {
-        fprintf(stderr, "[tsmm] tile table not used: %s\n", tab.error.c_str());
+        fprintf(stderr, "[tsmm] tile table not used: %s\n", table_unusable_reason(p.caps).c_str());
     }
     // no table entry: the wide kernels where they apply (they read and split
     // A once at any n), else the natural family
@@ -799,7 +900,24 @@ const char *tsmm_status_string(tsmm_status s) {
 
 const char *tsmm_last_error(void) { return g_err.c_str(); }
 
-int32_t tsmm_version(void) { return 10000; }
+int32_t tsmm_version(void) { return 10100; }
+
+tsmm_status tsmm_table_key(int32_t gcn_arch, char *buf, size_t len) {
+    g_err.clear();
+    if (!buf || len == 0) return fail(TSMM_ERROR_INVALID_VALUE, "NULL buffer");
+    if (gcn_arch < 0) return fail(TSMM_ERROR_INVALID_VALUE, "bad architecture %d", (int)gcn_arch);
+    if (gcn_arch == 0) {
+        tsmm_device_caps caps;
+        int dev = 0;
+        const tsmm_status st = query_caps(&caps, &dev);
+        if (st != TSMM_SUCCESS) return st;
+        gcn_arch = caps.gcn_arch;
+    }
+    const int n = snprintf(buf, len, "key arch gfx%d\nkey hip %d\nkey libtsmm %d\n", (int)gcn_arch,
+                           hip_runtime_version(), (int)tsmm_version());
+    if (n < 0 || (size_t)n >= len) return fail(TSMM_ERROR_INVALID_VALUE, "buffer of %zu bytes is too small", len);
+    return TSMM_SUCCESS;
+}
 
 // ------------------------------------------------------------------ pack
 
@@ -886,7 +1004,7 @@ tsmm_status tsmm_pack(const void *B, int64_t k, int64_t n, tsmm_layout layout, t
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(TSMM_ERROR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
     P->device = dev;
-    e = hipMalloc(&P->dev, L.bytes);
+    e = dev_malloc(&P->dev, L.bytes, "pack");
     if (e != hipSuccess) return fail(TSMM_ERROR_OUT_OF_MEMORY, "hipMalloc(%zu): %s", L.bytes, hipGetErrorString(e));
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(P->dev);
@@ -998,7 +1116,7 @@ tsmm_status tsmm_pack_a(const void *A, int64_t m, int64_t k, int64_t lda, tsmm_d
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(TSMM_ERROR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
     P->device = dev;
-    e = hipMalloc(&P->dev, P->L.bytes);
+    e = dev_malloc(&P->dev, P->L.bytes, "pack_a");
     if (e != hipSuccess)
         return fail(TSMM_ERROR_OUT_OF_MEMORY, "hipMalloc(%zu): %s", P->L.bytes, hipGetErrorString(e));
     e = launch_pack_a(dtype, terms, A, lda, P->dev, m, k, alpha, static_cast<hipStream_t>(stream));
@@ -1165,7 +1283,7 @@ tsmm_status ensure_workspace(tsmm_plan_s &p) {
     p.workspace = nullptr;
     p.owns_workspace = false;
     void *ws = nullptr;
-    hipError_t e = hipMalloc(&ws, p.workspace_bytes);
+    hipError_t e = dev_malloc(&ws, p.workspace_bytes, "workspace");
     if (e != hipSuccess)
         return fail(TSMM_ERROR_OUT_OF_MEMORY, "workspace (%zu bytes): %s", p.workspace_bytes, hipGetErrorString(e));
     p.workspace = ws;
@@ -1578,15 +1696,20 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
     // compute unit (two wavefronts per SIMD); chunks are handed out at run
     // time, so the grid only needs to fill the device
     bool from_table = false;
-    const int chunk = batched_table_chunk(dtype, &from_table);
+    const int chunk = batched_table_chunk(dtype, p->caps, &from_table);
     p->tile = tsmm_tile{TSMM_KERNEL_BATCHED, 0, kBatchWaves, 1, 1, 1, chunk};
     p->tile_from_table = from_table;
     p->block = 64 * kBatchWaves;
 
-    hipError_t e1 = hipMalloc(&p->d_desc, sizeof(BatchDesc) * count);
-    hipError_t e2 = hipMalloc(&p->d_inst_start, sizeof(int64_t) * (count + 1));
-    hipError_t e3 = hipMalloc(&p->d_ctr, sizeof(int32_t) * 2);
-    hipError_t e5 = hipHostMalloc(&p->h_desc, sizeof(BatchDesc) * count, hipHostMallocDefault);
+    void *dd = nullptr, *ds = nullptr, *dc = nullptr, *hd = nullptr;
+    hipError_t e1 = dev_malloc(&dd, sizeof(BatchDesc) * count, "batched");
+    hipError_t e2 = dev_malloc(&ds, sizeof(int64_t) * (count + 1), "batched");
+    hipError_t e3 = dev_malloc(&dc, sizeof(int32_t) * 2, "batched");
+    hipError_t e5 = host_malloc_pinned(&hd, sizeof(BatchDesc) * count, "batched");
+    p->d_desc = dd;
+    p->d_inst_start = ds;
+    p->d_ctr = dc;
+    p->h_desc = hd;
     if (e1 || e2 || e3 || e5) {
         tsmm_plan_destroy(p.release());
         return fail(TSMM_ERROR_OUT_OF_MEMORY, "batched plan allocation failed");

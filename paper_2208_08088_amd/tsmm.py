@@ -76,6 +76,7 @@ SIGNATURES = [
     ("tsmm_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("tsmm_last_error", ctypes.c_char_p, []),
     ("tsmm_version", _I32, []),
+    ("tsmm_table_key", ctypes.c_int, [_I32, ctypes.c_char_p, _SZ]),
     ("tsmm_pack", ctypes.c_int, [_VP, _I64, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _PVP]),
     ("tsmm_packed_bytes", ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
     ("tsmm_unpack", ctypes.c_int, [_VP, _VP, _VP]),
@@ -156,6 +157,14 @@ def _need_cuda(t, name, dtype=None, shape=None, colmajor=False):
 
 def version():
     return _lib().tsmm_version()
+
+
+def table_key(gcn_arch: int = 0) -> str:
+    """The key lines a tile table needs to be used by this library on this
+    runtime (tsmm_table_key); gcn_arch 0 means the current device's."""
+    buf = ctypes.create_string_buffer(256)
+    _check(_lib().tsmm_table_key(int(gcn_arch), buf, 256), "tsmm_table_key")
+    return buf.value.decode()
 
 
 # ---------------------------------------------------------------- packed
@@ -278,13 +287,13 @@ class Plan:
     def set_mode(self, mode: str):
         _check(_lib().tsmm_plan_set_mode(self._h, _MODES[mode]), "tsmm_plan_set_mode")
         self.mode = _MODES[mode]
-        self._ws = None
+        self._drop_workspace()
         return self
 
     def set_tile(self, kernel=0, rows_per_wave=0, waves_per_wg=0, wg_per_cu=0, splitk=0, nsplit=0, chunk_rows=0):
         _set_tile(self._h, kernel=kernel, rows_per_wave=rows_per_wave, waves_per_wg=waves_per_wg,
                   wg_per_cu=wg_per_cu, splitk=splitk, nsplit=nsplit, chunk_rows=chunk_rows)
-        self._ws = None
+        self._drop_workspace()
         return self
 
     def get_tile(self) -> dict:
@@ -302,10 +311,12 @@ class Plan:
         _need_cuda(C, "C", _OUT_OF_DT[self.dtype], (self.m, self.n), colmajor=cm)
         lib = _lib()
         _check(lib.tsmm_plan_set_stream(self._h, _stream()), "tsmm_plan_set_stream")
+        # the candidates run on plan-owned scratch, never on this binding's
+        # tensor, which is released first
+        self._drop_workspace()
         ms = ctypes.c_double(0.0)
         _check(lib.tsmm_plan_tune(self._h, _ptr(A), packed.handle, _ptr(C), int(reps), ctypes.byref(ms)),
                "tsmm_plan_tune")
-        self._ws = None
         return ms.value
 
     def workspace_bytes(self) -> int:
@@ -322,6 +333,14 @@ class Plan:
             key, _, val = kv.partition("=")
             out[key] = val
         return out
+
+    def _drop_workspace(self):
+        """Detach this binding's workspace tensor from the C plan, then let
+        it go: the plan must never keep a pointer into memory that torch's
+        allocator may hand to another tensor."""
+        if self._ws is not None:
+            _check(_lib().tsmm_plan_set_workspace(self._h, None, 0), "tsmm_plan_set_workspace")
+            self._ws = None
 
     def _ensure_workspace(self):
         nb = self.workspace_bytes()

@@ -47,7 +47,7 @@ def test_status_strings_and_version(T):
     for s in range(8):
         assert lib.tsmm_status_string(s)
     assert lib.tsmm_status_string(99) == b"unknown status"
-    assert lib.tsmm_version() == 10000
+    assert lib.tsmm_version() == 10100
 
 
 def test_pack_validates_before_touching_hip(T):
@@ -186,13 +186,14 @@ def test_set_mode_rules(T):
     assert e.value.status == T.NOT_SUPPORTED
 
 
-def test_tile_table_parsing(tmp_path):
+def test_tile_table_parsing(T, tmp_path):
     # a table is read once per process: check it in a child process
     import subprocess
     import sys
+    key = T.table_key(950)
     tab = tmp_path / "t.txt"
-    tab.write_text("# comment\nN f64 native 8 1 2 : stream 2 4 6 1 1\nT f64 native 4 4 2 : splitk 4 4 2 300 1\n"
-                   "B f32 native 0 0 0 : batched 0 8 1 1 1 2048\n")
+    tab.write_text("# comment\n" + key + "N f64 native 8 1 2 : stream 2 4 6 1 1\n"
+                   "T f64 native 4 4 2 : splitk 4 4 2 300 1\nB f32 native 0 0 0 : batched 0 8 1 1 1 2048\n")
     code = (
         "from paper_2208_08088_amd import tsmm as T\n"
         "p = T.plan_with_caps(1 << 23, 8, 8, 'N'); i = p.info(); t = p.get_tile()\n"
@@ -204,7 +205,7 @@ def test_tile_table_parsing(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True)
     assert out.returncode == 0 and "ok" in out.stdout, out.stderr
     bad = tmp_path / "bad.txt"
-    bad.write_text("N f64 native 8 1 2 : nosuchkernel 2 4 6 1 1\n")
+    bad.write_text(key + "N f64 native 8 1 2 : nosuchkernel 2 4 6 1 1\n")
     code2 = ("from paper_2208_08088_amd import tsmm as T\n"
              "p = T.plan_with_caps(1 << 23, 8, 8, 'N'); assert p.info()['table'] == '0'\n"
              "print('ok')\n")
@@ -219,10 +220,62 @@ def test_tile_table_parsing(tmp_path):
     # the batched layout takes that kernel
     for line in ("B f32 native 0 0 0 : batched 0 8 1 1 1\n", "B f32 native 0 0 0 : stream 0 8 1 1 1 2048\n",
                  "N f64 native 8 1 2 : batched 2 4 6 1 1\n"):
-        bad.write_text("N f64 native 8 1 2 : stream 2 4 6 1 1\n" + line)
+        bad.write_text(key + "N f64 native 8 1 2 : stream 2 4 6 1 1\n" + line)
         out = subprocess.run([sys.executable, "-c", code2], cwd=ROOT, env=dict(os.environ, TSMM_TILE_TABLE=str(bad)),
                              capture_output=True, text=True)
         assert out.returncode == 0 and "ok" in out.stdout, (line, out.stderr)
+
+
+def test_tile_table_keys(T, tmp_path):
+    # a table is used only where its key lines (architecture, HIP runtime,
+    # library version) match; otherwise the plan takes built-in tiles, or
+    # fails with TSMM_ERROR_TABLE under TSMM_STRICT_TABLE
+    import subprocess
+    import sys
+    key = T.table_key(950)
+    lines = dict(l.split()[1:] for l in key.splitlines())
+    assert lines["arch"] == "gfx950" and int(lines["libtsmm"]) == T.version() and int(lines["hip"]) > 0
+    with pytest.raises(T.TsmmError):
+        T.table_key(-1)
+    entry = "N f64 native 8 1 2 : stream 2 4 6 1 1\n"
+    probe = ("from paper_2208_08088_amd import tsmm as T\n"
+             "p = T.plan_with_caps(1 << 23, 8, 8, 'N', gcn_arch=%d); print('table=' + p.info()['table'])\n")
+
+    def run(text, arch=950, strict=False):
+        tab = tmp_path / "k.txt"
+        tab.write_text(text)
+        env = dict(os.environ, TSMM_TILE_TABLE=str(tab), TSMM_LOG="1")
+        if strict:
+            env["TSMM_STRICT_TABLE"] = "1"
+        return subprocess.run([sys.executable, "-c", probe % arch], cwd=ROOT, env=env, capture_output=True,
+                              text=True)
+
+    out = run(key + entry)
+    assert out.returncode == 0 and "table=1" in out.stdout, out.stderr
+    foreign = {
+        "another architecture": (key.replace("gfx950", "gfx942"), "is for gfx942"),
+        "another library version": (key.replace("libtsmm %d" % T.version(), "libtsmm 10000"), "libtsmm 10000"),
+        "another HIP runtime": (key.replace("hip %s" % lines["hip"], "hip 60000000"), "HIP runtime 60000000"),
+        "no key lines": ("", "no key lines"),
+    }
+    for what, (k, why) in foreign.items():
+        out = run(k + entry)
+        assert out.returncode == 0 and "table=0" in out.stdout, (what, out.stderr)
+        assert "tile table" in out.stderr and why in out.stderr, (what, out.stderr)  # the fallback is logged
+        out = run(k + entry, strict=True)
+        assert out.returncode != 0 and "tile table" in out.stderr and why in out.stderr, (what, out.stderr)
+    # the keyed architecture only: a plan for another device takes built-in tiles
+    out = run(key + entry, arch=942)
+    assert out.returncode == 0 and "table=0" in out.stdout, out.stderr
+    out = run("key arch gfx950\nkey hip\n" + entry, strict=True)
+    assert out.returncode != 0 and "malformed key line" in out.stderr
+
+
+def test_shipped_tile_table_is_keyed_for_this_library(T):
+    # the install-time table in the package carries this library's version
+    path = os.path.join(ROOT, "paper_2208_08088_amd", "tile_table.txt")
+    keys = [l.split()[1:] for l in open(path) if l.startswith("key ")]
+    assert dict(keys)["libtsmm"] == str(T.version()) and dict(keys)["arch"] == "gfx950"
 
 
 def test_valu64_tile_rules(T):

@@ -56,7 +56,7 @@ def test_written_keys_are_the_planner_keys(A, tmp_path):
             layout, A._DT_NAME[dt], mode, kc, nt, mcl, A._KERNEL_NAME[t["kernel"]], t["rows_per_wave"],
             t["waves_per_wg"], t["wg_per_cu"], t["splitk"], t["nsplit"]))
     tab = tmp_path / "t.txt"
-    tab.write_text("\n".join(lines) + "\n")
+    tab.write_text(A.T.table_key(950) + "\n".join(lines) + "\n")
     code = ("import torch\n"
             "from paper_2208_08088_amd import autotune as A\n"
             "for name, (layout, dt, mode, m, n, k) in A.CLASSES.items():\n"

@@ -130,6 +130,20 @@ def test_every_tile_gives_the_same_bits(k, n):
                     assert e.status == T.NOT_SUPPORTED
                     continue
                 assert np.array_equal(C, ref), (rt, waves, wpc)
+    # column groups (nsplit): each group of a row block is its own
+    # workgroup; the per-element order of the products does not change
+    for ns in (2, 4, 8):
+        if ns > (n + 15) // 16:
+            continue
+        for rt in (1, 2):
+            try:
+                C, p = run(A, B, C0, 1.5, 0.5, tile=dict(kernel=T.KERNEL_STREAM, rows_per_wave=rt, waves_per_wg=4,
+                                                            wg_per_cu=1, nsplit=ns))
+            except T.TsmmError as e:
+                assert e.status == T.NOT_SUPPORTED
+                continue
+            assert p.info()["nsplit"] == str(ns)
+            assert np.array_equal(C, ref), ("nsplit", ns, rt)
     C, _ = run(A, B, C0, 1.5, 0.5, tile=dict(kernel=T.KERNEL_SIMPLE))
     assert_normwise(C, oracle.gemm_n(A, B, C0, 1.5, 0.5), 1e-12)
 

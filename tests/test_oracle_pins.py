@@ -312,3 +312,56 @@ def test_pack_a_split_reconstructs_the_scaled_value():
     for i in range(0, 64, 7):
         for j in range(16):
             assert rec[i, j] == float(_rn(alpha, A[i, j], True))
+
+
+def _two_product(a, b):
+    """Error-free product (Dekker, with Veltkamp's split): a*b == p + e
+    exactly for binary64 a, b far from overflow and underflow."""
+    c = 134217729.0  # 2^27 + 1
+    t = c * a
+    ah = t - (t - a)
+    al = a - ah
+    t = c * b
+    bh = t - (t - b)
+    bl = b - bh
+    p = a * b
+    e = ((ah * bh - p) + ah * bl + al * bh) + al * bl
+    return p, e
+
+
+def test_two_product_is_exact():
+    # checked against exact rationals on random pairs
+    a = I.host_normal((64,), 5, 1)
+    b = I.host_normal((64,), 5, 2) * 1e3
+    p, e = _two_product(a, b)
+    for x, y, pp, ee in zip(a, b, p, e):
+        assert Fraction(x) * Fraction(y) == Fraction(pp) + Fraction(ee)
+
+
+def test_op_t_oracle_error_at_the_full_reduction_length():
+    # The reduction workload's shared dimension is K = 2^22 with normal(0, 1)
+    # entries, where the GPU bar is a normwise relative error of 1e-12.  The
+    # oracle sums in binary64 recursively (one rounding per step); here its
+    # outputs are compared with the correctly rounded exact dot products
+    # (every product split exactly into two binary64 values, the 2K terms
+    # summed exactly by math.fsum).  Each output lies within the textbook
+    # bound gamma_K * sum|a*b|, and the normwise error is far below 1e-12,
+    # so the oracle can referee that bar.  (Each output depends only on its
+    # own columns, so a 4-column slice gives the full problem's bits.)
+    import math
+    K = 1 << 22
+    A = I.host_normal((K, 4), I.BASE_SEED, 21)
+    B = I.host_normal((K, 4), I.BASE_SEED, 22)
+    C = oracle.gemm_t(A, B)
+    exact = np.empty((4, 4))
+    absum = np.empty((4, 4))
+    for i in range(4):
+        for j in range(4):
+            p, e = _two_product(A[:, i], B[:, j])
+            exact[i, j] = math.fsum(np.concatenate([p, e]).tolist())
+            absum[i, j] = math.fsum(np.abs(p).tolist())
+    gam = K * 2.0 ** -53 / (1 - K * 2.0 ** -53)
+    assert np.all(np.abs(C - exact) <= gam * absum * (1 + 1e-6))
+    err = np.linalg.norm(C - exact) / np.linalg.norm(exact)
+    print("oracle normwise error at K = 2^22 (normal inputs): %.2e" % err)
+    assert 0.0 < err <= 2e-13
