@@ -140,7 +140,8 @@ def test_every_tile_gives_the_same_bits(k, n):
                 C, p = run(A, B, C0, 1.5, 0.5, tile=dict(kernel=T.KERNEL_STREAM, rows_per_wave=rt, waves_per_wg=4,
                                                             wg_per_cu=1, nsplit=ns))
             except T.TsmmError as e:
-                assert e.status == T.NOT_SUPPORTED
+                # no instantiation, or a split through a column interleave group
+                assert e.status in (T.NOT_SUPPORTED, T.INVALID_VALUE), e
                 continue
             assert p.info()["nsplit"] == str(ns)
             assert np.array_equal(C, ref), ("nsplit", ns, rt)

@@ -200,7 +200,10 @@ def test_tiny_A_lo_term_underflow_is_bounded():
     # below are those of the two- and three-term splits.
     m, k, n = 2048, 64, 32
     A, B = precision_inputs(m, k, n, 52)
-    A = I.host_uniform((m, k), 52, 9, dtype=np.float32)
+    # magnitudes in [1, 2) with random signs, so that the shifted values stay
+    # normal binary32 numbers (at least 2^-115) and the shift is exact
+    sign = np.where(I.host_uniform((m, k), 52, 8) < 0, -1.0, 1.0)
+    A = (sign * I.host_uniform((m, k), 52, 9, 1.0, 2.0)).astype(np.float32)
     for shift, tol6 in ((-100, 1e-6), (-115, 2e-5)):
         As = np.ldexp(A.astype(np.float64), shift).astype(np.float32)
         assert np.array_equal(np.ldexp(As.astype(np.float64), -shift), A.astype(np.float64))  # exact shift
