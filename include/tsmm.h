@@ -378,6 +378,27 @@ void tsmm_plan_destroy(tsmm_plan_t plan);
 tsmm_status tsmm_execute(tsmm_plan_t plan, const void *A, tsmm_packed_t packed,
                          void *C, double alpha, double beta);
 
+/* tsmm_execute for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, natural strides, same kernels and the same results, bit
+ * for bit, as tsmm_execute with the same plan.  Split-k plans (op T; k-slab
+ * plans with parts of the k range) keep their partial sums in the
+ * library's static device scratch instead of a workspace: 32 MiB per
+ * device (TSMM_NOALLOC_SCRATCH_BYTES), alive until the process ends, its
+ * device address looked up on the first call on each device.  This call
+ * never allocates (no hipMalloc, no library allocation); the plan's own
+ * workspace is neither used nor created.  Every call on one device shares
+ * that scratch and leaves its last contents there (every partial is written
+ * before it is read, so nothing needs clearing): calls that overlap in time
+ * on one device -- concurrent streams, or host threads -- race and must be
+ * ordered by the caller.
+ * Errors: as tsmm_execute; NOT_SUPPORTED when the plan needs more scratch
+ * than TSMM_NOALLOC_SCRATCH_BYTES (plan with fewer split-k parts, or use
+ * tsmm_execute with a workspace); INVALID_VALUE for a batched plan. */
+#define TSMM_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+tsmm_status tsmm_execute_noalloc(tsmm_plan_t plan, const void *A, tsmm_packed_t packed, void *C,
+                                 double alpha, double beta);
+
 /* tsmm_execute with leading dimensions (strided operands, as in BLAS):
  *   lda  TSMM_OP_N: row stride of A (>= k); TSMM_OP_T: row stride of the
  *        k x m A (>= m); TSMM_COLMAJOR: column stride of A (>= m).

@@ -1324,9 +1324,14 @@ tsmm_status tsmm_execute(tsmm_plan_t p, const void *A, tsmm_packed_t packed, voi
     return tsmm_execute_ld(p, A, lda, packed, C, ldc, alpha, beta);
 }
 
-tsmm_status tsmm_execute_ld(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_t packed, void *C, int64_t ldc,
-                            double alpha, double beta) {
-    g_err.clear();
+}  // extern "C"
+
+namespace {
+// tsmm_execute_ld with the split-k partial sums in `scratch` (at least the
+// plan's workspace bytes) when it is not NULL, else in the plan's
+// workspace (the caller's, or allocated on first use).
+tsmm_status execute_core(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_t packed, void *C, int64_t ldc,
+                         double alpha, double beta, void *scratch) {
     if (!p || !packed) return fail(TSMM_ERROR_INVALID_VALUE, "NULL plan or packed operand");
     if (p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan: use tsmm_execute_batched");
     if (p->device < 0) return fail(TSMM_ERROR_NO_DEVICE, "plan was built for explicit caps, not a device");
@@ -1431,19 +1436,20 @@ tsmm_status tsmm_execute_ld(tsmm_plan_t p, const void *A, int64_t lda, tsmm_pack
         const bool il = frag4_pg(p->dtype, p->NT, p->n) > 1;
         if (packed->L.KC != p->KC || packed->L.NT != p->NT)
             return fail(TSMM_ERROR_SHAPE_MISMATCH, "packed operand has no image for the k-slab kernel");
-        tsmm_status st = ensure_workspace(*p);
+        tsmm_status st = scratch ? TSMM_SUCCESS : ensure_workspace(*p);
         if (st != TSMM_SUCCESS) return st;
         e = launch_slab(p->dtype, p->NT, p->tile.rows_per_wave, p->vec, il, A, base + packed->L.off_frag, C,
-                        static_cast<double *>(p->workspace), p->m, p->n, p->k, lda, ldc, p->KC, alpha, beta,
-                        p->tile.splitk, p->grid, s);
+                        static_cast<double *>(scratch ? scratch : p->workspace), p->m, p->n, p->k, lda, ldc, p->KC,
+                        alpha, beta, p->tile.splitk, p->grid, s);
         break;
     }
     case TSMM_KERNEL_SPLITK: {
-        tsmm_status st = ensure_workspace(*p);
+        tsmm_status st = scratch ? TSMM_SUCCESS : ensure_workspace(*p);
         if (st != TSMM_SUCCESS) return st;
         e = launch_splitk(p->KC, p->NT, p->tile.rows_per_wave, static_cast<const double *>(A),
-                          static_cast<const double *>(packed->ref), static_cast<double *>(p->workspace),
-                          static_cast<double *>(C), p->k, p->m, p->n, p->tile.splitk, alpha, beta, p->block, s);
+                          static_cast<const double *>(packed->ref),
+                          static_cast<double *>(scratch ? scratch : p->workspace), static_cast<double *>(C), p->k,
+                          p->m, p->n, p->tile.splitk, alpha, beta, p->block, s);
         break;
     }
     default:
@@ -1451,6 +1457,36 @@ tsmm_status tsmm_execute_ld(tsmm_plan_t p, const void *A, int64_t lda, tsmm_pack
         break;
     }
     return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "kernel launch");
+}
+}  // namespace
+
+extern "C" {
+
+tsmm_status tsmm_execute_ld(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_t packed, void *C, int64_t ldc,
+                            double alpha, double beta) {
+    g_err.clear();
+    return execute_core(p, A, lda, packed, C, ldc, alpha, beta, nullptr);
+}
+
+tsmm_status tsmm_execute_noalloc(tsmm_plan_t p, const void *A, tsmm_packed_t packed, void *C, double alpha,
+                                 double beta) {
+    g_err.clear();
+    if (!p || !packed) return fail(TSMM_ERROR_INVALID_VALUE, "NULL plan or packed operand");
+    if (p->batched) return fail(TSMM_ERROR_INVALID_VALUE, "batched plan: use tsmm_execute_batched");
+    if (p->device < 0) return fail(TSMM_ERROR_NO_DEVICE, "plan was built for explicit caps, not a device");
+    if (p->workspace_bytes > kScratchBytes)
+        return fail(TSMM_ERROR_NOT_SUPPORTED,
+                    "the plan needs %zu bytes of scratch; the static scratch holds %zu (fewer split-k parts, or "
+                    "tsmm_execute with a workspace)",
+                    p->workspace_bytes, kScratchBytes);
+    int64_t nat_a, nat_c;
+    natural_ld(*p, &nat_a, &nat_c);
+    void *scratch = nullptr;
+    if (p->workspace_bytes > 0 && p->m > 0 && p->n > 0 && p->k > 0 && alpha != 0.0) {
+        const hipError_t e = scratch_device_ptr(p->device, &scratch);
+        if (e != hipSuccess) return hip_fail(e, "static scratch address");
+    }
+    return execute_core(p, A, nat_a, packed, C, nat_c, alpha, beta, scratch);
 }
 
 // ------------------------------------------------------ runtime evaluator

@@ -238,6 +238,11 @@ namespace tsmm {
 
 // Pack B (k x n row-major) into the 16x16x4 fragment order.
 // bcol: B is column-major (element (l, j) at l + j*k) instead of row-major.
+// Static device scratch of tsmm_execute_noalloc (k_scratch.hip): bytes, and
+// its device address on a device (looked up once per device).
+constexpr size_t kScratchBytes = TSMM_NOALLOC_SCRATCH_BYTES;
+hipError_t scratch_device_ptr(int device, void **out);
+
 hipError_t launch_pack_frag4(tsmm_dtype dt, bool bcol, const void *B, void *frag, int64_t k, int64_t n,
                              int KC, int NT, bool vec, int pg, hipStream_t s);
 // Split-bf16 pack: column exponents, row-major planes and fragments.

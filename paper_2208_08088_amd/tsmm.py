@@ -97,6 +97,7 @@ SIGNATURES = [
     ("tsmm_plan_destroy", None, [_VP]),
     ("tsmm_execute", ctypes.c_int, [_VP, _VP, _VP, _VP, _DBL, _DBL]),
     ("tsmm_execute_ld", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _I64, _DBL, _DBL]),
+    ("tsmm_execute_noalloc", ctypes.c_int, [_VP, _VP, _VP, _VP, _DBL, _DBL]),
     ("tsmm_pack_a", ctypes.c_int, [_VP, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _DBL, _VP, _PVP]),
     ("tsmm_execute_packed_a", ctypes.c_int, [_VP, _VP, _VP, _VP, _DBL]),
     ("tsmm_plan_batched", ctypes.c_int, [_I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
@@ -421,6 +422,26 @@ def execute(p: Plan, A: torch.Tensor, packed: Packed, C: torch.Tensor, alpha: fl
     _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
     _check(lib.tsmm_execute_ld(p.handle, _ptr(A), lda, packed.handle, _ptr(C), ldc, float(alpha), float(beta)),
            "tsmm_execute_ld")
+    return C
+
+
+def execute_noalloc(p: Plan, A: torch.Tensor, packed: Packed, C: torch.Tensor, alpha: float = 1.0,
+                    beta: float = 0.0) -> torch.Tensor:
+    """C = alpha*op(A)*B + beta*C in place on torch's current stream without
+    any device allocation (tsmm_execute_noalloc): split-k partial sums go to
+    the library's static scratch, never to a workspace.  A and C contiguous
+    (column-major for layout "C")."""
+    in_dt = _TORCH_OF_DT[p.dtype]
+    a_shape = (p.k, p.m) if p.layout == OP_T else (p.m, p.k)
+    cm = p.layout == COLMAJOR
+    _need_cuda(A, "A", in_dt, a_shape, colmajor=cm)
+    _need_cuda(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n), colmajor=cm)
+    if packed.layout == OP_T and packed._keep is not None:
+        _need_cuda(packed._keep, "B")
+    lib = _lib()
+    _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
+    _check(lib.tsmm_execute_noalloc(p.handle, _ptr(A), packed.handle, _ptr(C), float(alpha), float(beta)),
+           "tsmm_execute_noalloc")
     return C
 
 
