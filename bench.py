@@ -207,62 +207,122 @@ def bound_of(bytes_, flops, dt):
     return ("hbm", t_hbm) if t_hbm >= t_cmp else ("mfma", t_cmp)
 
 
-CEIL_GRIDS = (1024, 2048, 4096)  # workgroups of 256 lanes (4, 8, 16 per compute unit)
-CEIL_UNROLLS = (2, 4, 8)          # 16-byte vectors per lane per step
+CEIL_GRIDS = (256, 512, 1024, 2048, 4096)  # workgroups of 256 lanes (1 to 16 per compute unit)
+CEIL_UNROLLS = (2, 4, 8)          # 16-byte vectors per lane per work item
+CEIL_POLICIES = (0, 1)            # cache policy of loads / stores: default, non-temporal
 
 
-def ceilings(torch, nbytes=4 << 30, reps=5):
+def ceilings(torch, nbytes=4 << 30, reps=5, detail=False):
     """Same-run bandwidth ceilings from the hand-written stream kernels of
     libtsmm_ceiling.so over `nbytes` buffers (16 times the last-level
     cache): read-only, write-only, copy (1 : 1) and 2 reads : 1 write.  For
-    each mix the best median over the launch shapes; rates count every byte
-    read and written."""
+    each mix the best median over the launch shapes and cache policies;
+    rates count every byte read and written."""
     import ctypes
+    import itertools
     from paper_2208_08088_amd import build as B
     lib = ctypes.CDLL(B.CEIL_LIB)
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
-    lib.ceiling_read.argtypes = [vp, i64, vp, ci, ci, vp]
-    lib.ceiling_write.argtypes = [vp, i64, ci, ci, vp]
-    lib.ceiling_copy.argtypes = [vp, vp, i64, ci, ci, vp]
-    lib.ceiling_mix2.argtypes = [vp, vp, vp, i64, ci, ci, vp]
+    lib.ceiling_read.argtypes = [vp, i64, vp, ci, ci, ci, vp]
+    lib.ceiling_write.argtypes = [vp, i64, ci, ci, ci, vp]
+    lib.ceiling_copy.argtypes = [vp, vp, i64, ci, ci, ci, ci, vp]
+    lib.ceiling_mix2.argtypes = [vp, vp, i64, ci, ci, ci, ci, vp]
     n = nbytes // 8
     s0 = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
-    s1 = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
     d = torch.empty(n, dtype=torch.float64, device="cuda")
     sink = torch.empty(max(CEIL_GRIDS) * 256 * 2, dtype=torch.float64, device="cuda")
     P = lambda t: ctypes.c_void_p(t.data_ptr())
     kinds = {
-        "read": (1, 0, lambda g, u, st: lib.ceiling_read(P(s0), nbytes, P(sink), g, u, st)),
-        "write": (0, 1, lambda g, u, st: lib.ceiling_write(P(d), nbytes, g, u, st)),
-        "copy": (1, 1, lambda g, u, st: lib.ceiling_copy(P(s0), P(d), nbytes, g, u, st)),
-        "mix2": (2, 1, lambda g, u, st: lib.ceiling_mix2(P(s0), P(s1), P(d), nbytes, g, u, st)),
+        "read": (1, 0, lambda g, u, lp, sp, st: lib.ceiling_read(P(s0), nbytes, P(sink), g, u, lp, st)),
+        "write": (0, 1, lambda g, u, lp, sp, st: lib.ceiling_write(P(d), nbytes, g, u, sp, st)),
+        "copy": (1, 1, lambda g, u, lp, sp, st: lib.ceiling_copy(P(s0), P(d), nbytes, g, u, lp, sp, st)),
+        "mix2": (2, 1, lambda g, u, lp, sp, st: lib.ceiling_mix2(P(s0), P(d), nbytes, g, u, lp, sp, st)),
     }
-    out = {}
+    out, rows = {}, []
     for name, (nr, nw, fn) in kinds.items():
         best = None
-        for g in CEIL_GRIDS:
-            for u in CEIL_UNROLLS:
+        for g, u, lp, sp in itertools.product(CEIL_GRIDS, CEIL_UNROLLS, CEIL_POLICIES if nr else (0,),
+                                              CEIL_POLICIES if nw else (0,)):
+            st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+            assert fn(g, u, lp, sp, st) == 0, (name, g, u, lp, sp)  # warm-up
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn(g, u, lp, sp, st)
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            rows.append((name, g, u, lp, sp, (nr + nw) * nbytes / ms / 1e6))
+            if best is None or ms < best[0]:
+                best = (ms, g, u, lp, sp)
+        ms, g, u, lp, sp = best
+        byt = (nr + nw) * nbytes
+        out[name] = dict(reads=nr, writes=nw, bytes=byt, us=ms * 1e3, GB_s=byt / ms / 1e6,
+                         hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, grid=g, unroll=u, load_nt=lp, store_nt=sp)
+    del s0, d, sink
+    torch.cuda.empty_cache()
+    out["kernel"] = ("libtsmm_ceiling.so stream kernels (two-stage register pipeline), %d GiB buffers, 16-byte "
+                     "buffer loads/stores; best of %d launch shapes x cache policies" % (nbytes >> 30,
+                                                                                         len(CEIL_GRIDS) * len(CEIL_UNROLLS)))
+    if detail:
+        out["sweep"] = rows
+    return out
+
+
+def mfma_ceilings(torch, reps=5):
+    """Same-run matrix-core ceilings (libtsmm_ceiling.so): back-to-back
+    binary64 16x16x4 and bfloat16 32x32x16 products with no memory traffic,
+    on operands drawn uniform in [-1, 1] and on zeros, one and two
+    wavefronts per SIMD; the best median per product and operand kind.
+    The part's clock falls with operand switching activity, so the
+    random-operand rate is what a product kernel can sustain on such data."""
+    import ctypes
+    from paper_2208_08088_amd import build as B
+    lib = ctypes.CDLL(B.CEIL_LIB)
+    lib.ceiling_mfma.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_void_p]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2208)
+    operands = {
+        0: {"random": torch.empty(4096, dtype=torch.float64, device="cuda").uniform_(-1, 1, generator=g),
+            "zeros": torch.zeros(4096, dtype=torch.float64, device="cuda")},
+        1: {"random": torch.empty(16384, dtype=torch.float32, device="cuda").uniform_(-1, 1, generator=g)
+            .to(torch.bfloat16), "zeros": torch.zeros(16384, dtype=torch.bfloat16, device="cuda")},
+    }
+    iters = {0: 4000, 1: 8000}
+    flops_per = {0: 2048, 1: 32768}
+    sink = torch.empty(512 * 256 * 2, dtype=torch.float64, device="cuda")
+    out = {}
+    for kind, name in ((0, "f64_16x16x4"), (1, "bf16_32x32x16")):
+        row = {}
+        for data, src in operands[kind].items():
+            best = None
+            for grid in (256, 512):
                 st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-                assert fn(g, u, st) == 0, (name, g, u)  # warm-up
+                assert lib.ceiling_mfma(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(sink.data_ptr()), kind, grid,
+                                        iters[kind], st) == 0
                 ts = []
                 for _ in range(reps):
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
                     e0.record()
-                    fn(g, u, st)
+                    lib.ceiling_mfma(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(sink.data_ptr()), kind, grid,
+                                     iters[kind], st)
                     e1.record()
                     e1.synchronize()
                     ts.append(e0.elapsed_time(e1))
                 ms = float(np.median(ts))
-                if best is None or ms < best[0]:
-                    best = (ms, g, u)
-        ms, g, u = best
-        byt = (nr + nw) * nbytes
-        out[name] = dict(reads=nr, writes=nw, bytes=byt, us=ms * 1e3, GB_s=byt / ms / 1e6,
-                         hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, grid=g, unroll=u)
-    del s0, s1, d, sink
+                tf = grid * 4 * iters[kind] * 32 * flops_per[kind] / ms / 1e9
+                if best is None or tf > best[0]:
+                    best = (tf, grid)
+            peak = PEAK_TFLOPS["f64" if kind == 0 else "bf16"]
+            row[data] = dict(TFLOP_s=best[0], peak_frac=best[0] / peak, waves_per_simd=best[1] // 256)
+        out[name] = row
+    del sink, operands
     torch.cuda.empty_cache()
-    out["kernel"] = "libtsmm_ceiling.so stream kernels, %d GiB buffers, 16-byte buffer loads/stores" % (nbytes >> 30)
     return out
 
 
@@ -381,8 +441,10 @@ def extras_precision(torch, T, I, steps, warmup):
         byt = m * (k + n) * s
         fl = 2.0 * m * n * k
         bnd = bound_of(byt, fl, "f64" if dt == torch.float64 else ("bf16" if mode != "native" else "f32"))
+        issued = {"bf16x6": 6, "bf16x3": 3}.get(name, 1) * fl
         out[name] = dict(plan=p.describe(), us=ms * 1e3, GB_s=byt / ms / 1e6, hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS,
-                         TFLOP_s=fl / ms / 1e9)
+                         TFLOP_s=fl / ms / 1e9, issued_TFLOP_s=issued / ms / 1e9,
+                         roofline_frac=bnd[1] / (ms * 1e-3))
         keep[name] = C[idx].cpu().numpy()
         del A, B, C
         torch.cuda.empty_cache()
@@ -682,6 +744,10 @@ def main():
     ceiling = ceilings(torch)
     log("ceilings: read %.0f, write %.0f, copy %.0f, 2:1 %.0f GB/s" % tuple(
         ceiling[kk]["GB_s"] for kk in ("read", "write", "copy", "mix2")))
+    mceil = mfma_ceilings(torch)
+    log("matrix-core ceilings: f64 %.1f TF (random) / %.1f (zeros), bf16 %.0f / %.0f" % (
+        mceil["f64_16x16x4"]["random"]["TFLOP_s"], mceil["f64_16x16x4"]["zeros"]["TFLOP_s"],
+        mceil["bf16_32x32x16"]["random"]["TFLOP_s"], mceil["bf16_32x32x16"]["zeros"]["TFLOP_s"]))
     cases = headline(torch, T, I, args)
     log("headline cases ready: %s" % ", ".join(c["tag"] for c in cases))
     # snapshot sampled C0 rows and check one call of each case (for the CPU leg)
@@ -708,6 +774,7 @@ def main():
                    GB_s=c["bytes"] / ms / 1e6, hbm_frac=c["bytes"] / ms / 1e6 / HBM_PEAK_GBS,
                    TFLOP_s=c["flops"] / ms / 1e9, bound=bnd, roofline_frac=t_ideal / (ms * 1e-3),
                    us_median=float(q[0]) * 1e3, us_min=float(np.min(msl)) * 1e3, us_p90=float(q[1]) * 1e3,
+                   mfma_ceiling_frac=c["flops"] / ms / 1e9 / mceil["f64_16x16x4"]["random"]["TFLOP_s"],
                    ceiling_mix="mix2" if c["beta"] != 0.0 else "copy",
                    ceiling_frac=c["bytes"] / ms / 1e6 / ceiling["mix2" if c["beta"] != 0.0 else "copy"]["GB_s"],
                    plan=c["p"].describe())
@@ -736,7 +803,7 @@ def main():
                   hbm_frac=value / HBM_PEAK_GBS, roofline=roofline, breakdown=breakdown,
                   timing="HIP events around each execute on its stream; step = sum of the six; beta = 1 C "
                          "restores between steps untimed",
-                  wall_ms_per_step=wall / args.steps * 1e3, ceilings=ceiling)
+                  wall_ms_per_step=wall / args.steps * 1e3, ceilings=ceiling, mfma_ceilings=mceil)
 
     keep_s = None
     if not args.no_extras and not args.only:
@@ -746,6 +813,10 @@ def main():
         opt["ceiling_frac"] = opt["GB_s"] / ceiling["read"]["GB_s"]  # op T only reads
         log("op T done")
         prec, keep_p = extras_precision(torch, T, I, args.steps, args.warmup)
+        for name, row in prec.items():  # issued products against the measured matrix-core rate
+            key = "f64_16x16x4" if name == "f64" else ("bf16_32x32x16" if name.startswith("bf16") else None)
+            if key:
+                row["mfma_ceiling_frac"] = row["issued_TFLOP_s"] / mceil[key]["random"]["TFLOP_s"]
         log("precision done")
         torch.cuda.empty_cache()
         bat, keep_b = extras_batched(torch, T, I, args.steps, args.warmup)

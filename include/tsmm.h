@@ -328,7 +328,10 @@ tsmm_status tsmm_plan_set_workspace(tsmm_plan_t plan, void *workspace,
                                     size_t bytes);
 
 /* A one-line text description of the plan (kernel, tile, grid; table=0
- * built-in or caller's tile, 1 tile table, 2 runtime evaluator); writes at
+ * built-in or caller's tile, 1 tile table, 2 runtime evaluator; ran=the
+ * kernel family the latest execute ran, "-" before the first: it names the
+ * any-shape kernel when operand alignment or strides kept the plan's
+ * kernel from running, which TSMM_LOG=1 also reports on stderr); writes at
  * most len bytes including the terminating NUL. */
 tsmm_status tsmm_plan_describe(tsmm_plan_t plan, char *buf, size_t len);
 
@@ -426,7 +429,9 @@ tsmm_status tsmm_execute_ld(tsmm_plan_t plan, const void *A, int64_t lda, tsmm_p
  * geometry, since the terms are the same values.
  * Asynchronous on the plan's stream.
  * Errors: INVALID_VALUE (NULL argument, packed_a not from tsmm_pack_a,
- * packed not a packed B, C not 4-byte aligned), SHAPE_MISMATCH (plan and
+ * packed not a packed B, C not 4-byte aligned, or in the split modes not
+ * 16-byte aligned where C moves in 16-byte vectors: n % 4 == 0 and
+ * n > 48), SHAPE_MISMATCH (plan and
  * handles disagree), NOT_SUPPORTED (not an op N plan), HIP. */
 tsmm_status tsmm_execute_packed_a(tsmm_plan_t plan, tsmm_packed_t packed_a, tsmm_packed_t packed,
                                   void *C, double beta);

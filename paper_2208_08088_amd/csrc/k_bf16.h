@@ -161,12 +161,12 @@ __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 
         rc[rt] = make_rsrc(C + row0 * n + col0, bytes);
         rl[rt] = make_rsrc(C + row0 * n + col0, beta != 0.0 ? bytes : 0);
     }
-    // Interleaved columns (IL, bfloat16 inputs with n % 4 == 0; the
-    // fragment order of tsmm_internal.h): tile tt of lane j is column
-    // colp(tt) of the group, a lane holds 4 adjacent columns in the 4 tiles
-    // of a group, and C moves in 16-byte vectors.
+    // Interleaved columns (IL, n % 4 == 0; the fragment order of
+    // tsmm_internal.h): tile tt of lane j is column colp(tt) of the group, a
+    // lane holds 4 adjacent columns in the 4 tiles of a group, and C moves
+    // in 16-byte vectors.
     constexpr int PG = IL ? 4 : 1;
-    static_assert(!IL || (PROD == 1 && NT % 4 == 0), "interleave: bfloat16 inputs, whole groups");
+    static_assert(!IL || NT % 4 == 0, "interleave: whole groups of 4 column tiles");
     auto colp = [=](int tt) { return 16 * PG * (tt / PG) + PG * j + tt % PG; };
     auto coff = [=](int tt, int r) { return (col0 + colp(tt) < n) ? ((4 * q + r) * n + colp(tt)) * 4 : kOOB; };
     auto voff = [=](int g, int r) {
@@ -247,7 +247,15 @@ __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 
     __builtin_amdgcn_sched_barrier(0);
 
     if constexpr (IL) {
-        // bfloat16 inputs: one accumulator, no column scale
+        // the column exponents of the split modes, per tile of this lane
+        int ecol[PROD > 1 ? NT : 1];
+        if constexpr (PROD > 1) {
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt) {
+                const int col = col0 + colp(tt);
+                ecol[tt] = col < n ? exps[col] : 0;
+            }
+        }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -261,8 +269,13 @@ __device__ __forceinline__ void bf16_step(const TA *__restrict__ A, const u16x8 
                     }
                     f4v o;
 #pragma unroll
-                    for (int i = 0; i < PG; ++i)
-                        o[i] = (float)epilogue(alpha, (double)acc[rt][PG * g + i][r], beta, (double)cv[rt][PG * g + i][r]);
+                    for (int i = 0; i < PG; ++i) {
+                        // the same arithmetic as the plain column order below
+                        double sacc = (double)acc[rt][PG * g + i][r];
+                        if constexpr (TWO_ACC) sacc = sacc + (double)acc2[rt][PG * g + i][r];
+                        if constexpr (PROD > 1) sacc = __builtin_ldexp(sacc, ecol[PG * g + i]);
+                        o[i] = (float)epilogue(alpha, sacc, beta, (double)cv[rt][PG * g + i][r]);
+                    }
                     BufIO<float>::store_vec(o, rc[rt], voff(g, r));
                 }
     } else {
@@ -370,7 +383,12 @@ struct Bf16Entry {
     TSMM_BE(TA, KC, 16, RT, P, V)
 #define TSMM_BE_KC(TA, RT, P, V) \
     TSMM_BE_NT(TA, 32, RT, P, V) TSMM_BE_NT(TA, 64, RT, P, V) TSMM_BE_NT(TA, 128, RT, P, V) TSMM_BE_NT(TA, 256, RT, P, V)
-// interleaved columns (bfloat16 inputs, NT >= 4)
+// interleaved columns (NT >= 4): bfloat16 inputs (TSMM_BEI*), binary32
+// split modes (TSMM_BEF*)
+#define TSMM_BEF(KC, NT, RT, P, V) {KC, NT, RT, P, V, 1, &tsmm::run_splitbf16<float, KC, NT, RT, P, V, true>},
+#define TSMM_BEF_NT(KC, RT, P, V) TSMM_BEF(KC, 4, RT, P, V) TSMM_BEF(KC, 8, RT, P, V) TSMM_BEF(KC, 16, RT, P, V)
+#define TSMM_BEF_KC(RT, P, V) \
+    TSMM_BEF_NT(32, RT, P, V) TSMM_BEF_NT(64, RT, P, V) TSMM_BEF_NT(128, RT, P, V) TSMM_BEF_NT(256, RT, P, V)
 #define TSMM_BEI(KC, NT, RT, V) {KC, NT, RT, 1, V, 1, &tsmm::run_splitbf16<uint16_t, KC, NT, RT, 1, V, true>},
 #define TSMM_BEI_NT(KC, RT, V) TSMM_BEI(KC, 4, RT, V) TSMM_BEI(KC, 8, RT, V) TSMM_BEI(KC, 16, RT, V)
 #define TSMM_BEI_KC(RT, V) TSMM_BEI_NT(32, RT, V) TSMM_BEI_NT(64, RT, V) TSMM_BEI_NT(128, RT, V) TSMM_BEI_NT(256, RT, V)

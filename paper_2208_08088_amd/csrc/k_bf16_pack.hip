@@ -80,7 +80,7 @@ hipError_t launch_pack_bf16(tsmm_dtype dt, const void *B, void *frag, void *plan
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pack_bf16<true>, dim3(blocks), dim3(256), 0, s, B, (const int32_t *)exps,
-                           static_cast<uint16_t *>(frag), static_cast<uint16_t *>(planes), k, n, NT, terms, 1);
+                           static_cast<uint16_t *>(frag), static_cast<uint16_t *>(planes), k, n, NT, terms, pg);
     } else {
         hipLaunchKernelGGL(k_pack_bf16<false>, dim3(blocks), dim3(256), 0, s, B, (const int32_t *)nullptr,
                            static_cast<uint16_t *>(frag), (uint16_t *)nullptr, k, n, NT, 1, pg);

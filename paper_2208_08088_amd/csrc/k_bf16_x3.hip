@@ -4,11 +4,11 @@
 namespace tsmm {
 static const Bf16Entry kX3[] = {
     TSMM_BE_KC(float, 1, 3, true) TSMM_BE_KC(float, 2, 3, true) TSMM_BE_KC(float, 1, 3, false)
+    TSMM_BEF_KC(1, 3, true) TSMM_BEF_KC(2, 3, true) TSMM_BEF_KC(1, 3, false)
 };
 Bf16Fn find_bf16_x3(int KC, int NT, int RT, bool vec, bool il) {
-    if (il) return nullptr;  // split planes keep the plain column order
     for (const Bf16Entry &e : kX3)
-        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec) return e.fn;
+        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec && e.il == (int)il) return e.fn;
     return nullptr;
 }
 }  // namespace tsmm

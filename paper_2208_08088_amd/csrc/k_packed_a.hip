@@ -75,7 +75,15 @@ hipError_t launch_pack_a(tsmm_dtype dt, int terms, const void *A, int64_t lda, v
 // the variants whose registers hold the two sets of A terms, the
 // accumulators and B without spilling (checked in the build's register
 // report); the planner halves RT or splits the columns to reach one.
-#define TSMM_BP(KC, NT, RT, P) {KC, NT, RT, P, 1, 0, &tsmm::run_splitbf16<uint16_t, KC, NT, RT, P, true, false>},
+#define TSMM_BP(KC, NT, RT, P) {KC, NT, RT, P, 1, 0, &tsmm::run_splitbf16<uint16_t, KC, NT, RT, P, true, false>}, \
+    TSMM_BPI(KC, NT, RT, P)
+// interleaved columns where a group of 4 column tiles exists
+#define TSMM_BPI(KC, NT, RT, P) TSMM_BPI_##NT(KC, RT, P)
+#define TSMM_BPI_1(KC, RT, P)
+#define TSMM_BPI_2(KC, RT, P)
+#define TSMM_BPI_4(KC, RT, P) {KC, 4, RT, P, 1, 1, &tsmm::run_splitbf16<uint16_t, KC, 4, RT, P, true, true>},
+#define TSMM_BPI_8(KC, RT, P) {KC, 8, RT, P, 1, 1, &tsmm::run_splitbf16<uint16_t, KC, 8, RT, P, true, true>},
+#define TSMM_BPI_16(KC, RT, P) {KC, 16, RT, P, 1, 1, &tsmm::run_splitbf16<uint16_t, KC, 16, RT, P, true, true>},
 #define TSMM_BP4(KC, RT, P) TSMM_BP(KC, 1, RT, P) TSMM_BP(KC, 2, RT, P) TSMM_BP(KC, 4, RT, P)
 #define TSMM_BP8(KC, RT, P) TSMM_BP4(KC, RT, P) TSMM_BP(KC, 8, RT, P)
 #define TSMM_BP16(KC, RT, P) TSMM_BP8(KC, RT, P) TSMM_BP(KC, 16, RT, P)
@@ -88,20 +96,20 @@ static const Bf16Entry kPre[] = {
     TSMM_BP8(32, 2, 6) TSMM_BP8(64, 2, 6) TSMM_BP8(128, 2, 6) TSMM_BP(256, 1, 2, 6) TSMM_BP(256, 2, 2, 6)
 };
 
-static Bf16Fn find_presplit(int products, int KC, int NT, int RT) {
+static Bf16Fn find_presplit(int products, int KC, int NT, int RT, bool il) {
     for (const Bf16Entry &e : kPre)
-        if (e.KC == KC && e.NT == NT && e.RT == RT && e.prod == products) return e.fn;
+        if (e.KC == KC && e.NT == NT && e.RT == RT && e.prod == products && e.il == (int)il) return e.fn;
     return nullptr;
 }
 
-bool splitbf16_presplit_exists(int products, int KC, int NT, int RT) {
-    return find_presplit(products, KC, NT, RT) != nullptr;
+bool splitbf16_presplit_exists(int products, int KC, int NT, int RT, bool il) {
+    return find_presplit(products, KC, NT, RT, il) != nullptr;
 }
 
-hipError_t launch_splitbf16_presplit(int products, int KC, int NT, int RT, const void *planes, const void *Bfrag,
-                                     const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k, double beta,
-                                     int64_t grid, int block, int nt_total, int nsplit, hipStream_t s) {
-    Bf16Fn fn = find_presplit(products, KC, NT, RT);
+hipError_t launch_splitbf16_presplit(int products, int KC, int NT, int RT, bool il, const void *planes,
+                                     const void *Bfrag, const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k,
+                                     double beta, int64_t grid, int block, int nt_total, int nsplit, hipStream_t s) {
+    Bf16Fn fn = find_presplit(products, KC, NT, RT, il);
     if (!fn || nsplit < 1 || NT * nsplit != nt_total) return hipErrorInvalidValue;
     return fn(planes, Bfrag, exps, C, m, n, k, 1.0, beta, grid, block, nt_total, nsplit, s);
 }

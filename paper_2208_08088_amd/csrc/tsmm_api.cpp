@@ -1252,11 +1252,11 @@ tsmm_status tsmm_plan_describe(tsmm_plan_t p, char *buf, size_t len) {
     snprintf(buf, len,
              "op=%c dtype=%s mode=%s m=%" PRId64 " n=%" PRId64 " k=%" PRId64
              " kernel=%s kc=%d nt=%d vec=%d rt=%d waves=%d wg_per_cu=%d splitk=%d nsplit=%d grid=%" PRId64 "x%" PRId64
-             " block=%d workspace=%zu table=%d",
+             " block=%d workspace=%zu table=%d ran=%s",
              p->layout == TSMM_OP_N ? 'N' : (p->layout == TSMM_OP_T ? 'T' : 'C'), dtype_name(p->dtype), mode_name(p->mode), p->m, p->n, p->k,
              kernel_name(p->tile.kernel), p->KC, p->NT, (int)p->vec, p->tile.rows_per_wave, p->tile.waves_per_wg,
              p->tile.wg_per_cu, p->tile.splitk, p->tile.nsplit, p->grid, p->grid_y, p->block, p->workspace_bytes,
-             (int)p->tile_from_table);
+             (int)p->tile_from_table, p->last_kernel ? kernel_name(p->last_kernel) : "-");
     return TSMM_SUCCESS;
 }
 
@@ -1400,6 +1400,13 @@ tsmm_status execute_core(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_
             kernel = TSMM_KERNEL_SIMPLE;
         }
     }
+    if (kernel != p->tile.kernel && p->last_kernel != kernel && log_level() >= 1) {
+        char buf[256];
+        tsmm_plan_describe(p, buf, sizeof buf);
+        fprintf(stderr, "[tsmm] execute runs the %s kernel instead of the plan's (operand alignment or strides): %s\n",
+                kernel_name(kernel), buf);
+    }
+    p->last_kernel = kernel;
     switch (kernel) {
     case TSMM_KERNEL_STREAM:
         e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec,
@@ -1411,7 +1418,7 @@ tsmm_status execute_core(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_
                           static_cast<double *>(C), p->m, p->n, p->k, alpha, beta, p->grid, s);
         break;
     case TSMM_KERNEL_SPLITBF16: {
-        const bool il = bfrag_pg(p->dtype, p->NT, p->n) > 1;  // bfloat16 inputs only (NATIVE mode)
+        const bool il = bfrag_pg(p->dtype, p->NT, p->n) > 1;
         e = launch_splitbf16(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave,
                              split_products(p->dtype, p->mode), il, A, base + packed->L.off_frag,
                              p->mode != TSMM_MODE_NATIVE ? reinterpret_cast<const int32_t *>(base + packed->L.off_exps)
@@ -1548,18 +1555,20 @@ extern "C" {
 static tsmm_status presplit_geometry(const tsmm_plan_s &p, tsmm_plan_s &q) {
     const int KC = kclass32(p.k), NT = ntclass(p.n), prod = split_products(p.dtype, p.mode);
     if (!KC || !NT) return fail(TSMM_ERROR_NOT_SUPPORTED, "split-bf16 modes need k <= %d and n <= 256", kMaxKC);
+    const int pg = bfrag_pg(p.dtype, NT, p.n);  // the packed B's column interleave group
     tsmm_tile t = p.tile.kernel == TSMM_KERNEL_SPLITBF16 ? p.tile : default_tile(p, TSMM_KERNEL_SPLITBF16);
     t.kernel = TSMM_KERNEL_SPLITBF16;
-    t.nsplit = std::max(1, std::min(t.nsplit, NT));
+    t.nsplit = std::max(1, std::min(t.nsplit, NT / pg));
     for (;;) {
         const int NTs = NT / t.nsplit;
         int rt = std::max(1, t.rows_per_wave);
-        while (rt > 1 && !splitbf16_presplit_exists(prod, KC, NTs, rt)) rt /= 2;
-        if (splitbf16_presplit_exists(prod, KC, NTs, rt)) {
+        while (rt > 1 && !splitbf16_presplit_exists(prod, KC, NTs, rt, pg > 1)) rt /= 2;
+        if (splitbf16_presplit_exists(prod, KC, NTs, rt, pg > 1)) {
             t.rows_per_wave = rt;
             break;
         }
-        if (t.nsplit * 2 > NT) return fail(TSMM_ERROR_NOT_SUPPORTED, "no pre-split kernel for KC=%d NT=%d", KC, NT);
+        if (t.nsplit * 2 > NT / pg)
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no pre-split kernel for KC=%d NT=%d", KC, NT);
         t.nsplit *= 2;
     }
     q = p;
@@ -1591,12 +1600,16 @@ tsmm_status tsmm_execute_packed_a(tsmm_plan_t p, tsmm_packed_t packed_a, tsmm_pa
         return fail(TSMM_ERROR_SHAPE_MISMATCH, "plan and packed B disagree");
     if (!C) return fail(TSMM_ERROR_INVALID_VALUE, "C is NULL");
     if (reinterpret_cast<uintptr_t>(C) & 3) return fail(TSMM_ERROR_INVALID_VALUE, "C must be 4-byte aligned");
+    const bool il = packed->L.pg > 1;  // C in 16-byte vectors
+    if (il && (reinterpret_cast<uintptr_t>(C) & 15))
+        return fail(TSMM_ERROR_INVALID_VALUE, "C must be 16-byte aligned when n is a multiple of 4 and n > 48");
     tsmm_plan_s q;
     const tsmm_status st = presplit_geometry(*p, q);
     if (st != TSMM_SUCCESS) return st;
     const char *base = static_cast<const char *>(packed->dev);
+    p->last_kernel = TSMM_KERNEL_SPLITBF16;
     const hipError_t e = launch_splitbf16_presplit(
-        split_products(p->dtype, p->mode), q.KC, q.NT / q.tile.nsplit, q.tile.rows_per_wave, packed_a->dev,
+        split_products(p->dtype, p->mode), q.KC, q.NT / q.tile.nsplit, q.tile.rows_per_wave, il, packed_a->dev,
         base + packed->L.off_frag, reinterpret_cast<const int32_t *>(base + packed->L.off_exps), C, p->m, p->n, p->k,
         beta, q.grid, q.block, q.NT, q.tile.nsplit, p->stream);
     return e == hipSuccess ? TSMM_SUCCESS : hip_fail(e, "pre-split launch");

@@ -50,10 +50,11 @@ namespace tsmm {
 //     bfrag[(((c*NT + t)*P + p)*64 + l)*8 + u] = plane p of
 //         B[32c + 8q + u][16t + j] * 2^-e_(16t+j)
 // where e_j is the column's power-of-two exponent (1 <= max|B[:,j]|*2^-e_j
-// < 2) and planes are the residual split hi, mid, lo.  For bfloat16 inputs
-// with NT >= 4 and n % 4 == 0 the columns are interleaved in groups of 4
-// tiles as above (16t + j -> colp(t, j) with PG = 4), so that binary32 C
-// moves in 16-byte vectors; the split planes keep the plain order.
+// < 2) and planes are the residual split hi, mid, lo.  With NT >= 4 and
+// n % 4 == 0 the columns are interleaved in groups of 4 tiles as above
+// (16t + j -> colp(t, j) with PG = 4), so that binary32 C moves in 16-byte
+// vectors; the row-major split planes and the exponents keep the plain
+// column order.
 //
 // The wide kernels (k_wide.hip; binary32 B with n = 128 or 256, k <= 256,
 // k % 8 == 0) use the 32x32 products.  Their image holds, per 32-row chunk
@@ -79,8 +80,12 @@ inline int frag4_pg(tsmm_dtype d, int NT, int64_t n) {
     const int vw = 16 / elem_bytes(d);
     return (NT % vw == 0 && n % vw == 0) ? vw : 1;
 }
-// Column interleave group of the bfloat16 fragments: bfloat16 inputs only.
-inline int bfrag_pg(tsmm_dtype d, int NT, int64_t n) { return (d == TSMM_BF16 && NT % 4 == 0 && n % 4 == 0) ? 4 : 1; }
+// Column interleave group of the bfloat16 fragments (bfloat16 inputs and
+// the split modes of binary32 inputs).
+inline int bfrag_pg(tsmm_dtype d, int NT, int64_t n) {
+    (void)d;
+    return (NT % 4 == 0 && n % 4 == 0) ? 4 : 1;
+}
 
 // Smallest k class >= k for the 16x16x4 kernels (0 if k > kMaxKC).
 inline int kclass4(int64_t k) {
@@ -199,6 +204,8 @@ struct tsmm_plan_s {
     int device = 0;
     tsmm_tile tile{};
     int tile_from_table = 0;  // tile source: 0 built-in default or the caller's, 1 tile table, 2 runtime evaluator
+    int last_kernel = 0;      // kernel family the last execute ran (0: none yet); differs from tile.kernel when
+                              // operand alignment or strides sent it to the any-shape kernel
     // derived launch geometry
     int KC = 0, NT = 0;
     bool vec = false;
@@ -307,10 +314,11 @@ hipError_t launch_pack_a(tsmm_dtype dt, int terms, const void *A, int64_t lda, v
                          double alpha, hipStream_t s);
 // The split-bf16 kernel on a pre-split A (products 3 or 6; alpha folded in
 // at pack time, so the epilogue takes alpha = 1).
-hipError_t launch_splitbf16_presplit(int products, int KC, int NT, int RT, const void *planes, const void *Bfrag,
+hipError_t launch_splitbf16_presplit(int products, int KC, int NT, int RT, bool il, const void *planes,
+                                     const void *Bfrag,
                                      const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k, double beta,
                                      int64_t grid, int block, int nt_total, int nsplit, hipStream_t s);
-bool splitbf16_presplit_exists(int products, int KC, int NT, int RT);
+bool splitbf16_presplit_exists(int products, int KC, int NT, int RT, bool il);
 
 // op N binary64 on the vector ALU: NB columns per wavefront (16, 32),
 // B row-major; requires n % NB == 0 and k % 8 == 0.  grid = 64-row tiles

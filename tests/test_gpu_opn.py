@@ -197,6 +197,12 @@ def test_misaligned_A_still_correct():
     announce("misaligned A")
     T.execute(p, Av, pk, C, 1.0, 0.0)
     assert_normwise(host(C), oracle.gemm_n(A, B), 1e-12)
+    # the plan says which kernel the execute ran: the any-shape kernel here,
+    # the plan's own kernel again for an aligned A
+    info = p.info()
+    assert info["kernel"] == "stream" and info["ran"] == "simple", p.describe()
+    T.execute(p, dev(A, torch.float64), pk, C, 1.0, 0.0)
+    assert p.info()["ran"] == "stream", p.describe()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
