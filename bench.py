@@ -517,9 +517,10 @@ def extras_colmajor(torch, T, I, steps, warmup):
 def extras_packed_a(torch, T, I, steps, warmup):
     """A packed once and reused (PACKA, alpha folded in): binary32 in the
     split-bf16 modes, beta = 0, fresh A (split in registers on every call,
-    the plan's own kernel) against the pre-split A of tsmm_pack_a (the
-    split-bf16 kernel loading the terms).  Bytes per call: fresh 4*m*k +
-    4*m*n, packed 2*terms*m*k + 4*m*n."""
+    the plan's own kernel) against tsmm_pack_a's handle (the split-bf16
+    kernel loading the pre-split terms, or the plan's wide kernel reading
+    RN32(alpha*A)).  Bytes per call: 4*m*k (fresh, or the wide kernel) or
+    2*terms*m*k (pre-split terms), plus 4*m*n."""
     out = {}
     for m, k, n in ((M_ROWS, 32, 32), (M_ROWS, 128, 128), (1 << 24, 256, 256)):
         A = I.device_uniform((m, k), I.BASE_SEED, 500 + k, torch.float32)
@@ -544,7 +545,11 @@ def extras_packed_a(torch, T, I, steps, warmup):
                     fn()
                     timer.stop(key, e0)
                 ms = float(np.median(timer.per_key_ms()[key]))
-                byt = (4 if key == "fresh" else 2 * terms) * m * k + 4 * m * n
+                # the packed call reads RN32(alpha*A) where the plan runs the
+                # wide kernel, else the pre-split terms
+                reads_a32 = key == "fresh" or p.info()["ran"] == "wide"
+                row[key + "_ran"] = p.info()["ran"]
+                byt = (4 if reads_a32 else 2 * terms) * m * k + 4 * m * n
                 row[key + "_us"] = ms * 1e3
                 row[key + "_GB_s"] = byt / ms / 1e6
                 row[key + "_hbm_frac"] = byt / ms / 1e6 / HBM_PEAK_GBS

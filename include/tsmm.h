@@ -266,8 +266,12 @@ void tsmm_packed_destroy(tsmm_packed_t packed);
  *           RN32(alpha*a) already split into its 2 / 3 bfloat16 terms (the
  *           residual split of those modes), one plane per term, rows padded
  *           to a multiple of 8 and the row count to a multiple of 16 with
- *           zeros: executes load the terms instead of splitting A on every
- *           call (2 / 3 bytes of traffic per term and element instead of 4).
+ *           zeros: executes on the split-bf16 kernel load the terms instead
+ *           of splitting A on every call (2 bytes of traffic per term and
+ *           element instead of 4).  When k % 8 == 0 it also holds
+ *           RN32(alpha*a) itself (m x k binary32), which executes of plans
+ *           that run the wide kernels read instead: those split in the
+ *           shadow of their products, into the same terms.
  *   alpha   folded into the handle; alpha = 0 makes executes compute
  *           beta*C without reading A or B (reference-BLAS convention).
  *   out     receives the handle (owns device memory; free it with
@@ -422,11 +426,13 @@ tsmm_status tsmm_execute_ld(tsmm_plan_t plan, const void *A, int64_t lda, tsmm_p
  * is an op N plan of the same m, k, dtype and mode as packed_a; packed is
  * B packed for that plan; C is row-major m x n (natural stride).
  * NATIVE plans run their own kernel on the packed copy of A.  Split-bf16
- * plans run the split-bf16 kernel on the pre-split terms (the plan's tile
- * when the plan uses that kernel, else its default tile, with fewer rows
- * per wavefront or more column groups where a variant needs them); for
- * alpha = 1 the result is bitwise that of tsmm_execute on the same
- * geometry, since the terms are the same values.
+ * plans that run a wide kernel (TSMM_KERNEL_WIDE; n = 128 or 256) run it on
+ * the handle's RN32(alpha*A) when it holds one (k % 8 == 0); other
+ * split-bf16 plans run the split-bf16 kernel on the pre-split terms (the
+ * plan's tile when the plan uses that kernel, else its default tile, with
+ * fewer rows per wavefront or more column groups where a variant needs
+ * them).  For alpha = 1 the result is bitwise that of tsmm_execute with
+ * the same kernel and geometry, since the terms are the same values.
  * Asynchronous on the plan's stream.
  * Errors: INVALID_VALUE (NULL argument, packed_a not from tsmm_pack_a,
  * packed not a packed B, C not 4-byte aligned, or in the split modes not

@@ -1112,6 +1112,13 @@ tsmm_status tsmm_pack_a(const void *A, int64_t m, int64_t k, int64_t lda, tsmm_d
         return TSMM_SUCCESS;
     }
     P->L.bytes = terms > 0 ? (size_t)terms * presplit_rows(m) * presplit_ld(k) * 2 : (size_t)m * k * elem_bytes(dtype);
+    if (terms > 0 && k % 8 == 0) {
+        // the wide kernels split A in the shadow of their products: for a plan
+        // that runs them, RN32(alpha*A) itself is the cheaper operand to read
+        P->L.has_a32 = true;
+        P->L.off_a32 = (P->L.bytes + 255) & ~(size_t)255;
+        P->L.bytes = P->L.off_a32 + (size_t)m * k * 4;
+    }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(TSMM_ERROR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
@@ -1120,6 +1127,9 @@ tsmm_status tsmm_pack_a(const void *A, int64_t m, int64_t k, int64_t lda, tsmm_d
     if (e != hipSuccess)
         return fail(TSMM_ERROR_OUT_OF_MEMORY, "hipMalloc(%zu): %s", P->L.bytes, hipGetErrorString(e));
     e = launch_pack_a(dtype, terms, A, lda, P->dev, m, k, alpha, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess && P->L.has_a32)
+        e = launch_pack_a(dtype, 0, A, lda, static_cast<char *>(P->dev) + P->L.off_a32, m, k, alpha,
+                          static_cast<hipStream_t>(stream));
     if (e != hipSuccess) {
         (void)hipFree(P->dev);
         return hip_fail(e, "pack A");
@@ -1600,6 +1610,10 @@ tsmm_status tsmm_execute_packed_a(tsmm_plan_t p, tsmm_packed_t packed_a, tsmm_pa
         return fail(TSMM_ERROR_SHAPE_MISMATCH, "plan and packed B disagree");
     if (!C) return fail(TSMM_ERROR_INVALID_VALUE, "C is NULL");
     if (reinterpret_cast<uintptr_t>(C) & 3) return fail(TSMM_ERROR_INVALID_VALUE, "C must be 4-byte aligned");
+    if (p->tile.kernel == TSMM_KERNEL_WIDE && packed_a->L.has_a32)
+        // the plan's wide kernel on RN32(alpha*A): it splits each value into
+        // the same terms as the pre-split planes hold
+        return tsmm_execute(p, static_cast<const char *>(packed_a->dev) + packed_a->L.off_a32, packed, C, 1.0, beta);
     const bool il = packed->L.pg > 1;  // C in 16-byte vectors
     if (il && (reinterpret_cast<uintptr_t>(C) & 15))
         return fail(TSMM_ERROR_INVALID_VALUE, "C must be 16-byte aligned when n is a multiple of 4 and n > 48");

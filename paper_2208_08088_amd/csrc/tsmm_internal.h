@@ -129,6 +129,10 @@ struct PackedLayout {
     size_t off_exps = 0;        // split: n int32
     int wide_KC = 0, wide_NT = 0;  // wide-kernel image (0: none)
     size_t off_wide = 0;
+    // packed A of the split modes with k % 8 == 0: RN32(alpha*A), dense
+    // row-major m x k binary32, after the planes (for the wide kernels)
+    bool has_a32 = false;
+    size_t off_a32 = 0;
     size_t bytes = 0;
 };
 

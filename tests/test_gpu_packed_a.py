@@ -53,12 +53,17 @@ def test_packed_split_is_bitwise_the_fresh_split(mode, m, k, n):
     Ad = dev(A, torch.float32)
     for alpha in (1.0, 0.5):  # powers of two scale every term exactly
         announce("packed A split", mode, m, k, n, "alpha", alpha)
-        Cf = dev(C0, torch.float32)
-        T.execute(split_plan(m, n, k, mode, True), Ad, pk, Cf, alpha, 0.5)
         p = split_plan(m, n, k, mode)
+        # the packed path runs the plan's wide kernel on RN32(alpha*A) where
+        # the plan has one (k % 8 == 0), else the split-bf16 kernel on the
+        # pre-split terms: the fresh reference runs the same kernel
+        wide = p.info()["kernel"] == "wide" and k % 8 == 0
+        Cf = dev(C0, torch.float32)
+        T.execute(split_plan(m, n, k, mode, not wide), Ad, pk, Cf, alpha, 0.5)
         pa = T.pack_a(Ad, mode, alpha)
         Cp = dev(C0, torch.float32)
         T.execute_packed_a(p, pa, pk, Cp, 0.5)
+        assert p.info()["ran"] == ("wide" if wide else "splitbf16"), p.describe()
         assert torch.equal(Cp, Cf), (mode, alpha)
         assert_normwise(host(Cp), oracle.gemm_n(A, B, C0, alpha, 0.5), TOL[mode], mode)
     # a scale that is not a power of two rounds alpha*a to binary32 first:
@@ -86,7 +91,10 @@ def test_pre_split_terms_through_identity(mode, m, k):
     planes = oracle.pack_a(A, alpha, TERMS[mode])
     want = sum((planes[t].astype(np.uint32) << 16).view(np.float32).astype(np.float64) for t in range(TERMS[mode]))
     assert np.array_equal(host(C), want.astype(np.float32).astype(np.float64))
-    assert pa.nbytes() == TERMS[mode] * ((m + 15) // 16 * 16) * ((k + 7) // 8 * 8) * 2
+    planes_bytes = TERMS[mode] * ((m + 15) // 16 * 16) * ((k + 7) // 8 * 8) * 2
+    # k % 8 == 0: RN32(alpha*A) itself follows the planes (for wide plans)
+    a32 = (planes_bytes + 255) // 256 * 256 - planes_bytes + m * k * 4 if k % 8 == 0 else 0
+    assert pa.nbytes() == planes_bytes + a32
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
