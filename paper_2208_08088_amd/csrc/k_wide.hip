@@ -206,6 +206,9 @@ __device__ __forceinline__ void wide_half_split(const u32x4 *sb, int s, bool pre
 
 // One quad (four rows of a 32-row tile, four columns per lane) of the
 // epilogue.  KIND 0: general, 1: beta == 0, 2: beta == 0 and alpha == 1.
+// At KIND 2 the split modes scale in binary32: acc * 2^e is exact in
+// binary64, so RN32 of it is one correctly rounded scaling, which is what
+// v_ldexp_f32 computes (subnormal and overflowing results included).
 template <int MODE, int KIND>
 __device__ __forceinline__ f4v wide_out4(const f16v (&acc)[4], int r, const int (&e)[4], double alpha, double beta,
                                          const f4v &c) {
@@ -215,6 +218,8 @@ __device__ __forceinline__ f4v wide_out4(const f16v (&acc)[4], int r, const int 
         const float a = acc[i][r];
         if constexpr (MODE == 0 && KIND == 2) {
             o[i] = a;  // RN32(a) == a
+        } else if constexpr (KIND == 2) {
+            o[i] = __builtin_ldexpf(a, e[i]);  // RN32(a * 2^e)
         } else {
 #pragma clang fp contract(off)
             double t = (double)a;

@@ -147,3 +147,26 @@ def test_wide_unaligned_operands():
     q = T.plan(m, n, k, "N", torch.float32).set_mode("bf16x6").set_tile(kernel=T.KERNEL_WIDE)
     with pytest.raises(T.TsmmError):
         T.execute(q, A_off, T.pack(dev(B, torch.float32), "N", "bf16x6"), C, 1.0, 0.0)
+
+
+@pytest.mark.parametrize("mode", ["bf16x6", "bf16x3"])
+def test_wide_unit_scale_shortcut_is_the_general_epilogue(mode):
+    # alpha = 1, beta = 0 scales the accumulators by the column exponents in
+    # binary32 (one correctly rounded ldexp); the general binary64 epilogue
+    # (alpha = 1, beta = 1 on a zero C) must give the same values, also for
+    # columns whose results are subnormal (scaled by 2^-140) or near the top
+    # of the binary32 range (2^+120)
+    m, k, n = 3000, 64, 128
+    A = I.host_uniform((m, k), 91, 1, dtype=np.float32)
+    B = I.host_uniform((k, n), 91, 2, dtype=np.float64)
+    B[:, 5] *= 2.0 ** -140
+    B[:, 9] *= 2.0 ** -132
+    B[:, 70] *= 2.0 ** 120
+    B = B.astype(np.float32)
+    Cs = run_wide(A, B, None, 1.0, 0.0, mode)
+    Cg = run_wide(A, B, np.zeros((m, n), dtype=np.float32), 1.0, 1.0, mode)
+    assert np.array_equal(Cs, Cg)
+    assert np.count_nonzero(np.abs(Cs[:, 5]) < 2.0 ** -126) > m // 2  # the subnormal column is exercised
+    ref = oracle.gemm_n(A, B)
+    normal = [j for j in range(n) if j not in (5, 9)]
+    assert_normwise(Cs[:, normal], ref[:, normal], TOL[mode], mode)
