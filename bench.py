@@ -20,10 +20,13 @@ step time: GB/s, whole job.  The wall time of the bracketed steps, restores
 included, is reported beside it.
 
 Bandwidth ceilings (same run): hand-written read-only, write-only, copy
-(1 read : 1 write) and 2-read : 1-write stream kernels over 4 GiB buffers
-(libtsmm_ceiling.so), best launch shape of a small sweep; each headline
-case is also given as a fraction of the ceiling of its own read : write
-mix (beta 0: copy; beta 1: 2 : 1).
+(1 read : 1 write) and 2-read : 1-write stream kernels (libtsmm_ceiling.so),
+best launch shape of a small sweep, over buffers of each headline case's
+own size (A and C of m = 2^23 rows of k = n = 8, 32, 128 doubles: 512 MiB,
+2 GiB, 8 GiB; the rate of a plain stream falls with its buffer size, 13%
+from 512 MiB to 8 GiB for a copy) and over 4 GiB for the op T extra's
+reads; each headline case is also given as a fraction of the ceiling of
+its own read : write mix at its own size (beta 0: copy; beta 1: 2 : 1).
 
 Extras (same run, reported beside the headline): the 4096 x 16 latency
 case, the op T split-k shape (C(64x64) = A^T B, A and B 2^22 x 64), the
@@ -56,7 +59,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}
 M_ROWS = 1 << 23
-CPU_SAMPLE_ROWS = 5 << 20  # sampled rows of each sub-case: about 7 s of oracle time on 16 cores
+CPU_SAMPLE_ROWS = 7 << 20  # sampled rows of each sub-case: about 10 s of oracle time on 16 cores
 CPU_ONE_THREAD_DIV = 32    # the one-thread leg runs 1/32 of that sample
 KS = (8, 32, 128)
 BETAS = (0.0, 1.0)
@@ -81,7 +84,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default=None, help="profile helper: run only this headline sub-case, e.g. k128b1")
+    ap.add_argument("--only", default=None,
+                    help="profile helper: run only these headline sub-cases (comma list, e.g. k128b1 or "
+                         "k8b0,k128b1), after one calibration copy of known size and without the ceiling sweeps")
     return ap.parse_args()
 
 
@@ -125,7 +130,7 @@ def headline(torch, T, I, args):
               for r in range(N_A_BUFFERS)]
         for beta in BETAS:
             tag = "k%db%d" % (k, int(beta))
-            if args.only and tag != args.only:
+            if args.only and tag not in args.only.split(","):
                 continue
             C = I.device_uniform((M_ROWS, n), I.BASE_SEED, 300 + 10 * k + int(beta), torch.float64)
             C0 = C.clone() if beta != 0.0 else None  # pristine copy, restored before every call
@@ -186,19 +191,21 @@ def plan_tile(describe):
     return " ".join("%s=%s" % (f, d[f]) for f in TILE_FIELDS)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_stream_f64_headline_m2p23_pmc.txt")
+
+
 def measured_traffic(case, describe):
-    """HBM bytes per launch of `case` from the committed rocprofv3 counter
-    summary, or None when there is none, or the kernel sources or the
-    plan's tile changed since."""
-    path = os.path.join(ROOT, "profiles", "k_stream_f64_%s_pmc.txt" % {
-        "k128b1": "k128_n128_beta1_m2p23"}.get(case, case))
-    if not os.path.exists(path):
+    """HBM bytes per launch of headline sub-case `case` from the committed
+    rocprofv3 counter summary, or None when it holds no figure for the
+    case, or the kernel sources or the case's plan tile changed since."""
+    if not os.path.exists(TRAFFIC_PROFILE):
         return None
-    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
-    if (kv.get("case") != case or kv.get("source_hash") != kernel_source_hash()
-            or kv.get("plan_tile") != plan_tile(describe)):
+    kv = dict(line.strip().split("=", 1) for line in open(TRAFFIC_PROFILE)
+              if "=" in line and not line.startswith("#"))
+    if (kv.get("source_hash") != kernel_source_hash()
+            or kv.get("%s.plan_tile" % case) != plan_tile(describe)):
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return float(kv["%s.traffic_bytes_per_launch" % case])
 
 
 def bound_of(bytes_, flops, dt):
@@ -210,66 +217,87 @@ def bound_of(bytes_, flops, dt):
 CEIL_GRIDS = (256, 512, 1024, 2048, 4096)  # workgroups of 256 lanes (1 to 16 per compute unit)
 CEIL_UNROLLS = (2, 4, 8)          # 16-byte vectors per lane per work item
 CEIL_POLICIES = (0, 1)            # cache policy of loads / stores: default, non-temporal
+CEIL_LAYOUTS = (0, 1)             # item layout: wavefronts interleaved at 1 KiB, or wave-contiguous
 
 
 def ceilings(torch, nbytes=4 << 30, reps=5, detail=False):
     """Same-run bandwidth ceilings from the hand-written stream kernels of
-    libtsmm_ceiling.so over `nbytes` buffers (16 times the last-level
-    cache): read-only, write-only, copy (1 : 1) and 2 reads : 1 write.  For
-    each mix the best median over the launch shapes and cache policies;
-    rates count every byte read and written."""
+    libtsmm_ceiling.so over `nbytes` buffers (at least twice the 256 MiB
+    last-level cache): read-only, write-only, copy (1 : 1) and 2 reads :
+    1 write.  For each mix the best median over the launch shapes, cache
+    policies and item layouts; rates count every byte read and written."""
     import ctypes
     import itertools
     from paper_2208_08088_amd import build as B
     lib = ctypes.CDLL(B.CEIL_LIB)
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
-    lib.ceiling_read.argtypes = [vp, i64, vp, ci, ci, ci, vp]
-    lib.ceiling_write.argtypes = [vp, i64, ci, ci, ci, vp]
-    lib.ceiling_copy.argtypes = [vp, vp, i64, ci, ci, ci, ci, vp]
-    lib.ceiling_mix2.argtypes = [vp, vp, i64, ci, ci, ci, ci, vp]
+    lib.ceiling_read.argtypes = [vp, i64, vp, ci, ci, ci, ci, vp]
+    lib.ceiling_write.argtypes = [vp, i64, ci, ci, ci, ci, vp]
+    lib.ceiling_copy.argtypes = [vp, vp, i64, ci, ci, ci, ci, ci, vp]
+    lib.ceiling_mix2.argtypes = [vp, vp, i64, ci, ci, ci, ci, ci, vp]
     n = nbytes // 8
     s0 = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
     d = torch.empty(n, dtype=torch.float64, device="cuda")
     sink = torch.empty(max(CEIL_GRIDS) * 256 * 2, dtype=torch.float64, device="cuda")
     P = lambda t: ctypes.c_void_p(t.data_ptr())
     kinds = {
-        "read": (1, 0, lambda g, u, lp, sp, st: lib.ceiling_read(P(s0), nbytes, P(sink), g, u, lp, st)),
-        "write": (0, 1, lambda g, u, lp, sp, st: lib.ceiling_write(P(d), nbytes, g, u, sp, st)),
-        "copy": (1, 1, lambda g, u, lp, sp, st: lib.ceiling_copy(P(s0), P(d), nbytes, g, u, lp, sp, st)),
-        "mix2": (2, 1, lambda g, u, lp, sp, st: lib.ceiling_mix2(P(s0), P(d), nbytes, g, u, lp, sp, st)),
+        "read": (1, 0, lambda g, u, lp, sp, wl, st: lib.ceiling_read(P(s0), nbytes, P(sink), g, u, lp, wl, st)),
+        "write": (0, 1, lambda g, u, lp, sp, wl, st: lib.ceiling_write(P(d), nbytes, g, u, sp, wl, st)),
+        "copy": (1, 1, lambda g, u, lp, sp, wl, st: lib.ceiling_copy(P(s0), P(d), nbytes, g, u, lp, sp, wl, st)),
+        "mix2": (2, 1, lambda g, u, lp, sp, wl, st: lib.ceiling_mix2(P(s0), P(d), nbytes, g, u, lp, sp, wl, st)),
     }
     out, rows = {}, []
     for name, (nr, nw, fn) in kinds.items():
         best = None
-        for g, u, lp, sp in itertools.product(CEIL_GRIDS, CEIL_UNROLLS, CEIL_POLICIES if nr else (0,),
-                                              CEIL_POLICIES if nw else (0,)):
+        for g, u, lp, sp, wl in itertools.product(CEIL_GRIDS, CEIL_UNROLLS, CEIL_POLICIES if nr else (0,),
+                                                  CEIL_POLICIES if nw else (0,), CEIL_LAYOUTS):
             st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-            assert fn(g, u, lp, sp, st) == 0, (name, g, u, lp, sp)  # warm-up
+            assert fn(g, u, lp, sp, wl, st) == 0, (name, g, u, lp, sp, wl)  # warm-up
             ts = []
             for _ in range(reps):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
-                fn(g, u, lp, sp, st)
+                fn(g, u, lp, sp, wl, st)
                 e1.record()
                 e1.synchronize()
                 ts.append(e0.elapsed_time(e1))
             ms = float(np.median(ts))
-            rows.append((name, g, u, lp, sp, (nr + nw) * nbytes / ms / 1e6))
+            rows.append((name, g, u, lp, sp, wl, (nr + nw) * nbytes / ms / 1e6))
             if best is None or ms < best[0]:
-                best = (ms, g, u, lp, sp)
-        ms, g, u, lp, sp = best
+                best = (ms, g, u, lp, sp, wl)
+        ms, g, u, lp, sp, wl = best
         byt = (nr + nw) * nbytes
         out[name] = dict(reads=nr, writes=nw, bytes=byt, us=ms * 1e3, GB_s=byt / ms / 1e6,
-                         hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, grid=g, unroll=u, load_nt=lp, store_nt=sp)
+                         hbm_frac=byt / ms / 1e6 / HBM_PEAK_GBS, grid=g, unroll=u, load_nt=lp, store_nt=sp,
+                         wave_contiguous=wl)
     del s0, d, sink
     torch.cuda.empty_cache()
     out["kernel"] = ("libtsmm_ceiling.so stream kernels (two-stage register pipeline), %d GiB buffers, 16-byte "
-                     "buffer loads/stores; best of %d launch shapes x cache policies" % (nbytes >> 30,
-                                                                                         len(CEIL_GRIDS) * len(CEIL_UNROLLS)))
+                     "buffer loads/stores; best of %d launch shapes x cache policies x 2 item layouts"
+                     % (nbytes >> 30, len(CEIL_GRIDS) * len(CEIL_UNROLLS)))
     if detail:
         out["sweep"] = rows
     return out
+
+
+def calibration_copy(torch, nbytes=4 << 30):
+    """One launch of the ceiling copy kernel over `nbytes` (read once,
+    written once, default layout, non-temporal loads and stores): the
+    kernel of known traffic that scales the HBM byte counters of a
+    profiled run."""
+    import ctypes
+    from paper_2208_08088_amd import build as B
+    lib = ctypes.CDLL(B.CEIL_LIB)
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.ceiling_copy.argtypes = [vp, vp, i64, ci, ci, ci, ci, ci, vp]
+    s0 = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    d = torch.empty_like(s0)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.ceiling_copy(ctypes.c_void_p(s0.data_ptr()), ctypes.c_void_p(d.data_ptr()), nbytes, 256, 4, 1, 1, 0,
+                            st) == 0
+    torch.cuda.synchronize()
+    log("calibration copy: %d GiB read, %d GiB written" % (nbytes >> 30, nbytes >> 30))
 
 
 def mfma_ceilings(torch, reps=5):
@@ -324,6 +352,9 @@ def mfma_ceilings(torch, reps=5):
     del sink, operands
     torch.cuda.empty_cache()
     return out
+
+
+OPT_READ_BYTES = (1 << 22) * (64 + 64) * 8  # the op T extra reads A and B, 2^22 x 64 doubles each
 
 
 def extras_opt(torch, T, I, steps, warmup):
@@ -746,13 +777,21 @@ def main():
     T._lib()  # fail loudly if the HIP library is missing
     torch.cuda.set_device(0)
 
-    ceiling = ceilings(torch)
-    log("ceilings: read %.0f, write %.0f, copy %.0f, 2:1 %.0f GB/s" % tuple(
-        ceiling[kk]["GB_s"] for kk in ("read", "write", "copy", "mix2")))
-    mceil = mfma_ceilings(torch)
-    log("matrix-core ceilings: f64 %.1f TF (random) / %.1f (zeros), bf16 %.0f / %.0f" % (
-        mceil["f64_16x16x4"]["random"]["TFLOP_s"], mceil["f64_16x16x4"]["zeros"]["TFLOP_s"],
-        mceil["bf16_32x32x16"]["random"]["TFLOP_s"], mceil["bf16_32x32x16"]["zeros"]["TFLOP_s"]))
+    if args.only:
+        # profiling a single sub-case: one copy of known size for the
+        # counters' calibration instead of the ceiling sweeps
+        calibration_copy(torch)
+        ceiling = mceil = None
+    else:
+        ceiling = {}
+        for nb in sorted({M_ROWS * k * 8 for k in KS} | {OPT_READ_BYTES}):
+            ceiling[nb] = ceilings(torch, nbytes=nb)
+            log("ceilings over %d MiB: read %.0f, write %.0f, copy %.0f, 2:1 %.0f GB/s" % ((nb >> 20,) + tuple(
+                ceiling[nb][kk]["GB_s"] for kk in ("read", "write", "copy", "mix2"))))
+        mceil = mfma_ceilings(torch)
+        log("matrix-core ceilings: f64 %.1f TF (random) / %.1f (zeros), bf16 %.0f / %.0f" % (
+            mceil["f64_16x16x4"]["random"]["TFLOP_s"], mceil["f64_16x16x4"]["zeros"]["TFLOP_s"],
+            mceil["bf16_32x32x16"]["random"]["TFLOP_s"], mceil["bf16_32x32x16"]["zeros"]["TFLOP_s"]))
     cases = headline(torch, T, I, args)
     log("headline cases ready: %s" % ", ".join(c["tag"] for c in cases))
     # snapshot sampled C0 rows and check one call of each case (for the CPU leg)
@@ -779,10 +818,13 @@ def main():
                    GB_s=c["bytes"] / ms / 1e6, hbm_frac=c["bytes"] / ms / 1e6 / HBM_PEAK_GBS,
                    TFLOP_s=c["flops"] / ms / 1e9, bound=bnd, roofline_frac=t_ideal / (ms * 1e-3),
                    us_median=float(q[0]) * 1e3, us_min=float(np.min(msl)) * 1e3, us_p90=float(q[1]) * 1e3,
-                   mfma_ceiling_frac=c["flops"] / ms / 1e9 / mceil["f64_16x16x4"]["random"]["TFLOP_s"],
-                   ceiling_mix="mix2" if c["beta"] != 0.0 else "copy",
-                   ceiling_frac=c["bytes"] / ms / 1e6 / ceiling["mix2" if c["beta"] != 0.0 else "copy"]["GB_s"],
-                   plan=c["p"].describe())
+                   plan=c["p"].describe(), traffic_bytes=measured_traffic(c["tag"], c["p"].describe()))
+        if ceiling is not None:
+            mix = "mix2" if c["beta"] != 0.0 else "copy"
+            cz = ceiling[M_ROWS * c["k"] * 8]  # A and C of this case are this size (k = n)
+            row.update(mfma_ceiling_frac=c["flops"] / ms / 1e9 / mceil["f64_16x16x4"]["random"]["TFLOP_s"],
+                       ceiling_mix=mix, ceiling_bytes=M_ROWS * c["k"] * 8,
+                       ceiling_frac=c["bytes"] / ms / 1e6 / cz[mix]["GB_s"])
         breakdown.append(row)
         if dom is None or ms > dom[1]:
             dom = (c, ms, bnd)
@@ -808,14 +850,16 @@ def main():
                   hbm_frac=value / HBM_PEAK_GBS, roofline=roofline, breakdown=breakdown,
                   timing="HIP events around each execute on its stream; step = sum of the six; beta = 1 C "
                          "restores between steps untimed",
-                  wall_ms_per_step=wall / args.steps * 1e3, ceilings=ceiling, mfma_ceilings=mceil)
+                  wall_ms_per_step=wall / args.steps * 1e3,
+                  ceilings=None if ceiling is None else {"%d_MiB" % (nb >> 20): v for nb, v in ceiling.items()},
+                  mfma_ceilings=mceil)
 
     keep_s = None
     if not args.no_extras and not args.only:
         small, keep_s = extras_small(torch, T, I)
         log("small case done")
         opt, keep_t = extras_opt(torch, T, I, args.steps, args.warmup)
-        opt["ceiling_frac"] = opt["GB_s"] / ceiling["read"]["GB_s"]  # op T only reads
+        opt["ceiling_frac"] = opt["GB_s"] / ceiling[OPT_READ_BYTES]["read"]["GB_s"]  # op T only reads
         log("op T done")
         prec, keep_p = extras_precision(torch, T, I, args.steps, args.warmup)
         for name, row in prec.items():  # issued products against the measured matrix-core rate

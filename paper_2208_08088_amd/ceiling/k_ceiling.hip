@@ -23,10 +23,12 @@
 // Every entry point takes device pointers, a byte count that is a multiple
 // of the work item (256 lanes x 16 bytes x unroll), the launch shape
 // (workgroups, unroll 2/4/8), the cache policy of the loads and of the
-// stores (0 default, 1 non-temporal) and a HIP stream, and returns a
-// hipError_t.  Each workgroup walks its work items with a grid stride and
-// a two-stage register pipeline: the next item's loads are in flight while
-// the current item is stored.  Buffers are addressed through resources of
+// stores (0 default, 1 non-temporal), the item layout (0: the workgroup's
+// four wavefronts interleave at 1 KiB, 1: each wavefront owns unroll
+// contiguous KiB of the item, as a multiply kernel's wavefront owns its row
+// tiles) and a HIP stream, and returns a hipError_t.  Each workgroup walks
+// its work items with a grid stride and a two-stage register pipeline: the
+// next item's loads are in flight while the current item is stored.  Buffers are addressed through resources of
 // 1 GiB windows; loads past a window read 0 without touching memory.
 #include <hip/hip_runtime.h>
 
@@ -43,12 +45,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int64_t by
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(uint32_t)bytes, 0x00020000);
 }
 
-template <int UNROLL, int NR, int LP>
+// Byte offset of vector u of this lane within an item (WC: wave-contiguous).
+template <int UNROLL, bool WC>
+__device__ __forceinline__ int item_off(int u) {
+    if constexpr (WC)
+        return (int)(threadIdx.x >> 6) * (UNROLL * 1024) + u * 1024 + (int)(threadIdx.x & 63) * 16;
+    else
+        return u * kBlock * 16 + (int)threadIdx.x * 16;
+}
+
+template <int UNROLL, int NR, int LP, bool WC>
 __device__ __forceinline__ void load_item(__amdgpu_buffer_rsrc_t r0, __amdgpu_buffer_rsrc_t r1, int base,
                                           u32x4 (&v)[UNROLL]) {
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
-        const int off = base + u * kBlock * 16;
+        const int off = base + item_off<UNROLL, WC>(u);
         v[u] = u32x4{0u, 0u, 0u, 0u};
         if constexpr (NR >= 1) v[u] = __builtin_amdgcn_raw_buffer_load_b128(r0, off, 0, LP);
         if constexpr (NR >= 2) v[u] ^= __builtin_amdgcn_raw_buffer_load_b128(r1, off, 0, LP);
@@ -56,7 +67,7 @@ __device__ __forceinline__ void load_item(__amdgpu_buffer_rsrc_t r0, __amdgpu_bu
 }
 
 // LP / SP: cache policy bits of loads / stores (0 or 2 = non-temporal).
-template <int UNROLL, int NR, bool WRITE, int LP, int SP>
+template <int UNROLL, int NR, bool WRITE, int LP, int SP, bool WC>
 __global__ __launch_bounds__(kBlock) void k_stream(const char *__restrict__ s0, const char *__restrict__ s1,
                                                    char *__restrict__ d, int64_t bytes, u32x4 *__restrict__ sink) {
     constexpr int kItem = kBlock * 16 * UNROLL;  // bytes per work item
@@ -71,15 +82,15 @@ __global__ __launch_bounds__(kBlock) void k_stream(const char *__restrict__ s0, 
         int it = blockIdx.x;
         // offsets stay below 2^31: items * kItem <= 2^30 and the grid adds
         // at most 2^12 items of at most 2^15 bytes
-        load_item<UNROLL, NR, LP>(r0, r1, it * kItem + threadIdx.x * 16, v);
+        load_item<UNROLL, NR, LP, WC>(r0, r1, it * kItem, v);
         for (; it < items; it += gridDim.x) {
             // past the last item the offset lies beyond the window: zeros, no traffic
-            load_item<UNROLL, NR, LP>(r0, r1, (it + (int)gridDim.x) * kItem + threadIdx.x * 16, vn);
-            const int base = it * kItem + threadIdx.x * 16;
+            load_item<UNROLL, NR, LP, WC>(r0, r1, (it + (int)gridDim.x) * kItem, vn);
+            const int base = it * kItem;
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
                 if constexpr (WRITE) {
-                    const int off = base + u * kBlock * 16;
+                    const int off = base + item_off<UNROLL, WC>(u);
                     const u32x4 o = NR == 0 ? u32x4{(uint32_t)off, 1u, 2u, 3u} : v[u];
                     __builtin_amdgcn_raw_buffer_store_b128(o, rd, off, 0, SP);
                 } else {
@@ -93,33 +104,40 @@ __global__ __launch_bounds__(kBlock) void k_stream(const char *__restrict__ s0, 
     if constexpr (!WRITE) sink[(int64_t)blockIdx.x * kBlock + threadIdx.x] = acc;
 }
 
-template <int NR, bool WRITE, int LP, int SP>
+template <int NR, bool WRITE, int LP, int SP, bool WC>
 hipError_t launch_u(const char *a, const char *b, char *c, int64_t bytes, int grid, int unroll, u32x4 *k,
                     hipStream_t st) {
     switch (unroll) {
-    case 2: hipLaunchKernelGGL((k_stream<2, NR, WRITE, LP, SP>), dim3(grid), dim3(kBlock), 0, st, a, b, c, bytes, k); break;
-    case 4: hipLaunchKernelGGL((k_stream<4, NR, WRITE, LP, SP>), dim3(grid), dim3(kBlock), 0, st, a, b, c, bytes, k); break;
-    case 8: hipLaunchKernelGGL((k_stream<8, NR, WRITE, LP, SP>), dim3(grid), dim3(kBlock), 0, st, a, b, c, bytes, k); break;
+    case 2: hipLaunchKernelGGL((k_stream<2, NR, WRITE, LP, SP, WC>), dim3(grid), dim3(kBlock), 0, st, a, b, c, bytes, k); break;
+    case 4: hipLaunchKernelGGL((k_stream<4, NR, WRITE, LP, SP, WC>), dim3(grid), dim3(kBlock), 0, st, a, b, c, bytes, k); break;
+    case 8: hipLaunchKernelGGL((k_stream<8, NR, WRITE, LP, SP, WC>), dim3(grid), dim3(kBlock), 0, st, a, b, c, bytes, k); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int NR, bool WRITE, int LP, int SP>
+hipError_t launch_l(const char *a, const char *b, char *c, int64_t bytes, int grid, int unroll, int layout, u32x4 *k,
+                    hipStream_t st) {
+    return layout ? launch_u<NR, WRITE, LP, SP, true>(a, b, c, bytes, grid, unroll, k, st)
+                  : launch_u<NR, WRITE, LP, SP, false>(a, b, c, bytes, grid, unroll, k, st);
+}
+
 template <int NR, bool WRITE>
 hipError_t launch(const void *s0, const void *s1, void *d, int64_t bytes, int grid, int unroll, int lpol, int spol,
-                  void *sink, hipStream_t st) {
+                  int layout, void *sink, hipStream_t st) {
     if (unroll != 2 && unroll != 4 && unroll != 8) return hipErrorInvalidValue;
     const int64_t item = (int64_t)kBlock * 16 * unroll;
     if (bytes <= 0 || grid < 1 || grid > 4096 || bytes % item != 0 || (lpol != 0 && lpol != 1) ||
-        (spol != 0 && spol != 1))
+        (spol != 0 && spol != 1) || (layout != 0 && layout != 1))
         return hipErrorInvalidValue;
     const char *a = static_cast<const char *>(s0), *b = static_cast<const char *>(s1);
     char *c = static_cast<char *>(d);
     u32x4 *k = static_cast<u32x4 *>(sink);
-    if (lpol == 0 && spol == 0) return launch_u<NR, WRITE, 0, 0>(a, b, c, bytes, grid, unroll, k, st);
-    if (lpol == 0 && spol == 1) return launch_u<NR, WRITE, 0, 2>(a, b, c, bytes, grid, unroll, k, st);
-    if (lpol == 1 && spol == 0) return launch_u<NR, WRITE, 2, 0>(a, b, c, bytes, grid, unroll, k, st);
-    return launch_u<NR, WRITE, 2, 2>(a, b, c, bytes, grid, unroll, k, st);
+    if (lpol == 0 && spol == 0) return launch_l<NR, WRITE, 0, 0>(a, b, c, bytes, grid, unroll, layout, k, st);
+    if (lpol == 0 && spol == 1) return launch_l<NR, WRITE, 0, 2>(a, b, c, bytes, grid, unroll, layout, k, st);
+    if (lpol == 1 && spol == 0) return launch_l<NR, WRITE, 2, 0>(a, b, c, bytes, grid, unroll, layout, k, st);
+    return launch_l<NR, WRITE, 2, 2>(a, b, c, bytes, grid, unroll, layout, k, st);
 }
 
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -213,29 +231,31 @@ int ceiling_mfma(const void *src, void *sink, int kind, int grid, int iters, voi
 
 // sink: device memory of grid * 256 * 16 bytes (the read stream's result,
 // so the loads cannot be dropped).
-int ceiling_read(const void *src, int64_t bytes, void *sink, int grid, int unroll, int lpol, void *stream) {
+int ceiling_read(const void *src, int64_t bytes, void *sink, int grid, int unroll, int lpol, int layout,
+                 void *stream) {
     if (!src || !sink) return (int)hipErrorInvalidValue;
-    return (int)launch<1, false>(src, nullptr, nullptr, bytes, grid, unroll, lpol, 0, sink,
+    return (int)launch<1, false>(src, nullptr, nullptr, bytes, grid, unroll, lpol, 0, layout, sink,
                                  static_cast<hipStream_t>(stream));
 }
 
-int ceiling_write(void *dst, int64_t bytes, int grid, int unroll, int spol, void *stream) {
+int ceiling_write(void *dst, int64_t bytes, int grid, int unroll, int spol, int layout, void *stream) {
     if (!dst) return (int)hipErrorInvalidValue;
-    return (int)launch<0, true>(nullptr, nullptr, dst, bytes, grid, unroll, 0, spol, nullptr,
+    return (int)launch<0, true>(nullptr, nullptr, dst, bytes, grid, unroll, 0, spol, layout, nullptr,
                                 static_cast<hipStream_t>(stream));
 }
 
-int ceiling_copy(const void *src, void *dst, int64_t bytes, int grid, int unroll, int lpol, int spol, void *stream) {
+int ceiling_copy(const void *src, void *dst, int64_t bytes, int grid, int unroll, int lpol, int spol, int layout,
+                 void *stream) {
     if (!src || !dst) return (int)hipErrorInvalidValue;
-    return (int)launch<1, true>(src, nullptr, dst, bytes, grid, unroll, lpol, spol, nullptr,
+    return (int)launch<1, true>(src, nullptr, dst, bytes, grid, unroll, lpol, spol, layout, nullptr,
                                 static_cast<hipStream_t>(stream));
 }
 
 // dst is read and written in place (its second source is itself).
-int ceiling_mix2(const void *src, void *dst, int64_t bytes, int grid, int unroll, int lpol, int spol,
+int ceiling_mix2(const void *src, void *dst, int64_t bytes, int grid, int unroll, int lpol, int spol, int layout,
                  void *stream) {
     if (!src || !dst) return (int)hipErrorInvalidValue;
-    return (int)launch<2, true>(src, dst, dst, bytes, grid, unroll, lpol, spol, nullptr,
+    return (int)launch<2, true>(src, dst, dst, bytes, grid, unroll, lpol, spol, layout, nullptr,
                                 static_cast<hipStream_t>(stream));
 }
 

@@ -68,3 +68,16 @@ def test_written_keys_are_the_planner_keys(A, tmp_path):
     env = dict(os.environ, TSMM_TILE_TABLE=str(tab), TSMM_STRICT_TABLE="1")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True)
     assert out.returncode == 0 and "ok" in out.stdout, out.stderr[-2000:]
+
+
+def test_ties_go_to_the_fewest_workgroups_per_cu(A):
+    t = lambda w: dict(kernel=1, rows_per_wave=1, waves_per_wg=4, wg_per_cu=w, splitk=1, nsplit=2)
+    # within TIE of the fastest: the fewest resident workgroups wins
+    ms, tile = A.pick([(5.00, t(4)), (5.05, t(1)), (5.02, t(2))])
+    assert tile["wg_per_cu"] == 1 and ms == 5.05
+    # outside TIE the fastest stays
+    ms, tile = A.pick([(5.00, t(4)), (5.00 * (1 + A.TIE) + 0.01, t(1))])
+    assert tile["wg_per_cu"] == 4
+    # equal counts: the faster one
+    ms, tile = A.pick([(5.01, t(2)), (5.00, t(2)), (4.99, t(8))])
+    assert ms == 5.00
