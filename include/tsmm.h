@@ -151,7 +151,7 @@ typedef struct tsmm_tile {
                               32-row tiles, 2, or 4 for native mode at
                               n = 128; TSMM_KERNEL_COLMAJOR: column
                               groups inside a workgroup, 1 or 2)        */
-    int32_t waves_per_wg;  /* wavefronts per workgroup: 1..16               */
+    int32_t waves_per_wg;  /* wavefronts per workgroup: 1, 2 or 4           */
     int32_t wg_per_cu;     /* resident workgroups per compute unit (grid =
                               CUs * wg_per_cu, capped by the work): 1..32   */
     int32_t splitk;        /* op T: number of partial sums P (1..65536);

@@ -12,13 +12,17 @@ largest power of two that fits -- each candidate is timed on inputs larger
 than the last-level cache, and the fastest one is recorded.  Candidates the
 library rejects (capacity, missing instantiation) are skipped.
 
-Timings within TIE of the fastest count as a tie, and a tie goes to the
-tile with the fewest resident workgroups per compute unit.  Where column
-groups share A rows (nsplit > 1), fewer resident workgroups keep the
-partner workgroups in step, so the second read of each A row hits the L2:
-at m = 2^23, k = n = 128 binary64 one workgroup per CU reads A once and
-four read it 1.4 times, at the same time per call.  Measured HBM traffic
-is not part of the timing, so the rule settles it.
+Timings within TIE of the fastest count as a tie.  Where column groups
+share A rows (nsplit > 1) the HBM traffic depends on how many workgroups
+a compute unit holds, which the timing does not see, and a tie goes to
+the count that reads A least (measured with the read counters at
+m = 2^23, k = n = 128 binary64, beta 0 / beta 1):
+  - row-major streaming kernel: the fewest (A read 1.00x / 1.27x at one
+    workgroup per CU, 1.3-1.5x / 1.7x at 2 to 16);
+  - column-major kernel: the most (1.28x / 1.00x at 16 per CU, 1.06x /
+    1.41x at one).
+A tile with one column group reads A once and goes first; other ties go
+to the fastest tile.
 
 The table is plain text, one entry per class (see tsmm_api.cpp), written
 atomically; classes already present are kept unless --retune is given, so
@@ -83,11 +87,21 @@ BATCH_CHUNKS = (512, 1024, 2048, 4096, 8192, 16384, 32768)
 TIE = 0.02  # relative spread of repeated timings of one tile on this part
 
 
+def tie_rank(t):
+    """Order among tied tiles: lower is preferred (see the module notes).
+    One column group (A read once by construction) comes first."""
+    if t["nsplit"] > 1 and t["kernel"] == T.KERNEL_STREAM:
+        return t["wg_per_cu"]
+    if t["nsplit"] > 1 and t["kernel"] == T.KERNEL_COLMAJOR:
+        return 64 - t["wg_per_cu"]
+    return 0
+
+
 def pick(timed):
-    """The chosen (ms, tile) of [(ms, tile), ...]: the fewest workgroups per
-    compute unit among the tiles within TIE of the fastest."""
+    """The chosen (ms, tile) of [(ms, tile), ...]: among the tiles within
+    TIE of the fastest, the one tie_rank prefers, then the faster."""
     fastest = min(ms for ms, _ in timed)
-    near = [(t["wg_per_cu"], ms, i) for i, (ms, t) in enumerate(timed) if ms <= fastest * (1.0 + TIE)]
+    near = [(tie_rank(t), ms, i) for i, (ms, t) in enumerate(timed) if ms <= fastest * (1.0 + TIE)]
     return timed[min(near)[2]]
 HEADLINE = ["n_f64_k8", "n_f64_k32", "n_f64_k128", "t_f64_64x64"]
 

@@ -14,18 +14,57 @@
 
 namespace tsmm {
 
-// One thread per 8 consecutive columns of a row (a 16-byte plane vector).
-template <typename T>
+// alpha*A rounded to T.  VEC (rows of A and out 16-byte aligned, k a
+// multiple of the vector width): one 16-byte vector per thread and step,
+// consecutive threads on consecutive vectors of a row, so that every load
+// and store instruction covers whole lines; otherwise one thread per 8
+// consecutive columns, element by element.
+template <typename T, bool VEC>
 __global__ void k_pack_a_scale(const T *__restrict__ A, int64_t lda, T *__restrict__ out, int64_t m, int64_t k,
                                double alpha) {
-    const int64_t g8 = (k + 7) / 8;
-    const int64_t total = m * g8;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = i / g8, c0 = (i - r * g8) * 8;
+    if constexpr (VEC) {
+        constexpr int VW = 16 / (int)sizeof(T);
+        typedef T vec_t __attribute__((ext_vector_type(VW)));
+        const int64_t gv = k / VW;
+        const int64_t total = m * gv;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t r = i / gv, c0 = (i - r * gv) * VW;
+            const vec_t x = *reinterpret_cast<const vec_t *>(A + r * lda + c0);
+            vec_t y;
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-            if (c0 + e < k) out[r * k + c0 + e] = (T)(alpha * (double)A[r * lda + c0 + e]);
+            for (int e = 0; e < VW; ++e) y[e] = (T)(alpha * (double)x[e]);
+            *reinterpret_cast<vec_t *>(out + r * k + c0) = y;
+        }
+    } else {
+        const int64_t g8 = (k + 7) / 8;
+        const int64_t total = m * g8;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t r = i / g8, c0 = (i - r * g8) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (c0 + e < k) out[r * k + c0 + e] = (T)(alpha * (double)A[r * lda + c0 + e]);
+        }
     }
+}
+
+template <typename T>
+hipError_t launch_pack_a_scale(const void *A, int64_t lda, void *out, int64_t m, int64_t k, double alpha,
+                               hipStream_t s) {
+    constexpr int VW = 16 / (int)sizeof(T);
+    const bool vec = k % VW == 0 && lda % VW == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(out) % 16 == 0;
+    const int64_t work = vec ? m * (k / VW) : m * ((k + 7) / 8);
+    const int block = 256;
+    const unsigned grid = (unsigned)std::min<int64_t>((work + block - 1) / block, 65536);
+    if (vec)
+        hipLaunchKernelGGL((k_pack_a_scale<T, true>), dim3(grid), dim3(block), 0, s, static_cast<const T *>(A), lda,
+                           static_cast<T *>(out), m, k, alpha);
+    else
+        hipLaunchKernelGGL((k_pack_a_scale<T, false>), dim3(grid), dim3(block), 0, s, static_cast<const T *>(A), lda,
+                           static_cast<T *>(out), m, k, alpha);
+    return hipGetLastError();
 }
 
 template <int TERMS>
@@ -61,11 +100,9 @@ hipError_t launch_pack_a(tsmm_dtype dt, int terms, const void *A, int64_t lda, v
         hipLaunchKernelGGL(k_pack_a_split<3>, dim3(grid), dim3(block), 0, s, static_cast<const float *>(A), lda,
                            static_cast<uint16_t *>(out), m, k, alpha);
     else if (dt == TSMM_F64)
-        hipLaunchKernelGGL(k_pack_a_scale<double>, dim3(grid), dim3(block), 0, s, static_cast<const double *>(A), lda,
-                           static_cast<double *>(out), m, k, alpha);
+        return launch_pack_a_scale<double>(A, lda, out, m, k, alpha, s);
     else if (dt == TSMM_F32)
-        hipLaunchKernelGGL(k_pack_a_scale<float>, dim3(grid), dim3(block), 0, s, static_cast<const float *>(A), lda,
-                           static_cast<float *>(out), m, k, alpha);
+        return launch_pack_a_scale<float>(A, lda, out, m, k, alpha, s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

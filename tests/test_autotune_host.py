@@ -70,14 +70,27 @@ def test_written_keys_are_the_planner_keys(A, tmp_path):
     assert out.returncode == 0 and "ok" in out.stdout, out.stderr[-2000:]
 
 
-def test_ties_go_to_the_fewest_workgroups_per_cu(A):
-    t = lambda w: dict(kernel=1, rows_per_wave=1, waves_per_wg=4, wg_per_cu=w, splitk=1, nsplit=2)
-    # within TIE of the fastest: the fewest resident workgroups wins
+def test_ties_go_to_the_tile_that_reads_A_least(A):
+    from paper_2208_08088_amd import tsmm as T
+    t = lambda w, kern=T.KERNEL_STREAM, ns=2: dict(kernel=kern, rows_per_wave=1, waves_per_wg=4, wg_per_cu=w,
+                                                   splitk=1, nsplit=ns)
+    # streaming kernel with column groups: the fewest resident workgroups
     ms, tile = A.pick([(5.00, t(4)), (5.05, t(1)), (5.02, t(2))])
     assert tile["wg_per_cu"] == 1 and ms == 5.05
     # outside TIE the fastest stays
     ms, tile = A.pick([(5.00, t(4)), (5.00 * (1 + A.TIE) + 0.01, t(1))])
     assert tile["wg_per_cu"] == 4
     # equal counts: the faster one
-    ms, tile = A.pick([(5.01, t(2)), (5.00, t(2)), (4.99, t(8))])
+    ms, tile = A.pick([(5.01, t(2)), (5.00, t(2)), (4.99 * (1 + 2 * A.TIE), t(8))])
     assert ms == 5.00
+    # column-major kernel with column groups: the most resident workgroups
+    C = T.KERNEL_COLMAJOR
+    ms, tile = A.pick([(5.00, t(1, C)), (5.05, t(16, C)), (5.02, t(4, C))])
+    assert tile["wg_per_cu"] == 16
+    # no column groups: the fastest
+    ms, tile = A.pick([(5.02, t(1, ns=1)), (5.00, t(8, ns=1))])
+    assert tile["wg_per_cu"] == 8
+    # one column group before column groups, for either kernel
+    for kern in (T.KERNEL_STREAM, C):
+        ms, tile = A.pick([(5.00, t(1, kern)), (5.00, t(16, kern)), (5.05, t(2, kern, ns=1))])
+        assert tile["nsplit"] == 1

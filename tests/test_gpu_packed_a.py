@@ -122,6 +122,28 @@ def test_native_packed_a(dtype, m, k, n):
     assert_normwise(host(Cp), ref, tol)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_native_packed_a_from_an_unaligned_A(dtype):
+    # A one element past a 16-byte boundary: the element-wise packing path
+    # (the vector path needs 16-byte rows), same values as the aligned one
+    m, k, n = 999, 32, 16
+    f = np.float64 if dtype == torch.float64 else np.float32
+    A = I.host_uniform((m, k), 9100, 1, dtype=f)
+    B = I.host_uniform((k, n), 9100, 2, dtype=f)
+    buf = torch.zeros(m * k + 1, dtype=dtype, device="cuda")
+    buf[1:] = dev(A, dtype).reshape(-1)
+    announce("packed A unaligned", dtype)
+    pk = T.pack(dev(B, dtype))
+    Cs = []
+    for Ad in (buf[1:].view(m, k), dev(A, dtype)):
+        C = torch.full((m, n), float("nan"), dtype=dtype, device="cuda")
+        T.execute_packed_a(T.plan(m, n, k, "N", dtype), T.pack_a(Ad, "native", 3.0), pk, C, 0.0)
+        Cs.append(C)
+    assert torch.equal(Cs[0], Cs[1])
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    assert_normwise(host(Cs[0]), oracle.gemm_n(A, B, None, 3.0, 0.0), tol)
+
+
 @pytest.mark.parametrize("mode", ["native", "bf16x3", "bf16x6"])
 def test_packed_a_small_integers_exact(mode):
     # every product and partial sum is exact: the result equals the oracle
