@@ -18,7 +18,8 @@ a compute unit holds, which the timing does not see, and a tie goes to
 the count that reads A least (measured with the read counters at
 m = 2^23, k = n = 128 binary64, beta 0 / beta 1):
   - row-major streaming kernel: the fewest (A read 1.00x / 1.27x at one
-    workgroup per CU, 1.3-1.5x / 1.7x at 2 to 16);
+    workgroup per CU, 1.3-1.5x / 1.7x at 2 to 16), then the fewest row
+    tiles per wavefront (two read A 1.05x / 1.8x at one workgroup per CU);
   - column-major kernel: the most (1.28x / 1.00x at 16 per CU, 1.06x /
     1.41x at one).
 A tile with one column group reads A once and goes first; other ties go
@@ -91,10 +92,10 @@ def tie_rank(t):
     """Order among tied tiles: lower is preferred (see the module notes).
     One column group (A read once by construction) comes first."""
     if t["nsplit"] > 1 and t["kernel"] == T.KERNEL_STREAM:
-        return t["wg_per_cu"]
+        return (1, t["wg_per_cu"], t["rows_per_wave"])
     if t["nsplit"] > 1 and t["kernel"] == T.KERNEL_COLMAJOR:
-        return 64 - t["wg_per_cu"]
-    return 0
+        return (1, -t["wg_per_cu"], 0)
+    return (0, 0, 0)
 
 
 def pick(timed):
@@ -142,17 +143,17 @@ def candidates(p):
     base = p.get_tile()
     base.pop("chunk_rows", None)  # batched plans only
     out = [dict(base)]
-    # the natural family's default tile, whatever the plan picked
-    nat = dict(base)
-    if base["kernel"] != natural_kernel(p):
-        try:
-            p.set_tile(kernel=natural_kernel(p))
-            nat = p.get_tile()
-            nat.pop("chunk_rows", None)
-            out.append(dict(nat))
-        except T.TsmmError:
-            nat = None
-        p.set_tile(**base)
+    # the natural family's built-in default tile, whatever the plan picked
+    # (the table's tile may be a neighbour of it; the sweep is centred on
+    # the default, so that a retune does not drift with the table)
+    try:
+        p.set_tile(kernel=natural_kernel(p))
+        nat = p.get_tile()
+        nat.pop("chunk_rows", None)
+        out.append(dict(nat))
+    except T.TsmmError:
+        nat = None
+    p.set_tile(**base)
     kern = nat["kernel"] if nat else None
     if kern == T.KERNEL_STREAM:
         for ns in sorted({nat["nsplit"], nat["nsplit"] * 2}):

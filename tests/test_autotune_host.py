@@ -90,6 +90,10 @@ def test_ties_go_to_the_tile_that_reads_A_least(A):
     # no column groups: the fastest
     ms, tile = A.pick([(5.02, t(1, ns=1)), (5.00, t(8, ns=1))])
     assert tile["wg_per_cu"] == 8
+    # streaming kernel: then the fewest row tiles per wavefront
+    r = lambda rt: dict(t(1), rows_per_wave=rt)
+    ms, tile = A.pick([(5.00, r(2)), (5.01, r(1))])
+    assert tile["rows_per_wave"] == 1
     # one column group before column groups, for either kernel
     for kern in (T.KERNEL_STREAM, C):
         ms, tile = A.pick([(5.00, t(1, kern)), (5.00, t(16, kern)), (5.05, t(2, kern, ns=1))])
