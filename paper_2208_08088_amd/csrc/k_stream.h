@@ -213,10 +213,12 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
                     BufIO<T>::store_vec(v, rc[rt], voff(g, r));
                 }
         } else {
+            // the column tiles of one row quad back to back: the parts of a
+            // 128-byte line of C reach the cache together
 #pragma unroll
-            for (int tt = 0; tt < NT; ++tt)
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int tt = 0; tt < NT; ++tt) {
                     if constexpr (!CPRE) cv[rt][tt][r] = beta != 0.0 ? BufIO<T>::load1(rl[rt], coff(tt, r)) : (T)0;
                     BufIO<T>::store1((T)epilogue(alpha, (double)acc[rt][tt][r], beta, (double)cv[rt][tt][r]), rc[rt],
                                      coff(tt, r));
