@@ -273,9 +273,9 @@ def ceilings(torch, nbytes=4 << 30, reps=5, detail=False):
                          wave_contiguous=wl)
     del s0, d, sink
     torch.cuda.empty_cache()
-    out["kernel"] = ("libtsmm_ceiling.so stream kernels (two-stage register pipeline), %d GiB buffers, 16-byte "
+    out["kernel"] = ("libtsmm_ceiling.so stream kernels (two-stage register pipeline), %d MiB buffers, 16-byte "
                      "buffer loads/stores; best of %d launch shapes x cache policies x 2 item layouts"
-                     % (nbytes >> 30, len(CEIL_GRIDS) * len(CEIL_UNROLLS)))
+                     % (nbytes >> 20, len(CEIL_GRIDS) * len(CEIL_UNROLLS)))
     if detail:
         out["sweep"] = rows
     return out
