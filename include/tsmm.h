@@ -310,10 +310,13 @@ tsmm_status tsmm_plan_set_mode(tsmm_plan_t plan, tsmm_mode mode);
 /* Replace the tile (autotuner and tests).  The tile is validated against
  * the shape and the device limits; INVALID_VALUE / NOT_SUPPORTED if it
  * cannot run.  A batched plan takes kernel TSMM_KERNEL_BATCHED (or AUTO)
- * and only chunk_rows may differ from its defaults; the chunk list is
- * rebuilt on the device (synchronously), so the plan must be idle, and a
- * plan from which a graph was made refuses it (INVALID_VALUE) while the
- * graph exists. */
+ * and only chunk_rows and wg_per_cu may differ from its defaults
+ * (wg_per_cu 1, 2 or 4 resident workgroups per compute unit, as far as the
+ * LDS holds that many copies of the largest packed B, else INVALID_VALUE;
+ * 0 keeps the plan's count, or takes the table's when chunk_rows is 0
+ * too); the chunk list is rebuilt on the device (synchronously), so the
+ * plan must be idle, and a plan from which a graph was made refuses it
+ * (INVALID_VALUE) while the graph exists. */
 tsmm_status tsmm_plan_set_tile(tsmm_plan_t plan, const tsmm_tile *tile);
 tsmm_status tsmm_plan_get_tile(tsmm_plan_t plan, tsmm_tile *tile);
 
@@ -448,7 +451,8 @@ tsmm_status tsmm_execute_packed_a(tsmm_plan_t plan, tsmm_packed_t packed_a, tsmm
  * launch: instance b is m[b] x k[b] times k[b] x n[b].  Host arrays.  The
  * plan cuts the instances into chunks of rows (sized from chunk_rows, from
  * the tile table's batched entry for the dtype, else 4096; instances of one kernel
- * variant together, longest first) that the launch's workgroups take from
+ * variant together, longest first) that the launch's workgroups (the
+ * table entry's workgroups per compute unit, else one) take from
  * a device counter; the plan owns that counter, which every launch leaves
  * at zero, so the launches (or graph replays) of one plan must not overlap
  * in time.  Results do not depend on which workgroup takes which chunk.

@@ -32,6 +32,7 @@ an interrupted run resumes where it stopped.
 from __future__ import annotations
 
 import argparse
+import itertools
 import os
 import sys
 import time
@@ -85,6 +86,7 @@ CLASSES = {
     "b_bf16_512": ("B", torch.bfloat16, "native", 512, 0, 0),
 }
 BATCH_CHUNKS = (512, 1024, 2048, 4096, 8192, 16384, 32768)
+BATCH_WPC = (1, 2, 4)
 TIE = 0.02  # relative spread of repeated timings of one tile on this part
 
 
@@ -218,7 +220,8 @@ def time_plan(p, As, pk, C, beta, reps):
 
 
 def tune_batched(name, spec, reps, log):
-    """Chunk size of the persistent batched launch for one dtype."""
+    """Chunk size and resident workgroups per CU of the persistent batched
+    launch for one dtype."""
     _, dt, _, count, _, _ = spec
     ms, ns, ks = I.batched_shapes(count, I.BASE_SEED)
     As, packs, Cs = [], [], []
@@ -230,8 +233,11 @@ def tune_batched(name, spec, reps, log):
     bp = T.plan_batched(ms, ns, ks, dt)
     bp.bind(As, packs, Cs)
     best = None
-    for chunk in BATCH_CHUNKS:
-        bp.set_chunk_rows(chunk)
+    for chunk, wpc in itertools.product(BATCH_CHUNKS, BATCH_WPC):
+        try:
+            bp.set_chunk_rows(chunk, wpc)
+        except T.TsmmError:
+            continue  # that many copies of the largest packed B do not fit the LDS
         bp.execute()  # warm-up
         times = []
         for _ in range(reps):
@@ -243,7 +249,7 @@ def tune_batched(name, spec, reps, log):
             e1.synchronize()
             times.append(e0.elapsed_time(e1))
         ms_ = float(np.median(times))
-        log("  %-14s chunk_rows=%d  %.3f ms" % (name, chunk, ms_))
+        log("  %-14s chunk_rows=%d wg_per_cu=%d  %.3f ms" % (name, chunk, wpc, ms_))
         if best is None or ms_ < best[0]:
             best = (ms_, bp.get_tile())
     t = best[1]

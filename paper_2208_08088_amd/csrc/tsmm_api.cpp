@@ -699,15 +699,23 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
 
 bool valid_chunk_rows(int c) { return c >= kBatchChunkMin && c <= kBatchChunkMax && is_pow2(c); }
 
-// Chunk size of batched plans of `dtype`: the table's batched entry, else
-// the default.
-int batched_table_chunk(tsmm_dtype dtype, const tsmm_device_caps &caps, bool *from_table) {
+// Workgroups per compute unit a batched plan can keep resident: 1, 2 or
+// 4, as far as the LDS holds that many copies of the largest packed B.
+bool batched_wpc_fits(const tsmm_plan_s &p, int wpc) {
+    return (wpc == 1 || wpc == 2 || wpc == 4) && (int64_t)wpc * (int64_t)(p.batch_lds + 1024) <= p.caps.lds_bytes_per_cu;
+}
+
+// Chunk size and workgroups per CU of batched plans of `dtype`: the
+// table's batched entry, else the defaults (one workgroup per CU).
+int batched_table_chunk(tsmm_dtype dtype, const tsmm_device_caps &caps, bool *from_table, int *wpc = nullptr) {
     *from_table = false;
+    if (wpc) *wpc = 1;
     Table &tab = table();
     if (table_usable(caps)) {
         auto it = tab.entries.find(TableKey{kLayoutBatched, dtype, TSMM_MODE_NATIVE, 0, 0, 0});
         if (it != tab.entries.end() && valid_chunk_rows(it->second.chunk_rows)) {
             *from_table = true;
+            if (wpc) *wpc = it->second.wg_per_cu;
             return it->second.chunk_rows;
         }
     }
@@ -735,24 +743,33 @@ tsmm_status batched_chunks(tsmm_plan_s &p, int chunk_rows) {
     return TSMM_SUCCESS;
 }
 
-// tsmm_plan_set_tile on a batched plan: only the chunk size is free.
+// tsmm_plan_set_tile on a batched plan: the chunk size and the workgroups
+// per compute unit are free.
 tsmm_status set_batched_tile(tsmm_plan_s &p, const tsmm_tile &t) {
     if (t.kernel != TSMM_KERNEL_AUTO && t.kernel != TSMM_KERNEL_BATCHED)
         return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans run the batched kernel");
     if ((t.rows_per_wave != 0) || (t.waves_per_wg != 0 && t.waves_per_wg != kBatchWaves) ||
-        (t.wg_per_cu != 0 && t.wg_per_cu != 1) || (t.splitk != 0 && t.splitk != 1) ||
-        (t.nsplit != 0 && t.nsplit != 1))
-        return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take only chunk_rows (%d waves, 1 workgroup per CU)",
+        (t.splitk != 0 && t.splitk != 1) || (t.nsplit != 0 && t.nsplit != 1))
+        return fail(TSMM_ERROR_NOT_SUPPORTED, "batched plans take only chunk_rows and wg_per_cu (%d waves)",
                     kBatchWaves);
     bool from_table = false;
-    const int chunk = t.chunk_rows ? t.chunk_rows : batched_table_chunk(p.dtype, p.caps, &from_table);
+    int table_wpc = 1;
+    const int chunk = t.chunk_rows ? t.chunk_rows : batched_table_chunk(p.dtype, p.caps, &from_table, &table_wpc);
     if (!valid_chunk_rows(chunk))
         return fail(TSMM_ERROR_INVALID_VALUE, "chunk_rows %d: a power of two in %d..%d", chunk, kBatchChunkMin,
                     kBatchChunkMax);
+    // wg_per_cu 0: the table's with the table's chunk size, else the plan's current one
+    const int wpc = t.wg_per_cu ? t.wg_per_cu
+                                : t.chunk_rows ? p.tile.wg_per_cu
+                                               : (from_table && batched_wpc_fits(p, table_wpc) ? table_wpc : 1);
+    if (!batched_wpc_fits(p, wpc))
+        return fail(TSMM_ERROR_INVALID_VALUE, "wg_per_cu %d: 1, 2 or 4 workgroups of %zu LDS bytes within %d", wpc,
+                    p.batch_lds, p.caps.lds_bytes_per_cu);
     if (p.graphs > 0) return fail(TSMM_ERROR_INVALID_VALUE, "a graph captured from this plan still exists");
     hipError_t e = hipSetDevice(p.device);
     if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
     if (e != hipSuccess) return hip_fail(e, "batched plan re-tile");
+    p.tile.wg_per_cu = wpc;
     tsmm_status st = batched_chunks(p, chunk);
     if (st != TSMM_SUCCESS) return st;
     p.tile_from_table = from_table;
@@ -1755,12 +1772,15 @@ tsmm_status tsmm_plan_batched(int64_t count, const int64_t *m, const int64_t *n,
         const int KC = dtype == TSMM_BF16 ? kclass32(I.k) : kclass4(I.k);
         p->batch_lds = std::max(p->batch_lds, batched_lds_bytes(dtype, KC, ntclass(I.n)));
     }
-    // the batched kernel's fixed workgroup (kBatchWaves wavefronts), one per
-    // compute unit (two wavefronts per SIMD); chunks are handed out at run
-    // time, so the grid only needs to fill the device
+    // the batched kernel's fixed workgroup (kBatchWaves wavefronts), one
+    // per compute unit (two wavefronts per SIMD) unless the table asks for
+    // more; chunks are handed out at run time, so the grid only needs to
+    // fill the device
     bool from_table = false;
-    const int chunk = batched_table_chunk(dtype, p->caps, &from_table);
-    p->tile = tsmm_tile{TSMM_KERNEL_BATCHED, 0, kBatchWaves, 1, 1, 1, chunk};
+    int wpc = 1;
+    const int chunk = batched_table_chunk(dtype, p->caps, &from_table, &wpc);
+    if (!batched_wpc_fits(*p, wpc)) wpc = 1;
+    p->tile = tsmm_tile{TSMM_KERNEL_BATCHED, 0, kBatchWaves, wpc, 1, 1, chunk};
     p->tile_from_table = from_table;
     p->block = 64 * kBatchWaves;
 

@@ -471,10 +471,13 @@ class BatchedPlan:
     def handle(self):
         return self._h
 
-    def set_chunk_rows(self, chunk_rows: int = 0):
+    def set_chunk_rows(self, chunk_rows: int = 0, wg_per_cu: int = 0):
         """Rows per work item of the persistent launch (0: the tile table's
-        or the default); the plan must be idle and have no live graph."""
-        _set_tile(self._h, kernel=KERNEL_BATCHED, chunk_rows=chunk_rows)
+        or the default) and resident workgroups per compute unit (1, 2 or 4
+        as the LDS allows; 0: the table's with the table's chunk size, else
+        the plan's current count); the plan must be idle and have no live
+        graph."""
+        _set_tile(self._h, kernel=KERNEL_BATCHED, chunk_rows=chunk_rows, wg_per_cu=wg_per_cu)
         return self
 
     def get_tile(self) -> dict:

@@ -114,15 +114,29 @@ def test_chunk_size_does_not_change_results(dtype):
     announce("chunk default", dtype, t["chunk_rows"])
     bp.execute(As, packs, Cs)
     ref = [c.clone() for c in Cs]
-    for chunk in (256, 1024, 65536):
-        announce("chunk", dtype, chunk)
-        bp.set_chunk_rows(chunk)
-        assert bp.get_tile()["chunk_rows"] == chunk
+    for chunk, wpc in ((256, 1), (1024, 1), (65536, 1), (1024, 2), (256, 4)):
+        announce("chunk", dtype, chunk, "wg_per_cu", wpc)
+        try:
+            bp.set_chunk_rows(chunk, wpc)
+        except T.TsmmError as e:
+            # more copies of the largest packed B than the LDS holds
+            assert wpc > 1 and e.status == T.INVALID_VALUE, e
+            continue
+        t = bp.get_tile()
+        assert t["chunk_rows"] == chunk and t["wg_per_cu"] == wpc
+        assert "wg_per_cu=%d" % wpc in bp.describe()
         for c in Cs:
             c.zero_()
         bp.execute()
         for b in range(count):
-            assert torch.equal(Cs[b], ref[b]), (chunk, b)
+            assert torch.equal(Cs[b], ref[b]), (chunk, wpc, b)
+    # the workgroup count stays when only the chunk size changes
+    bp.set_chunk_rows(1024, 1)
+    bp.set_chunk_rows(2048)
+    assert bp.get_tile()["wg_per_cu"] == 1
+    with pytest.raises(T.TsmmError) as e:
+        bp.set_chunk_rows(1024, 3)
+    assert e.value.status == T.INVALID_VALUE
     for b in range(count):
         if ms[b]:
             assert_normwise(host(Cs[b]), oracle.gemm_n(Ah[b], Bh[b]), 1e-6 if dtype == torch.float32 else 1e-5)
