@@ -280,6 +280,8 @@ class Plan:
         self.m, self.n, self.k, self.layout, self.dtype = m, n, k, layout, dtype
         self.mode = MODE_NATIVE
         self._ws = None
+        self._ws_bytes = None  # the plan's workspace need, while its tile stands
+        self._stream_set = None  # the stream last given to tsmm_plan_set_stream
 
     @property
     def handle(self):
@@ -311,7 +313,7 @@ class Plan:
         _need_cuda(A, "A", in_dt, a_shape, colmajor=cm)
         _need_cuda(C, "C", _OUT_OF_DT[self.dtype], (self.m, self.n), colmajor=cm)
         lib = _lib()
-        _check(lib.tsmm_plan_set_stream(self._h, _stream()), "tsmm_plan_set_stream")
+        self._set_stream()
         # the candidates run on plan-owned scratch, never on this binding's
         # tensor, which is released first
         self._drop_workspace()
@@ -342,12 +344,23 @@ class Plan:
         if self._ws is not None:
             _check(_lib().tsmm_plan_set_workspace(self._h, None, 0), "tsmm_plan_set_workspace")
             self._ws = None
+        self._ws_bytes = None  # the tile (or mode) changes with every caller of this
 
     def _ensure_workspace(self):
-        nb = self.workspace_bytes()
+        if self._ws_bytes is None:
+            self._ws_bytes = self.workspace_bytes()
+        nb = self._ws_bytes
         if nb and (self._ws is None or self._ws.numel() < nb):
             self._ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
             _check(_lib().tsmm_plan_set_workspace(self._h, _ptr(self._ws), nb), "tsmm_plan_set_workspace")
+
+    def _set_stream(self):
+        """Queue this plan's launches on torch's current stream (the C call
+        only when the stream changed)."""
+        st = torch.cuda.current_stream().cuda_stream
+        if st != self._stream_set:
+            _check(_lib().tsmm_plan_set_stream(self._h, ctypes.c_void_p(st)), "tsmm_plan_set_stream")
+            self._stream_set = st
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
@@ -382,6 +395,9 @@ def plan_with_caps(m, n, k, layout="N", dtype=torch.float64, compute_units=256, 
 def _leading_dim(t, name, dtype, shape, colmajor):
     """The stride between rows (row-major) or columns (column-major) of a
     2-D device tensor whose elements within a row (column) are adjacent."""
+    if (not colmajor and isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.shape == shape
+            and t.is_contiguous()):
+        return max(1, shape[1])  # a dense row-major matrix: the common case, checked in one pass
     if not isinstance(t, torch.Tensor):
         raise TypeError("%s must be a torch.Tensor" % name)
     if t.device.type != "cuda":
@@ -418,9 +434,8 @@ def execute(p: Plan, A: torch.Tensor, packed: Packed, C: torch.Tensor, alpha: fl
     if packed.layout == OP_T and packed._keep is not None:
         _need_cuda(packed._keep, "B")
     p._ensure_workspace()
-    lib = _lib()
-    _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
-    _check(lib.tsmm_execute_ld(p.handle, _ptr(A), lda, packed.handle, _ptr(C), ldc, float(alpha), float(beta)),
+    p._set_stream()
+    _check(_lib().tsmm_execute_ld(p.handle, _ptr(A), lda, packed.handle, _ptr(C), ldc, float(alpha), float(beta)),
            "tsmm_execute_ld")
     return C
 
@@ -438,9 +453,8 @@ def execute_noalloc(p: Plan, A: torch.Tensor, packed: Packed, C: torch.Tensor, a
     _need_cuda(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n), colmajor=cm)
     if packed.layout == OP_T and packed._keep is not None:
         _need_cuda(packed._keep, "B")
-    lib = _lib()
-    _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
-    _check(lib.tsmm_execute_noalloc(p.handle, _ptr(A), packed.handle, _ptr(C), float(alpha), float(beta)),
+    p._set_stream()
+    _check(_lib().tsmm_execute_noalloc(p.handle, _ptr(A), packed.handle, _ptr(C), float(alpha), float(beta)),
            "tsmm_execute_noalloc")
     return C
 
@@ -450,9 +464,8 @@ def execute_packed_a(p: Plan, packed_a: PackedA, packed: Packed, C: torch.Tensor
     torch's current stream; C row-major m x n, contiguous."""
     _need_cuda(C, "C", _OUT_OF_DT[p.dtype], (p.m, p.n))
     p._ensure_workspace()
-    lib = _lib()
-    _check(lib.tsmm_plan_set_stream(p.handle, _stream()), "tsmm_plan_set_stream")
-    _check(lib.tsmm_execute_packed_a(p.handle, packed_a.handle, packed.handle, _ptr(C), float(beta)),
+    p._set_stream()
+    _check(_lib().tsmm_execute_packed_a(p.handle, packed_a.handle, packed.handle, _ptr(C), float(beta)),
            "tsmm_execute_packed_a")
     return C
 
