@@ -149,9 +149,12 @@ typedef struct tsmm_tile {
                               8 (TSMM_KERNEL_VALU64: C columns per
                               wavefront, 16 or 32; TSMM_KERNEL_WIDE:
                               32-row tiles, 2, or 4 for native mode at
-                              n = 128; TSMM_KERNEL_COLMAJOR: column
-                              groups inside a workgroup, 1 or 2)        */
-    int32_t waves_per_wg;  /* wavefronts per workgroup: 1, 2 or 4           */
+                              n = 128, with 4 wavefronts; 1 with 8;
+                              TSMM_KERNEL_COLMAJOR: column groups
+                              inside a workgroup, 1 or 2)               */
+    int32_t waves_per_wg;  /* wavefronts per workgroup: 1, 2 or 4
+                              (TSMM_KERNEL_WIDE: 4, one per SIMD, or 8,
+                              two per SIMD)                             */
     int32_t wg_per_cu;     /* resident workgroups per compute unit (grid =
                               CUs * wg_per_cu, capped by the work): 1..32   */
     int32_t splitk;        /* op T: number of partial sums P (1..65536);

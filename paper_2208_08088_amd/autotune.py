@@ -192,9 +192,11 @@ def candidates(p):
             for P in (256, 512, 1024, 2048):
                 out.append(dict(kernel=kern, rows_per_wave=rg, waves_per_wg=4, wg_per_cu=1, splitk=P, nsplit=1))
     if p.dtype == T.F32 and p.layout == T.OP_N and p.n in (128, 256) and 0 < p.k <= 256 and p.k % 8 == 0:
-        # the wide kernels (32-row tiles per wavefront; 4 only at n = 128)
+        # the wide kernels (32-row tiles per wavefront; 4 only at n = 128),
+        # four wavefronts per workgroup, or eight with one row tile each
         for rt in ((2, 4) if p.n == 128 and p.mode == T.MODE_NATIVE else (2,)):
             out.append(dict(kernel=T.KERNEL_WIDE, rows_per_wave=rt, waves_per_wg=4, wg_per_cu=1, splitk=1, nsplit=1))
+        out.append(dict(kernel=T.KERNEL_WIDE, rows_per_wave=1, waves_per_wg=8, wg_per_cu=1, splitk=1, nsplit=1))
     seen, uniq = set(), []
     for c in out:
         key = tuple(sorted(c.items()))

@@ -6,8 +6,8 @@
 
 namespace tsmm {
 
-StreamFn find_stream_f64(int KC, int NT, int RT, bool vec, bool il);
-StreamFn find_stream_f32(int KC, int NT, int RT, bool vec, bool il);
+StreamFn find_stream_f64(int KC, int NT, int RT, bool vec, int cm);
+StreamFn find_stream_f32(int KC, int NT, int RT, bool vec, int cm);
 
 static inline unsigned blocks_for(int64_t count, int block) {
     return (unsigned)((count + block - 1) / block);
@@ -149,21 +149,21 @@ hipError_t launch_simple_t(tsmm_dtype dt, const void *A, const void *B, void *C,
 
 // ------------------------------------------------------- stream dispatch
 
-static StreamFn find_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il) {
-    if (dt == TSMM_F64) return find_stream_f64(KC, NT, RT, vec, il);
-    if (dt == TSMM_F32) return find_stream_f32(KC, NT, RT, vec, il);
+static StreamFn find_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, int cm) {
+    if (dt == TSMM_F64) return find_stream_f64(KC, NT, RT, vec, cm);
+    if (dt == TSMM_F32) return find_stream_f32(KC, NT, RT, vec, cm);
     return nullptr;
 }
 
-bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il) {
-    return find_stream(dt, KC, NT, RT, vec, il) != nullptr;
+bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, int cm) {
+    return find_stream(dt, KC, NT, RT, vec, cm) != nullptr;
 }
 
-hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il, const void *A,
+hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, int cm, const void *A,
                          const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldc,
                          double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
                          hipStream_t s) {
-    StreamFn fn = find_stream(dt, KC, NT, RT, vec, il);
+    StreamFn fn = find_stream(dt, KC, NT, RT, vec, cm);
     if (!fn || nsplit < 1 || NT * nsplit != nt_total) return hipErrorInvalidValue;
     return fn(A, Bfrag, C, m, n, k, lda, ldc, alpha, beta, grid, block, nt_total, nsplit, s);
 }

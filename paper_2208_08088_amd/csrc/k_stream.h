@@ -98,7 +98,22 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
 // into a_load.  C rows are read through a resource that is empty when
 // beta == 0 (no traffic, no branch), before the prefetch is issued, so the
 // epilogue's wait for them does not include the prefetch.
-template <typename T, int KC, int NT, int RT, bool VEC, bool IL, bool CPRE = true>
+// The neighbouring lane's value (lane ^ 1): DPP quad permutation [1, 0, 3, 2]
+// on both halves of a binary64 value.
+__device__ __forceinline__ double lane_pair_swap(double x) {
+    const u32x2 w = __builtin_bit_cast(u32x2, x);
+    u32x2 r;
+    r[0] = (uint32_t)__builtin_amdgcn_mov_dpp((int)w[0], 0xB1, 0xF, 0xF, false);
+    r[1] = (uint32_t)__builtin_amdgcn_mov_dpp((int)w[1], 0xB1, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, r);
+}
+
+// How C moves (CM): 0 element by element; 1 interleaved columns (the
+// fragments of PG adjacent columns in one lane, 16-byte vectors); 2 lane
+// pairs (binary64, one column tile, n even): lanes j and j ^ 1 swap half of
+// their accumulators so that each holds two adjacent columns of a row and C
+// moves in 16-byte vectors with the plain column order of the packed B.
+template <typename T, int KC, int NT, int RT, bool VEC, int CM, bool CPRE = true>
 __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__restrict__ Bsrc, int bstride,
                                             T *__restrict__ C, int64_t m, int n, int k, int lda, int ldc,
                                             bool kfull, double alpha,
@@ -119,13 +134,15 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
         rc[rt] = make_rsrc(C + row0 * ldc + col0, bytes);
         rl[rt] = make_rsrc(C + row0 * ldc + col0, beta != 0.0 ? bytes : 0);
     }
-    // With interleaved columns (IL; tsmm_internal.h) tile tt of lane j is
+    // With interleaved columns (CM 1; tsmm_internal.h) tile tt of lane j is
     // column colp(tt) of the column group, a lane holds PG adjacent columns
     // of each row in the tiles of one group, and C moves in 16-byte vectors
     // (n is then a multiple of PG); otherwise element by element.
-    constexpr int PG = IL ? Mfma4<T>::VW : 1;
-    static_assert(!IL || NT % PG == 0, "interleave groups must be whole");
-    constexpr bool cvec = IL;
+    constexpr int PG = CM == 1 ? Mfma4<T>::VW : 1;
+    static_assert(CM != 1 || NT % PG == 0, "interleave groups must be whole");
+    constexpr bool cvec = CM == 1;
+    constexpr bool PAIR = CM == 2;
+    static_assert(!PAIR || (sizeof(T) == 8 && NT == 1 && CPRE), "lane pairs: binary64, one column tile");
     auto colp = [=](int tt) { return 16 * PG * (tt / PG) + PG * j + tt % PG; };
     // byte offset of accumulator element (tt, r): row M::row(q, r), column
     // colp(tt); kOOB for columns beyond n
@@ -137,11 +154,22 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
     auto voff = [=](int g, int r) {
         return (col0 + colp(PG * g) < n) ? (M::row(q, r) * ldc + colp(PG * g)) * SZ : kOOB;
     };
+    // lane pairs: after the swap the even lane of a pair holds row
+    // M::row(q, 2p) and the odd lane row M::row(q, 2p + 1), both at columns
+    // j & ~1 and j | 1 (whole vectors lie inside or outside n when n is even)
+    const int odd = j & 1;
+    auto poff = [=](int p) {
+        return (col0 + (j & ~1) < n) ? (M::row(q, 2 * p + odd) * ldc + (j & ~1)) * SZ : kOOB;
+    };
     T cv[RT][NT][4];
+    typename M::vec cp[RT][2];
     if constexpr (CPRE) {
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-            if constexpr (cvec) {
+            if constexpr (PAIR) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p) cp[rt][p] = BufIO<T>::load_vec(rl[rt], poff(p));
+            } else if constexpr (cvec) {
 #pragma unroll
                 for (int g = 0; g < NT / PG; ++g)
 #pragma unroll
@@ -195,7 +223,18 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
     // spoken for), C is read here, and only when beta != 0.
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-        if constexpr (cvec) {
+        if constexpr (PAIR) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const T lo = acc[rt][0][2 * p], hi = acc[rt][0][2 * p + 1];
+                const T got = lane_pair_swap(odd ? lo : hi);
+                const T c0 = odd ? got : lo, c1 = odd ? hi : got;  // columns j & ~1, j | 1
+                typename M::vec v;
+                v[0] = (T)epilogue(alpha, (double)c0, beta, (double)cp[rt][p][0]);
+                v[1] = (T)epilogue(alpha, (double)c1, beta, (double)cp[rt][p][1]);
+                BufIO<T>::store_vec(v, rc[rt], poff(p));
+            }
+        } else if constexpr (cvec) {
 #pragma unroll
             for (int g = 0; g < NT / PG; ++g)
 #pragma unroll
@@ -230,7 +269,7 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
 // KC: packed k class; NT: 16-column tiles per workgroup (all of n, or one
 // column group of it); RT: 16-row tiles per wavefront step; VEC: vector
 // k-slot mapping.  nt_total is the number of column tiles of the packed B.
-template <typename T, int KC, int NT, int RT, bool VEC, bool IL>
+template <typename T, int KC, int NT, int RT, bool VEC, int CM>
 __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A,
                                                           const T *__restrict__ Bf,
                                                           T *__restrict__ C, int64_t m, int n,
@@ -289,19 +328,19 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(const T *__restrict__ A
     // compiler sink the prefetch past it); a pair's second step may lie past
     // the last tile, where its loads return 0 and its stores are dropped.
     for (; t < ntile; t += 2 * tstride) {
-        stream_step<T, KC, NT, RT, VEC, IL>(A, Bsrc, bstride, C, m, n, k, lda, ldc, kfull, alpha, beta, col0, t,
+        stream_step<T, KC, NT, RT, VEC, CM>(A, Bsrc, bstride, C, m, n, k, lda, ldc, kfull, alpha, beta, col0, t,
                                             t + tstride, voff0, q, lane, j, a0, a1);
-        stream_step<T, KC, NT, RT, VEC, IL>(A, Bsrc, bstride, C, m, n, k, lda, ldc, kfull, alpha, beta, col0,
+        stream_step<T, KC, NT, RT, VEC, CM>(A, Bsrc, bstride, C, m, n, k, lda, ldc, kfull, alpha, beta, col0,
                                             t + tstride,
                                             t + 2 * tstride, voff0, q, lane, j, a1, a0);
     }
 }
 
-template <typename T, int KC, int NT, int RT, bool VEC, bool IL>
+template <typename T, int KC, int NT, int RT, bool VEC, int CM>
 hipError_t run_stream(const void *A, const void *Bf, void *C, int64_t m, int64_t n, int64_t k, int64_t lda,
                       int64_t ldc, double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
                       hipStream_t s) {
-    hipLaunchKernelGGL((k_stream<T, KC, NT, RT, VEC, IL>), dim3((unsigned)grid), dim3(block), 0, s,
+    hipLaunchKernelGGL((k_stream<T, KC, NT, RT, VEC, CM>), dim3((unsigned)grid), dim3(block), 0, s,
                        static_cast<const T *>(A), static_cast<const T *>(Bf), static_cast<T *>(C),
                        m, (int)n, (int)k, (int)lda, (int)ldc, alpha, beta, nt_total, nsplit);
     return hipGetLastError();
@@ -310,7 +349,7 @@ hipError_t run_stream(const void *A, const void *Bf, void *C, int64_t m, int64_t
 typedef hipError_t (*StreamFn)(const void *, const void *, void *, int64_t, int64_t, int64_t, int64_t, int64_t,
                                double, double, int64_t, int, int, int, hipStream_t);
 struct StreamEntry {
-    int KC, NT, RT, vec, il;
+    int KC, NT, RT, vec, cm;
     StreamFn fn;
 };
 
@@ -320,10 +359,11 @@ struct StreamEntry {
 // RT = 4 (accumulators stay within 128 registers), NT <= 2 for RT = 8.
 // TSMM_SE_* instantiate the plain column order; TSMM_SI, TSMM_SIS (scalar
 // mapping) and TSMM_SEI*_* the interleaved order, where it applies
-// (NT >= VW).
-#define TSMM_SE(T, KC, NT, RT, V) {KC, NT, RT, V, 0, &tsmm::run_stream<T, KC, NT, RT, V, false>},
-#define TSMM_SI(T, KC, NT, RT) {KC, NT, RT, 1, 1, &tsmm::run_stream<T, KC, NT, RT, true, true>},
-#define TSMM_SIS(T, KC, NT, RT) {KC, NT, RT, 0, 1, &tsmm::run_stream<T, KC, NT, RT, false, true>},
+// (NT >= VW); TSMM_SP the binary64 lane pairs (NT = 1).
+#define TSMM_SE(T, KC, NT, RT, V) {KC, NT, RT, V, 0, &tsmm::run_stream<T, KC, NT, RT, V, 0>},
+#define TSMM_SI(T, KC, NT, RT) {KC, NT, RT, 1, 1, &tsmm::run_stream<T, KC, NT, RT, true, 1>},
+#define TSMM_SIS(T, KC, NT, RT) {KC, NT, RT, 0, 1, &tsmm::run_stream<T, KC, NT, RT, false, 1>},
+#define TSMM_SP(KC, RT, V) {KC, 1, RT, V, 2, &tsmm::run_stream<double, KC, 1, RT, V, 2>},
 #define TSMM_SE_RT1(T, KC, V) \
     TSMM_SE(T, KC, 1, 1, V) TSMM_SE(T, KC, 2, 1, V) TSMM_SE(T, KC, 4, 1, V) TSMM_SE(T, KC, 8, 1, V) TSMM_SE(T, KC, 16, 1, V)
 #define TSMM_SE_RT2(T, KC, V) \

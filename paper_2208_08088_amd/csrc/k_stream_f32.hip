@@ -22,9 +22,9 @@ static const StreamEntry kF32[] = {
     TSMM_SEI32_RT2(256)
 };
 
-StreamFn find_stream_f32(int KC, int NT, int RT, bool vec, bool il) {
+StreamFn find_stream_f32(int KC, int NT, int RT, bool vec, int cm) {
     for (const StreamEntry &e : kF32)
-        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec && e.il == (int)il) return e.fn;
+        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec && e.cm == cm) return e.fn;
     return nullptr;
 }
 

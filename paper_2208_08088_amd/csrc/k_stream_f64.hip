@@ -21,11 +21,18 @@ static const StreamEntry kF64[] = {
     // vector mapping with interleaved columns (n even)
     TSMM_SEI64_ALL(8) TSMM_SEI64_ALL(16) TSMM_SI(double, 8, 2, 8) TSMM_SI(double, 16, 2, 8) TSMM_SEI64_ALL(32)
     TSMM_SEI64_ALL(64) TSMM_SEI64_RT1(128) TSMM_SEI64_RT2(128) TSMM_SEI64_RT1(256) TSMM_SEI64_RT2(256)
+    // one column tile, n even: lane pairs (16-byte C vectors)
+    TSMM_SP(4, 1, false) TSMM_SP(8, 1, false) TSMM_SP(16, 1, false) TSMM_SP(32, 1, false) TSMM_SP(64, 1, false)
+    TSMM_SP(128, 1, false) TSMM_SP(256, 1, false) TSMM_SP(4, 2, false) TSMM_SP(4, 4, false)
+    TSMM_SP(8, 1, true) TSMM_SP(8, 2, true) TSMM_SP(8, 4, true) TSMM_SP(8, 8, true)
+    TSMM_SP(16, 1, true) TSMM_SP(16, 2, true) TSMM_SP(16, 4, true) TSMM_SP(16, 8, true)
+    TSMM_SP(32, 1, true) TSMM_SP(32, 2, true) TSMM_SP(32, 4, true) TSMM_SP(64, 1, true) TSMM_SP(64, 2, true)
+    TSMM_SP(64, 4, true) TSMM_SP(128, 1, true) TSMM_SP(128, 2, true) TSMM_SP(256, 1, true) TSMM_SP(256, 2, true)
 };
 
-StreamFn find_stream_f64(int KC, int NT, int RT, bool vec, bool il) {
+StreamFn find_stream_f64(int KC, int NT, int RT, bool vec, int cm) {
     for (const StreamEntry &e : kF64)
-        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec && e.il == (int)il) return e.fn;
+        if (e.KC == KC && e.NT == NT && e.RT == RT && e.vec == (int)vec && e.cm == cm) return e.fn;
     return nullptr;
 }
 

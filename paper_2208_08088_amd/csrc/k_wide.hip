@@ -14,7 +14,9 @@
 // (global_load_lds_dwordx4: lane l's 16 bytes land at base + 16*l, checked
 // on the device), so the copy needs no registers; the next chunk's A and the
 // next slab are in flight while the current chunk's products run.  One
-// workgroup of four wavefronts per compute unit, persistent over row tiles.
+// workgroup per compute unit, persistent over row tiles, of four wavefronts
+// (one per SIMD, RT = 2 or 4) or eight (two per SIMD, RT = 1, 128
+// accumulation registers each).
 //
 // Fragment order (matrix-core lane layout established by an on-device
 // probe): in both 32x32 products lane l = 32*q + j supplies A(row j, ...)
@@ -37,8 +39,6 @@ namespace tsmm {
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
-
-constexpr int kWideWaves = 4;
 
 template <int MODE> struct WideCfg {
     static constexpr int TERMS = MODE == 0 ? 1 : (MODE == 3 ? 2 : 3);
@@ -77,10 +77,11 @@ __device__ __forceinline__ void wide_load_a(const float *__restrict__ A, int64_t
 }
 
 // This wavefront's share of slab c into LDS (LDS-DMA, 16 bytes per lane;
-// the fragment offset is a scalar operand, always inside the image).
-template <int SLAB>
+// the fragment offset is a scalar operand, always inside the image); WV
+// wavefronts share the slab.
+template <int SLAB, int WV>
 __device__ __forceinline__ void wide_dma(__amdgpu_buffer_rsrc_t rw, int c, int wave, int lane, u32x4 *dst) {
-    constexpr int PER = SLAB / kWideWaves;
+    constexpr int PER = SLAB / WV;
     u32x4 *d = dst + wave * PER * 64;
     const int f0 = (c * SLAB + wave * PER) * 1024;
 #pragma unroll
@@ -296,17 +297,17 @@ __device__ __forceinline__ void wide_epilogue(const f16v (&acc)[RT][NT], const i
 
 // MODE: 0 binary32 products, 3 or 6 split-bf16 products.  KC: packed k
 // class (64, 128, 256); NT: 32-column tiles (n / 32); RT: 32-row tiles per
-// wavefront.
-template <int MODE, int KC, int NT, int RT>
-__global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_wide(
+// wavefront; WV: wavefronts per workgroup (4 or 8: one or two per SIMD).
+template <int MODE, int KC, int NT, int RT, int WV>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(WV / 4, WV / 4))) void k_wide(
     const float *__restrict__ A, const u32x4 *__restrict__ W, const int32_t *__restrict__ exps,
     float *__restrict__ C, int64_t m, int n, int k, double alpha, double beta) {
     constexpr int F = WideCfg<MODE>::F;
     constexpr int TERMS = WideCfg<MODE>::TERMS;
     constexpr int NCH = KC / 32;
     constexpr int SLAB = F * NT;
-    constexpr int ROWS = kWideWaves * RT * 32;
-    static_assert(NCH % 2 == 0 && SLAB % kWideWaves == 0 && NT % 4 == 0, "wide kernel shape");
+    constexpr int ROWS = WV * RT * 32;
+    static_assert(NCH % 2 == 0 && SLAB % WV == 0 && NT % 4 == 0 && (WV == 4 || WV == 8), "wide kernel shape");
 
     __shared__ u32x4 sb0[SLAB * 64];
     __shared__ u32x4 sb1[SLAB * 64];
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu
     //   loads may still be in flight: slab g+1 has landed.
     f4v x0[RT][4], x1[RT][4];
     if constexpr (MODE == 0) {
-        wide_dma<SLAB>(rw, 0, wave, lane, sb0);
+        wide_dma<SLAB, WV>(rw, 0, wave, lane, sb0);
         wide_load_a<RT, 0, 4>(A, m, k, tile * ROWS + wrow, 0, j, q, x0);
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
@@ -352,13 +353,13 @@ __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu
             const int64_t next = tile + gridDim.x;
 #pragma unroll
             for (int c = 0; c < NCH; c += 2) {
-                wide_dma<SLAB>(rw, c + 1, wave, lane, sb1);
+                wide_dma<SLAB, WV>(rw, c + 1, wave, lane, sb1);
                 wide_load_a<RT, 0, 4>(A, m, k, tile * ROWS + wrow, c + 1, j, q, x1);
                 wide_chunk_f32<NT, RT>(sb0, x0, acc, lane);
                 __builtin_amdgcn_s_waitcnt(0x0F70);
                 __syncthreads();
                 const bool last = c + 2 >= NCH;
-                wide_dma<SLAB>(rw, last ? 0 : c + 2, wave, lane, sb0);
+                wide_dma<SLAB, WV>(rw, last ? 0 : c + 2, wave, lane, sb0);
                 wide_load_a<RT, 0, 4>(A, m, k, (last ? next : tile) * ROWS + wrow, last ? 0 : c + 2, j, q, x0);
                 wide_chunk_f32<NT, RT>(sb1, x1, acc, lane);
                 __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu
         constexpr int WAIT_END = 0x0F70 | (NA & 15) | ((NA >> 4) << 14);  // vmcnt(NA)
         u32x4 atA[RT][TERMS], atB[RT][TERMS];  // A terms of the chunk's first / second k-step
         u32x4 b[2][2][TERMS];                  // B fragments, one step ahead
-        wide_dma<SLAB>(rw, 0, wave, lane, sb0);
+        wide_dma<SLAB, WV>(rw, 0, wave, lane, sb0);
         wide_load_a<RT, 0, 4>(A, m, k, tile * ROWS + wrow, 0, j, q, x0);
         wide_load_a<RT, 0, 4>(A, m, k, tile * ROWS + wrow, 1, j, q, x1);
         __builtin_amdgcn_s_waitcnt(WAIT_END);
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu
                     const int c1 = cc + 1 < NCH ? cc + 1 : cc + 1 - NCH;
                     const int c2 = cc + 2 < NCH ? cc + 2 : cc + 2 - NCH;
                     const int64_t t2 = cc + 2 < NCH ? tile : next;
-                    wide_dma<SLAB>(rw, c1, wave, lane, nxt);
+                    wide_dma<SLAB, WV>(rw, c1, wave, lane, nxt);
                     wide_load_a<RT, 0, 2>(A, m, k, t2 * ROWS + wrow, c2, j, q, xc);
                     __builtin_amdgcn_sched_barrier(0);
                     f4v s0[RT], s1[RT];
@@ -491,10 +492,10 @@ hipError_t launch_pack_wide(const void *Bf32, const void *planes, void *W, int64
     return hipGetLastError();
 }
 
-template <int MODE, int KC, int NT, int RT>
+template <int MODE, int KC, int NT, int RT, int WV>
 hipError_t run_wide(const float *A, const void *W, const int32_t *exps, float *C, int64_t m, int64_t n, int64_t k,
                     double alpha, double beta, int64_t grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_wide<MODE, KC, NT, RT>), dim3((unsigned)grid), dim3(64 * kWideWaves), 0, s, A,
+    hipLaunchKernelGGL((k_wide<MODE, KC, NT, RT, WV>), dim3((unsigned)grid), dim3(64 * WV), 0, s, A,
                        static_cast<const u32x4 *>(W), exps, C, m, (int)n, (int)k, alpha, beta);
     return hipGetLastError();
 }
@@ -502,32 +503,37 @@ hipError_t run_wide(const float *A, const void *W, const int32_t *exps, float *C
 typedef hipError_t (*WideFn)(const float *, const void *, const int32_t *, float *, int64_t, int64_t, int64_t,
                              double, double, int64_t, hipStream_t);
 struct WideEntry {
-    int mode, KC, NT, RT;
+    int mode, KC, NT, RT, WV;
     WideFn fn;
 };
 
-#define TSMM_WE(M, KC, NT, RT) {M, KC, NT, RT, &run_wide<M, KC, NT, RT>},
-#define TSMM_WE_KC(M, NT, RT) TSMM_WE(M, 64, NT, RT) TSMM_WE(M, 128, NT, RT) TSMM_WE(M, 256, NT, RT)
+#define TSMM_WE(M, KC, NT, RT, WV) {M, KC, NT, RT, WV, &run_wide<M, KC, NT, RT, WV>},
+#define TSMM_WE_KC(M, NT, RT, WV) TSMM_WE(M, 64, NT, RT, WV) TSMM_WE(M, 128, NT, RT, WV) TSMM_WE(M, 256, NT, RT, WV)
 // four 32-row tiles per wavefront only for binary32 products: the split
-// modes' A terms would not fit the registers beside 256 accumulators
-static const WideEntry kWideTable[] = {TSMM_WE_KC(0, 8, 2) TSMM_WE_KC(0, 4, 2) TSMM_WE_KC(0, 4, 4)
-                                       TSMM_WE_KC(3, 8, 2) TSMM_WE_KC(3, 4, 2) TSMM_WE_KC(6, 8, 2)
-                                       TSMM_WE_KC(6, 4, 2)};
+// modes' A terms would not fit the registers beside 256 accumulators.
+// Eight wavefronts (two per SIMD) hold one row tile each.
+static const WideEntry kWideTable[] = {TSMM_WE_KC(0, 8, 2, 4) TSMM_WE_KC(0, 4, 2, 4) TSMM_WE_KC(0, 4, 4, 4)
+                                       TSMM_WE_KC(3, 8, 2, 4) TSMM_WE_KC(3, 4, 2, 4) TSMM_WE_KC(6, 8, 2, 4)
+                                       TSMM_WE_KC(6, 4, 2, 4)
+                                       TSMM_WE_KC(0, 8, 1, 8) TSMM_WE_KC(0, 4, 1, 8) TSMM_WE_KC(3, 8, 1, 8)
+                                       TSMM_WE_KC(3, 4, 1, 8) TSMM_WE_KC(6, 8, 1, 8) TSMM_WE_KC(6, 4, 1, 8)};
 
-static WideFn find_wide(int mode, int KC, int NT, int RT) {
+static WideFn find_wide(int mode, int KC, int NT, int RT, int WV) {
     for (const WideEntry &e : kWideTable)
-        if (e.mode == mode && e.KC == KC && e.NT == NT && e.RT == RT) return e.fn;
+        if (e.mode == mode && e.KC == KC && e.NT == NT && e.RT == RT && e.WV == WV) return e.fn;
     return nullptr;
 }
 
-bool wide_variant_exists(int products, int KC, int NT, int RT) { return find_wide(products, KC, NT, RT) != nullptr; }
+bool wide_variant_exists(int products, int KC, int NT, int RT, int waves) {
+    return find_wide(products, KC, NT, RT, waves) != nullptr;
+}
 
-int64_t wide_rows_per_wg(int RT) { return (int64_t)kWideWaves * RT * 32; }
+int64_t wide_rows_per_wg(int RT, int waves) { return (int64_t)waves * RT * 32; }
 
-hipError_t launch_wide(int products, int KC, int NT, int RT, const void *A, const void *W, const int32_t *exps,
-                       void *C, int64_t m, int64_t n, int64_t k, double alpha, double beta, int64_t grid,
-                       hipStream_t s) {
-    WideFn fn = find_wide(products, KC, NT, RT);
+hipError_t launch_wide(int products, int KC, int NT, int RT, int waves, const void *A, const void *W,
+                       const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k, double alpha, double beta,
+                       int64_t grid, hipStream_t s) {
+    WideFn fn = find_wide(products, KC, NT, RT, waves);
     if (!fn || n != 32 * NT || k > KC || k % 8 != 0 || grid < 1) return hipErrorInvalidValue;
     return fn(static_cast<const float *>(A), W, exps, static_cast<float *>(C), m, n, k, alpha, beta, grid, s);
 }

@@ -545,10 +545,12 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
     if (t.wg_per_cu == 0) t.wg_per_cu = d.wg_per_cu;
     if (t.splitk == 0) t.splitk = d.splitk;
     if (t.nsplit == 0) t.nsplit = d.nsplit;
-    if (t.rows_per_wave < 0 || t.waves_per_wg < 1 || t.waves_per_wg > 4 || !is_pow2(t.waves_per_wg) ||
+    // eight wavefronts only for the wide kernel (two per SIMD)
+    const int max_waves = t.kernel == TSMM_KERNEL_WIDE ? 8 : 4;
+    if (t.rows_per_wave < 0 || t.waves_per_wg < 1 || t.waves_per_wg > max_waves || !is_pow2(t.waves_per_wg) ||
         t.wg_per_cu < 1 || t.wg_per_cu > 32 || t.splitk < 1 || t.splitk > 65536 || t.nsplit < 1 ||
         t.nsplit > 16 || !is_pow2(t.nsplit))
-        return fail(TSMM_ERROR_INVALID_VALUE, "tile out of range (waves_per_wg 1/2/4, wg_per_cu 1..32, "
+        return fail(TSMM_ERROR_INVALID_VALUE, "tile out of range (waves_per_wg 1/2/4 (wide: 4/8), wg_per_cu 1..32, "
                                               "splitk 1..65536, nsplit 1/2/4/8/16)");
     if (t.nsplit > 1 && t.kernel != TSMM_KERNEL_STREAM && t.kernel != TSMM_KERNEL_SPLITBF16 &&
         t.kernel != TSMM_KERNEL_COLMAJOR)
@@ -614,13 +616,14 @@ tsmm_status apply_tile(tsmm_plan_s &p, const tsmm_tile &tile_in) {
         p.KC = wide_kc(p.k);
         p.NT = (int)(p.n / 32);
         p.vec = true;
-        if (!wide_variant_exists(wide_products(p), p.KC, p.NT, t.rows_per_wave))
-            return fail(TSMM_ERROR_NOT_SUPPORTED, "no wide kernel for KC=%d n=%" PRId64 " RT=%d", p.KC, p.n,
-                        t.rows_per_wave);
-        if (t.waves_per_wg != 4 || t.wg_per_cu != 1 || t.nsplit != 1)
+        if ((t.waves_per_wg != 4 && t.waves_per_wg != 8) || t.wg_per_cu != 1 || t.nsplit != 1)
             return fail(TSMM_ERROR_INVALID_VALUE,
-                        "the wide kernel runs one workgroup of 4 wavefronts per compute unit, no column split");
-        const int64_t tiles = (p.m + wide_rows_per_wg(t.rows_per_wave) - 1) / wide_rows_per_wg(t.rows_per_wave);
+                        "the wide kernel runs one workgroup of 4 or 8 wavefronts per compute unit, no column split");
+        if (!wide_variant_exists(wide_products(p), p.KC, p.NT, t.rows_per_wave, t.waves_per_wg))
+            return fail(TSMM_ERROR_NOT_SUPPORTED, "no wide kernel for KC=%d n=%" PRId64 " RT=%d waves=%d", p.KC,
+                        p.n, t.rows_per_wave, t.waves_per_wg);
+        const int64_t rows_wg = wide_rows_per_wg(t.rows_per_wave, t.waves_per_wg);
+        const int64_t tiles = (p.m + rows_wg - 1) / rows_wg;
         p.grid = std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
         break;
     }
@@ -1435,11 +1438,19 @@ tsmm_status execute_core(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_
     }
     p->last_kernel = kernel;
     switch (kernel) {
-    case TSMM_KERNEL_STREAM:
-        e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec,
-                          frag4_pg(p->dtype, p->NT, p->n) > 1, A, base + packed->L.off_frag, C, p->m, p->n, p->k,
-                          lda, ldc, alpha, beta, p->grid, p->block, p->NT, p->tile.nsplit, s);
+    case TSMM_KERNEL_STREAM: {
+        // C in 16-byte vectors: interleaved columns where the fragments
+        // have them, else (binary64, one column tile, n even) lane pairs
+        // when C and ldc allow it, else element by element
+        int cm = frag4_pg(p->dtype, p->NT, p->n) > 1 ? 1 : 0;
+        if (cm == 0 && p->dtype == TSMM_F64 && p->NT == 1 && p->n % 2 == 0 && c16 && ldc % 2 == 0 &&
+            stream_variant_exists(p->dtype, p->KC, 1, p->tile.rows_per_wave, p->vec, 2))
+            cm = 2;
+        e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec, cm, A,
+                          base + packed->L.off_frag, C, p->m, p->n, p->k, lda, ldc, alpha, beta, p->grid, p->block,
+                          p->NT, p->tile.nsplit, s);
         break;
+    }
     case TSMM_KERNEL_VALU64:
         e = launch_valu64(p->tile.rows_per_wave, static_cast<const double *>(A), static_cast<const double *>(Brow),
                           static_cast<double *>(C), p->m, p->n, p->k, alpha, beta, p->grid, s);
@@ -1456,7 +1467,8 @@ tsmm_status execute_core(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_
     case TSMM_KERNEL_WIDE:
         if (!packed->L.wide_KC || packed->L.wide_KC != p->KC)
             return fail(TSMM_ERROR_SHAPE_MISMATCH, "packed operand has no image for the wide kernel");
-        e = launch_wide(wide_products(*p), p->KC, p->NT, p->tile.rows_per_wave, A, base + packed->L.off_wide,
+        e = launch_wide(wide_products(*p), p->KC, p->NT, p->tile.rows_per_wave, p->tile.waves_per_wg, A,
+                        base + packed->L.off_wide,
                         p->mode != TSMM_MODE_NATIVE ? reinterpret_cast<const int32_t *>(base + packed->L.off_exps)
                                                     : nullptr,
                         C, p->m, p->n, p->k, alpha, beta, p->grid, s);
@@ -1567,8 +1579,10 @@ std::vector<tsmm_tile> tune_candidates(const tsmm_plan_s &p) {
     default:
         break;
     }
-    if (wide_ok(p))
+    if (wide_ok(p)) {
         for (int rt : {2, 4}) add(TSMM_KERNEL_WIDE, rt, 1, 1, 1);
+        out.push_back(tsmm_tile{TSMM_KERNEL_WIDE, 1, 8, 1, 1, 1, 0});  // two wavefronts per SIMD
+    }
     return out;
 }
 }  // namespace

@@ -270,11 +270,12 @@ hipError_t launch_unpack_split(const void *planes, const int32_t *exps, void *B_
 size_t wide_image_bytes(int KC, int NT, int terms);
 hipError_t launch_pack_wide(const void *Bf32, const void *planes, void *W, int64_t k, int64_t n, int KC, int NT,
                             int terms, hipStream_t s);
-bool wide_variant_exists(int products, int KC, int NT, int RT);
-int64_t wide_rows_per_wg(int RT);
-hipError_t launch_wide(int products, int KC, int NT, int RT, const void *A, const void *W, const int32_t *exps,
-                       void *C, int64_t m, int64_t n, int64_t k, double alpha, double beta, int64_t grid,
-                       hipStream_t s);
+// waves: wavefronts per workgroup (4 with RT 2 or 4, 8 with RT 1).
+bool wide_variant_exists(int products, int KC, int NT, int RT, int waves);
+int64_t wide_rows_per_wg(int RT, int waves);
+hipError_t launch_wide(int products, int KC, int NT, int RT, int waves, const void *A, const void *W,
+                       const int32_t *exps, void *C, int64_t m, int64_t n, int64_t k, double alpha, double beta,
+                       int64_t grid, hipStream_t s);
 
 // C = beta*C (alpha == 0 or k == 0 paths).
 hipError_t launch_scale(tsmm_dtype out_dt, void *C, int64_t count, double beta, hipStream_t s);
@@ -294,15 +295,17 @@ hipError_t launch_simple_t(tsmm_dtype dt, const void *A, const void *B, void *C,
 // op N streaming, binary64 / binary32 16x16x4 fragments.
 // NT: column tiles per workgroup; nt_total = NT * nsplit column tiles of
 // the packed B.  With nsplit > 1, grid must be a multiple of 8 * nsplit.
-// il: the fragments interleave columns (pg > 1).
+// cm: how C moves: 0 element by element; 1 the fragments interleave
+// columns (pg > 1), 16-byte vectors; 2 lane pairs (binary64, NT = 1, n
+// even), 16-byte vectors.
 // lda, ldc: row strides of A and C in elements (>= k, >= n); vector
-// k-slot mapping needs lda a multiple of the vector width, interleaved
-// columns ldc a multiple of it.
-hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il, const void *A,
+// k-slot mapping needs lda a multiple of the vector width, C vectors (cm 1
+// and 2) a 16-byte aligned C and ldc a multiple of it.
+hipError_t launch_stream(tsmm_dtype dt, int KC, int NT, int RT, bool vec, int cm, const void *A,
                          const void *Bfrag, void *C, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldc,
                          double alpha, double beta, int64_t grid, int block, int nt_total, int nsplit,
                          hipStream_t s);
-bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, bool il);
+bool stream_variant_exists(tsmm_dtype dt, int KC, int NT, int RT, bool vec, int cm);
 
 // op N, split-bf16 (terms 2 or 3 of binary32 A and B; products 3 or 6) or
 // plain bf16 inputs (terms == 1).

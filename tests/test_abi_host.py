@@ -319,6 +319,18 @@ def test_wide_tile_rules(T):
     assert r.get_tile()["rows_per_wave"] == 2
     with pytest.raises(T.TsmmError):
         r.set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=4)
+    # eight wavefronts (two per SIMD) with one 32-row tile each: 256 rows
+    # per workgroup again
+    for mode in ("native", "bf16x3", "bf16x6"):
+        w = T.plan_with_caps(1 << 24, 256, 256, "N", dtype=f32)
+        if mode != "native":
+            w.set_mode(mode)
+        w.set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=1, waves_per_wg=8)
+        assert w.info()["waves"] == "8" and w.info()["block"] == "512" and w.info()["grid"] == "256x1"
+        w = T.plan_with_caps(1000, 128, 64, "N", dtype=f32).set_mode(mode) if mode != "native" else \
+            T.plan_with_caps(1000, 128, 64, "N", dtype=f32)
+        w.set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=1, waves_per_wg=8)
+        assert w.info()["grid"] == "4x1"
     bad = [
         (dict(m=1000, n=192, k=256, dtype=f32), {}),                     # n not 128 / 256
         (dict(m=1000, n=256, k=100, dtype=f32), {}),                     # k % 8 != 0
@@ -327,6 +339,9 @@ def test_wide_tile_rules(T):
         (dict(m=1000, n=256, k=256, dtype=f32), dict(rows_per_wave=4)),  # 512 accumulators
         (dict(m=1000, n=256, k=256, dtype=f32), dict(wg_per_cu=2)),
         (dict(m=1000, n=256, k=256, dtype=f32), dict(nsplit=2)),
+        (dict(m=1000, n=256, k=256, dtype=f32), dict(rows_per_wave=2, waves_per_wg=8)),  # 256 registers
+        (dict(m=1000, n=256, k=256, dtype=f32), dict(rows_per_wave=1, waves_per_wg=4)),  # not built
+        (dict(m=1000, n=256, k=256, dtype=f32), dict(waves_per_wg=2)),
     ]
     for shape, extra in bad:
         with pytest.raises(T.TsmmError):

@@ -184,6 +184,66 @@ def test_closed_forms(dtype):
     assert np.array_equal(C, exp)
 
 
+def offset_rows(x, off, ld):
+    """x (r x c) binary64 as a row-major view with row stride ld whose first
+    element lies off elements into its buffer (off 1: 8-byte aligned only);
+    the padding holds 777."""
+    r, c = x.shape
+    buf = torch.full((off + r * ld,), 777.0, dtype=torch.float64, device="cuda")
+    v = buf[off:].view(r, ld)
+    v[:, :c] = dev(x, torch.float64)
+    return buf, v[:, :c]
+
+
+@pytest.mark.parametrize("m,k,n", [(1000, 8, 8), (777, 8, 2), (515, 16, 16), (300, 5, 6), (2049, 32, 14),
+                                   (129, 128, 10), (33, 256, 4), (999, 4, 12), (17, 64, 16)])
+def test_lane_pair_c_vectors(m, k, n):
+    # binary64 with one column tile and n even: lanes j and j ^ 1 swap half
+    # of their accumulators and C moves in 16-byte vectors when C is
+    # 16-byte aligned with an even stride; otherwise element by element.
+    # Both give the oracle's small-integer results exactly, the same bits on
+    # uniform data, and leave the padding of C alone.
+    seed = 4100 + m + k + n
+    for data in ("ints", "uniform"):
+        if data == "ints":
+            A = I.host_ints((m, k), seed, 1, -4, 4, dtype=np.float64)
+            B = I.host_ints((k, n), seed, 2, -4, 4, dtype=np.float64)
+            C0 = I.host_ints((m, n), seed, 3, -4, 4, dtype=np.float64)
+        else:
+            A = I.host_uniform((m, k), seed, 4)
+            B = I.host_uniform((k, n), seed, 5)
+            C0 = I.host_uniform((m, n), seed, 6)
+        pk = T.pack(dev(B, torch.float64))
+        want = oracle.gemm_n(A, B, C0, 1.5, 0.5)
+        outs = []
+        for rt in (0, 1, 2, 4, 8):
+            for off, pad in ((0, 0), (0, 2), (1, 0), (0, 1), (2, 4)):
+                try:
+                    p = T.plan(m, n, k, "N", torch.float64).set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=rt)
+                except T.TsmmError as e:
+                    assert e.status == T.NOT_SUPPORTED and rt > 1, e  # no instantiation
+                    break
+                buf, Cv = offset_rows(C0, off, n + pad)
+                announce("lane pairs", m, n, k, data, "rt", rt, "offset", off, "pad", pad)
+                T.execute(p, dev(A, torch.float64), pk, Cv, 1.5, 0.5)
+                assert p.info()["ran"] == "stream", p.describe()
+                C = host(Cv)
+                if data == "ints":
+                    assert np.array_equal(C, want), (rt, off, pad)
+                else:
+                    assert_normwise(C, want, 1e-12, p.describe())
+                outs.append(C)
+                full = buf[off:].view(m, n + pad)
+                assert bool((full[:, n:] == 777.0).all()) and (off == 0 or float(buf[0]) == 777.0)
+        assert all(np.array_equal(o, outs[0]) for o in outs)
+    # beta = 0 reads no C (NaN in C stays out)
+    A = I.host_uniform((m, k), seed, 7)
+    p = T.plan(m, n, k, "N", torch.float64)
+    Cd = torch.full((m, n), float("nan"), dtype=torch.float64, device="cuda")
+    T.execute(p, dev(A, torch.float64), pk, Cd, -0.75, 0.0)
+    assert_normwise(host(Cd), oracle.gemm_n(A, B, None, -0.75, 0.0), 1e-12)
+
+
 def test_misaligned_A_still_correct():
     m, k, n = 500, 32, 32
     A = I.host_uniform((m, k), 8, 1)

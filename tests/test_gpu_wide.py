@@ -2,9 +2,10 @@
 k <= 256): binary32 products and the two- / three-term bfloat16 splits,
 each against the FP64 oracle on the same (widened) inputs.  Shapes cover
 ragged row counts (partial 32-row tiles and partial workgroup tiles), k
-below the packed class (zero-padded chunks), both row-tile depths, beta 0
-and beta != 0, and exactly representable cases that must match bit for
-bit."""
+below the packed class (zero-padded chunks), every row-tile depth (one
+tile per wavefront runs eight wavefronts per workgroup, two per SIMD),
+beta 0 and beta != 0, and exactly representable cases that must match bit
+for bit."""
 import numpy as np
 import pytest
 import torch
@@ -31,7 +32,8 @@ def run_wide(A, B, C0, alpha, beta, mode, rt=0):
     p = T.plan(m, n, k, "N", torch.float32)
     if mode != "native":
         p.set_mode(mode)
-    p.set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=rt)
+    # one 32-row tile per wavefront: eight wavefronts per workgroup
+    p.set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=rt, waves_per_wg=8 if rt == 1 else 0)
     assert p.info()["kernel"] == "wide"
     pk = T.pack(dev(B, torch.float32), "N", mode)
     C = dev(C0, torch.float32) if C0 is not None else torch.full((m, n), np.nan, dtype=torch.float32, device="cuda")
@@ -40,7 +42,9 @@ def run_wide(A, B, C0, alpha, beta, mode, rt=0):
 
 
 SHAPES = [(4096, 256, 256, 0), (1000, 256, 256, 0), (70001, 128, 128, 4), (70001, 128, 128, 2),
-          (777, 64, 128, 0), (300, 200, 256, 0), (129, 8, 128, 0), (33, 96, 256, 0), (5000, 136, 128, 4)]
+          (777, 64, 128, 0), (300, 200, 256, 0), (129, 8, 128, 0), (33, 96, 256, 0), (5000, 136, 128, 4),
+          (4096, 256, 256, 1), (1000, 256, 256, 1), (70001, 128, 128, 1), (777, 64, 128, 1), (33, 96, 256, 1),
+          (5000, 136, 128, 1), (300, 200, 256, 1)]
 
 
 @pytest.mark.parametrize("mode", ["native", "bf16x6", "bf16x3"])
@@ -112,24 +116,27 @@ def test_wide_bf16x3_identity_keeps_16_bits():
 
 @pytest.mark.parametrize("mode", ["native", "bf16x6"])
 def test_wide_matches_other_kernel(mode):
-    # the wide kernel and the natural family agree to the tolerance, and the
-    # wide kernel is bitwise repeatable
+    # the wide kernel and the natural family agree to the tolerance; the
+    # wide kernel is bitwise repeatable and gives the same bits with four or
+    # eight wavefronts per workgroup
     m, k, n = 4000, 256, 256
     A = dev(I.col_scaled_uniform(m, k, 750, 1), torch.float32)
     B = dev(I.host_uniform((k, n), 750, 2, dtype=np.float32), torch.float32)
     pk = T.pack(B, "N", mode)
     outs = []
-    for kern in (T.KERNEL_WIDE, T.KERNEL_WIDE, T.KERNEL_STREAM if mode == "native" else T.KERNEL_SPLITBF16):
+    for kern, rt, waves in ((T.KERNEL_WIDE, 0, 0), (T.KERNEL_WIDE, 0, 0), (T.KERNEL_WIDE, 1, 8),
+                            (T.KERNEL_STREAM if mode == "native" else T.KERNEL_SPLITBF16, 0, 0)):
         p = T.plan(m, n, k, "N", torch.float32)
         if mode != "native":
             p.set_mode(mode)
-        p.set_tile(kernel=kern)
-        announce("wide vs", kern)
+        p.set_tile(kernel=kern, rows_per_wave=rt, waves_per_wg=waves)
+        announce("wide vs", kern, rt, waves)
         C = torch.empty((m, n), dtype=torch.float32, device="cuda")
         T.execute(p, A, pk, C, 1.0, 0.0)
         outs.append(host(C))
     assert np.array_equal(outs[0], outs[1])
-    assert oracle.normwise_rel_err(outs[0], outs[2]) <= 2 * TOL[mode]
+    assert np.array_equal(outs[0], outs[2])
+    assert oracle.normwise_rel_err(outs[0], outs[3]) <= 2 * TOL[mode]
 
 
 def test_wide_unaligned_operands():
