@@ -111,8 +111,9 @@ template <> struct BufIO<double> {
     static __device__ __forceinline__ void store1(double v, __amdgpu_buffer_rsrc_t r, int voff) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, 0, AUX);
     }
+    template <int AUX = 2>
     static __device__ __forceinline__ void store_vec(d2v v, __amdgpu_buffer_rsrc_t r, int voff) {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, 0, 2);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, 0, AUX);
     }
 };
 template <> struct BufIO<float> {
@@ -128,8 +129,9 @@ template <> struct BufIO<float> {
     static __device__ __forceinline__ void store1(float v, __amdgpu_buffer_rsrc_t r, int voff) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0, AUX);
     }
+    template <int AUX = 2>
     static __device__ __forceinline__ void store_vec(f4v v, __amdgpu_buffer_rsrc_t r, int voff) {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, 0, 2);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, 0, AUX);
     }
 };
 

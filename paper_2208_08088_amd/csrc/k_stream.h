@@ -108,11 +108,15 @@ __device__ __forceinline__ double lane_pair_swap(double x) {
     return __builtin_bit_cast(double, r);
 }
 
-// How C moves (CM): 0 element by element; 1 interleaved columns (the
+// How C moves (CM & 3): 0 element by element; 1 interleaved columns (the
 // fragments of PG adjacent columns in one lane, 16-byte vectors); 2 lane
 // pairs (binary64, one column tile, n even): lanes j and j ^ 1 swap half of
 // their accumulators so that each holds two adjacent columns of a row and C
 // moves in 16-byte vectors with the plain column order of the packed B.
+// CM & 4: the 16-byte C stores take the default cache policy instead of the
+// streaming one (chosen at launch for beta == 0 on the memory-bound binary64
+// classes: there it was measured 5-6% faster, and 2-3% slower at beta != 0,
+// where C is also read).
 template <typename T, int KC, int NT, int RT, bool VEC, int CM, bool CPRE = true>
 __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__restrict__ Bsrc, int bstride,
                                             T *__restrict__ C, int64_t m, int n, int k, int lda, int ldc,
@@ -138,10 +142,11 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
     // column colp(tt) of the column group, a lane holds PG adjacent columns
     // of each row in the tiles of one group, and C moves in 16-byte vectors
     // (n is then a multiple of PG); otherwise element by element.
-    constexpr int PG = CM == 1 ? Mfma4<T>::VW : 1;
-    static_assert(CM != 1 || NT % PG == 0, "interleave groups must be whole");
-    constexpr bool cvec = CM == 1;
-    constexpr bool PAIR = CM == 2;
+    constexpr int PG = (CM & 3) == 1 ? Mfma4<T>::VW : 1;
+    static_assert((CM & 3) != 1 || NT % PG == 0, "interleave groups must be whole");
+    constexpr bool cvec = (CM & 3) == 1;
+    constexpr bool PAIR = (CM & 3) == 2;
+    constexpr int SAUX = (CM & 4) ? 0 : 2;  // cache policy of the 16-byte C stores
     static_assert(!PAIR || (sizeof(T) == 8 && NT == 1 && CPRE), "lane pairs: binary64, one column tile");
     auto colp = [=](int tt) { return 16 * PG * (tt / PG) + PG * j + tt % PG; };
     // byte offset of accumulator element (tt, r): row M::row(q, r), column
@@ -232,7 +237,7 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
                 typename M::vec v;
                 v[0] = (T)epilogue(alpha, (double)c0, beta, (double)cp[rt][p][0]);
                 v[1] = (T)epilogue(alpha, (double)c1, beta, (double)cp[rt][p][1]);
-                BufIO<T>::store_vec(v, rc[rt], poff(p));
+                BufIO<T>::template store_vec<SAUX>(v, rc[rt], poff(p));
             }
         } else if constexpr (cvec) {
 #pragma unroll
@@ -249,7 +254,7 @@ __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__
 #pragma unroll
                     for (int i = 0; i < PG; ++i)
                         v[i] = (T)epilogue(alpha, (double)acc[rt][PG * g + i][r], beta, (double)cv[rt][PG * g + i][r]);
-                    BufIO<T>::store_vec(v, rc[rt], voff(g, r));
+                    BufIO<T>::template store_vec<SAUX>(v, rc[rt], voff(g, r));
                 }
         } else {
             // the column tiles of one row quad back to back: the parts of a
@@ -359,11 +364,15 @@ struct StreamEntry {
 // RT = 4 (accumulators stay within 128 registers), NT <= 2 for RT = 8.
 // TSMM_SE_* instantiate the plain column order; TSMM_SI, TSMM_SIS (scalar
 // mapping) and TSMM_SEI*_* the interleaved order, where it applies
-// (NT >= VW); TSMM_SP the binary64 lane pairs (NT = 1).
+// (NT >= VW); TSMM_SP the binary64 lane pairs (NT = 1); TSMM_SID and
+// TSMM_SPD the binary64 vector modes with default-policy C stores.
 #define TSMM_SE(T, KC, NT, RT, V) {KC, NT, RT, V, 0, &tsmm::run_stream<T, KC, NT, RT, V, 0>},
 #define TSMM_SI(T, KC, NT, RT) {KC, NT, RT, 1, 1, &tsmm::run_stream<T, KC, NT, RT, true, 1>},
 #define TSMM_SIS(T, KC, NT, RT) {KC, NT, RT, 0, 1, &tsmm::run_stream<T, KC, NT, RT, false, 1>},
 #define TSMM_SP(KC, RT, V) {KC, 1, RT, V, 2, &tsmm::run_stream<double, KC, 1, RT, V, 2>},
+// the same two C modes with default-policy C stores (beta == 0)
+#define TSMM_SID(KC, NT, RT) {KC, NT, RT, 1, 5, &tsmm::run_stream<double, KC, NT, RT, true, 5>},
+#define TSMM_SPD(KC, RT) {KC, 1, RT, 1, 6, &tsmm::run_stream<double, KC, 1, RT, true, 6>},
 #define TSMM_SE_RT1(T, KC, V) \
     TSMM_SE(T, KC, 1, 1, V) TSMM_SE(T, KC, 2, 1, V) TSMM_SE(T, KC, 4, 1, V) TSMM_SE(T, KC, 8, 1, V) TSMM_SE(T, KC, 16, 1, V)
 #define TSMM_SE_RT2(T, KC, V) \

@@ -28,6 +28,17 @@ static const StreamEntry kF64[] = {
     TSMM_SP(16, 1, true) TSMM_SP(16, 2, true) TSMM_SP(16, 4, true) TSMM_SP(16, 8, true)
     TSMM_SP(32, 1, true) TSMM_SP(32, 2, true) TSMM_SP(32, 4, true) TSMM_SP(64, 1, true) TSMM_SP(64, 2, true)
     TSMM_SP(64, 4, true) TSMM_SP(128, 1, true) TSMM_SP(128, 2, true) TSMM_SP(256, 1, true) TSMM_SP(256, 2, true)
+    // default-policy C stores for beta == 0 (vector mapping, k classes up to 64)
+    TSMM_SPD(8, 1) TSMM_SPD(8, 2) TSMM_SPD(8, 4) TSMM_SPD(8, 8) TSMM_SPD(16, 1) TSMM_SPD(16, 2) TSMM_SPD(16, 4)
+    TSMM_SPD(16, 8) TSMM_SPD(32, 1) TSMM_SPD(32, 2) TSMM_SPD(32, 4) TSMM_SPD(64, 1) TSMM_SPD(64, 2) TSMM_SPD(64, 4)
+    TSMM_SID(8, 2, 1) TSMM_SID(8, 4, 1) TSMM_SID(8, 8, 1) TSMM_SID(8, 16, 1) TSMM_SID(8, 2, 2) TSMM_SID(8, 4, 2)
+    TSMM_SID(8, 8, 2) TSMM_SID(8, 2, 4) TSMM_SID(8, 4, 4) TSMM_SID(8, 2, 8)
+    TSMM_SID(16, 2, 1) TSMM_SID(16, 4, 1) TSMM_SID(16, 8, 1) TSMM_SID(16, 16, 1) TSMM_SID(16, 2, 2)
+    TSMM_SID(16, 4, 2) TSMM_SID(16, 8, 2) TSMM_SID(16, 2, 4) TSMM_SID(16, 4, 4) TSMM_SID(16, 2, 8)
+    TSMM_SID(32, 2, 1) TSMM_SID(32, 4, 1) TSMM_SID(32, 8, 1) TSMM_SID(32, 16, 1) TSMM_SID(32, 2, 2)
+    TSMM_SID(32, 4, 2) TSMM_SID(32, 8, 2) TSMM_SID(32, 2, 4) TSMM_SID(32, 4, 4)
+    TSMM_SID(64, 2, 1) TSMM_SID(64, 4, 1) TSMM_SID(64, 8, 1) TSMM_SID(64, 16, 1) TSMM_SID(64, 2, 2)
+    TSMM_SID(64, 4, 2) TSMM_SID(64, 8, 2) TSMM_SID(64, 2, 4) TSMM_SID(64, 4, 4)
 };
 
 StreamFn find_stream_f64(int KC, int NT, int RT, bool vec, int cm) {

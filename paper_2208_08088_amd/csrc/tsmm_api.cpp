@@ -1446,6 +1446,11 @@ tsmm_status execute_core(tsmm_plan_t p, const void *A, int64_t lda, tsmm_packed_
         if (cm == 0 && p->dtype == TSMM_F64 && p->NT == 1 && p->n % 2 == 0 && c16 && ldc % 2 == 0 &&
             stream_variant_exists(p->dtype, p->KC, 1, p->tile.rows_per_wave, p->vec, 2))
             cm = 2;
+        // beta == 0 on the memory-bound binary64 classes: default-policy C
+        // stores (measured faster there; streaming stores where C is read)
+        if (cm != 0 && beta == 0.0 && p->dtype == TSMM_F64 && p->KC <= 64 &&
+            stream_variant_exists(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec, cm | 4))
+            cm |= 4;
         e = launch_stream(p->dtype, p->KC, p->NT / p->tile.nsplit, p->tile.rows_per_wave, p->vec, cm, A,
                           base + packed->L.off_frag, C, p->m, p->n, p->k, lda, ldc, alpha, beta, p->grid, p->block,
                           p->NT, p->tile.nsplit, s);

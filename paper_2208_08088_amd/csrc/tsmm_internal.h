@@ -297,7 +297,8 @@ hipError_t launch_simple_t(tsmm_dtype dt, const void *A, const void *B, void *C,
 // the packed B.  With nsplit > 1, grid must be a multiple of 8 * nsplit.
 // cm: how C moves: 0 element by element; 1 the fragments interleave
 // columns (pg > 1), 16-byte vectors; 2 lane pairs (binary64, NT = 1, n
-// even), 16-byte vectors.
+// even), 16-byte vectors; 5, 6: modes 1, 2 with default-policy C stores
+// (binary64, beta == 0).
 // lda, ldc: row strides of A and C in elements (>= k, >= n); vector
 // k-slot mapping needs lda a multiple of the vector width, C vectors (cm 1
 // and 2) a 16-byte aligned C and ldc a multiple of it.

@@ -244,6 +244,36 @@ def test_lane_pair_c_vectors(m, k, n):
     assert_normwise(host(Cd), oracle.gemm_n(A, B, None, -0.75, 0.0), 1e-12)
 
 
+@pytest.mark.parametrize("m,k,n", [(2049, 8, 8), (1000, 16, 16), (777, 32, 32), (515, 64, 64), (300, 8, 2),
+                                   (129, 32, 64), (1000, 16, 34), (33, 64, 16)])
+def test_beta0_store_variants(m, k, n):
+    # beta = 0 on the memory-bound binary64 classes runs kernel variants of
+    # their own (default-policy C stores): small-integer results exact for
+    # every tile, NaN in C never read, and the same values as beta = 1 on a
+    # zero C (the streaming-store variants)
+    seed = 4200 + m + k + n
+    A = I.host_ints((m, k), seed, 1, -4, 4, dtype=np.float64)
+    B = I.host_ints((k, n), seed, 2, -4, 4, dtype=np.float64)
+    want = oracle.gemm_n(A, B, None, 1.5, 0.0)
+    pk = T.pack(dev(B, torch.float64))
+    Ad = dev(A, torch.float64)
+    for rt in (0, 1, 2, 4, 8):
+        for wpc in (1, 8):
+            try:
+                p = T.plan(m, n, k, "N", torch.float64).set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=rt,
+                                                                  wg_per_cu=wpc)
+            except T.TsmmError as e:
+                assert e.status == T.NOT_SUPPORTED and rt > 1, e
+                continue
+            announce("beta 0 stores", m, n, k, "rt", rt, "wpc", wpc)
+            C = torch.full((m, n), float("nan"), dtype=torch.float64, device="cuda")
+            T.execute(p, Ad, pk, C, 1.5, 0.0)
+            assert np.array_equal(host(C), want), (rt, wpc, p.describe())
+            C1 = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+            T.execute(p, Ad, pk, C1, 1.5, 1.0)
+            assert np.array_equal(host(C1), want), (rt, wpc)
+
+
 def test_misaligned_A_still_correct():
     m, k, n = 500, 32, 32
     A = I.host_uniform((m, k), 8, 1)
