@@ -93,11 +93,6 @@ __device__ __forceinline__ void stream_load_a(const T *__restrict__ A, int64_t m
     }
 }
 
-// One row step of the streaming kernel: tiles t .. t+RT-1 are multiplied
-// with the A rows already in a_use while the rows of tiles tnext.. stream
-// into a_load.  C rows are read through a resource that is empty when
-// beta == 0 (no traffic, no branch), before the prefetch is issued, so the
-// epilogue's wait for them does not include the prefetch.
 // The neighbouring lane's value (lane ^ 1): DPP quad permutation [1, 0, 3, 2]
 // on both halves of a binary64 value.
 __device__ __forceinline__ double lane_pair_swap(double x) {
@@ -108,6 +103,11 @@ __device__ __forceinline__ double lane_pair_swap(double x) {
     return __builtin_bit_cast(double, r);
 }
 
+// One row step of the streaming kernel: tiles t .. t+RT-1 are multiplied
+// with the A rows already in a_use while the rows of tiles tnext.. stream
+// into a_load.  C rows are read through a resource that is empty when
+// beta == 0 (no traffic, no branch), before the prefetch is issued, so the
+// epilogue's wait for them does not include the prefetch.
 // How C moves (CM & 3): 0 element by element; 1 interleaved columns (the
 // fragments of PG adjacent columns in one lane, 16-byte vectors); 2 lane
 // pairs (binary64, one column tile, n even): lanes j and j ^ 1 swap half of
@@ -115,8 +115,8 @@ __device__ __forceinline__ double lane_pair_swap(double x) {
 // moves in 16-byte vectors with the plain column order of the packed B.
 // CM & 4: the 16-byte C stores take the default cache policy instead of the
 // streaming one (chosen at launch for beta == 0 on the memory-bound binary64
-// classes: there it was measured 5-6% faster, and 2-3% slower at beta != 0,
-// where C is also read).
+// classes: there it was measured 2-13% faster, and 2-3% slower at
+// beta != 0, where C is also read).
 template <typename T, int KC, int NT, int RT, bool VEC, int CM, bool CPRE = true>
 __device__ __forceinline__ void stream_step(const T *__restrict__ A, const T *__restrict__ Bsrc, int bstride,
                                             T *__restrict__ C, int64_t m, int n, int k, int lda, int ldc,
