@@ -34,8 +34,11 @@ binary32 precision comparison (m = 2^24, k = n = 256: binary32 products,
 split-bf16 x3 / x6, binary64 on binary64 copies), the batched persistent
 launch (512 uneven instances, replayed from a HIP graph), the paper's own
 shape (square A 25600 x 25600 times B 25600 x N, N in {16, 64, 240}), the
-runtime evaluator on a shape class the tile table does not hold, and the
-headline sizes with column-major operands.
+runtime evaluator on a shape class the tile table does not hold, the
+headline sizes with column-major operands, the reused packed A, and the
+roofline kernel with all-zero A or B operands beside uniform ones (same
+instructions and bytes; the difference is the operands' switching
+activity, which the part's power limit turns into clock).
 
 The `roofline` object is for the kernel that takes the most time in a step,
 timed with HIP events on the stream it runs on; `cpu_baseline` times the
@@ -642,6 +645,39 @@ def loop_ms(torch, T, plans, As, packs, Cs, steps, warmup):
     return float(np.median(timer.per_key_ms()["loop"]))
 
 
+def extras_operand_activity(torch, T, I, steps, warmup):
+    """The roofline kernel (binary64, m = 2^23, k = n = 128, beta 0, the
+    table tile) on the same launch with uniform operands and with A or B
+    all zeros: the instructions and the bytes moved are the same, only the
+    switching activity of the operands changes.  A shorter time with zeros
+    shows that the part's power limit, through its clock, bounds the kernel
+    on real data."""
+    m, k = M_ROWS, 128
+    p = T.plan(m, k, k, "N", torch.float64)
+    Br = I.device_uniform((k, k), I.BASE_SEED, 61, torch.float64)
+    pk = {"uniform": T.pack(Br), "zero_B": T.pack(torch.zeros_like(Br))}
+    pk["zero_A"] = pk["uniform"]
+    Au = [I.device_uniform((m, k), I.BASE_SEED, 62 + r, torch.float64) for r in range(2)]
+    Az = [torch.zeros((m, k), dtype=torch.float64, device="cuda") for _ in range(2)]
+    C = torch.empty((m, k), dtype=torch.float64, device="cuda")
+    timer = Timer(torch)
+    for it in range(warmup + steps):
+        for name in ("uniform", "zero_A", "zero_B"):
+            A = (Az if name == "zero_A" else Au)[it % 2]
+            e0 = timer.start()
+            T.execute(p, A, pk[name], C, 1.0, 0.0)
+            if it >= warmup:
+                timer.stop(name, e0)
+    per = {name: float(np.median(v)) * 1e3 for name, v in timer.per_key_ms().items()}
+    out = dict(shape="f64 m=2^23 k=n=128, beta 0", plan=p.describe(),
+               us={name: per[name] for name in ("uniform", "zero_A", "zero_B")})
+    out["zero_A_speedup"] = per["uniform"] / per["zero_A"]
+    out["zero_B_speedup"] = per["uniform"] / per["zero_B"]
+    del Au, Az, C
+    torch.cuda.empty_cache()
+    return out
+
+
 def extras_batched(torch, T, I, steps, warmup):
     """The 512-instance batched launch (graph replay), binary32 and bfloat16
     inputs; beside it, the same instances as 512 single executes in plain
@@ -878,10 +914,12 @@ def main():
         log("column-major done")
         pka = extras_packed_a(torch, T, I, args.steps, args.warmup)
         log("packed A done")
+        act = extras_operand_activity(torch, T, I, max(3, args.steps // 4), 1)
+        log("operand activity done")
         del keep_t
         result["extras"] = dict(small_4096x16=small, op_t_splitk=opt, precision_m2p24_k256=prec,
                                 batched_512=bat, square_25600=sq, runtime_evaluator=tune,
-                                colmajor_m2p23=colm, packed_a_reuse=pka)
+                                colmajor_m2p23=colm, packed_a_reuse=pka, operand_activity_k128=act)
 
     if not args.no_cpu_baseline and not args.only:
         result["cpu_baseline"] = cpu_baseline(torch, I, cases, keep_s)
