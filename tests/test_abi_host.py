@@ -164,6 +164,9 @@ def test_set_tile_validation(T):
     with pytest.raises(T.TsmmError) as e:
         p.set_tile(kernel=T.KERNEL_STREAM, waves_per_wg=3)
     assert e.value.status == T.INVALID_VALUE
+    with pytest.raises(T.TsmmError) as e:
+        p.set_tile(kernel=T.KERNEL_STREAM, waves_per_wg=8)  # eight only for the wide kernels
+    assert e.value.status == T.INVALID_VALUE
     with pytest.raises(T.TsmmError):
         p.set_tile(kernel=T.KERNEL_STREAM, rows_per_wave=16)  # no such instantiation
     p.set_tile(kernel=T.KERNEL_SIMPLE)
