@@ -75,6 +75,30 @@ def test_packed_split_is_bitwise_the_fresh_split(mode, m, k, n):
 
 
 @pytest.mark.parametrize("mode", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("m,k,n", [(2050, 200, 256), (3000, 256, 256), (777, 64, 128)])
+def test_packed_a_through_the_eight_wavefront_wide_tile(mode, m, k, n):
+    # a plan on the wide kernel with eight wavefronts per workgroup (one row
+    # tile each) runs the packed call on RN32(alpha*A) with that tile: the
+    # same bits as the fresh call of the same plan
+    seed = 7100 + m + k + n
+    A = I.host_uniform((m, k), seed, 1, dtype=np.float32)
+    B = I.host_uniform((k, n), seed, 2, dtype=np.float32)
+    C0 = I.host_uniform((m, n), seed, 3, dtype=np.float32)
+    pk = T.pack(dev(B, torch.float32), "N", mode)
+    Ad = dev(A, torch.float32)
+    p = split_plan(m, n, k, mode).set_tile(kernel=T.KERNEL_WIDE, rows_per_wave=1, waves_per_wg=8)
+    for alpha in (1.0, 0.5):
+        announce("packed A eight-wavefront wide", mode, m, k, n, "alpha", alpha)
+        Cf = dev(C0, torch.float32)
+        T.execute(p, Ad, pk, Cf, alpha, 0.5)
+        Cp = dev(C0, torch.float32)
+        T.execute_packed_a(p, T.pack_a(Ad, mode, alpha), pk, Cp, 0.5)
+        assert p.info()["ran"] == "wide" and p.info()["waves"] == "8", p.describe()
+        assert torch.equal(Cp, Cf), (mode, alpha)
+        assert_normwise(host(Cp), oracle.gemm_n(A, B, C0, alpha, 0.5), TOL[mode], mode)
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "bf16x6"])
 @pytest.mark.parametrize("m,k", [(1000, 37), (70, 64), (129, 256)])
 def test_pre_split_terms_through_identity(mode, m, k):
     # B = I: each output is the sum of the terms of one packed element,
